@@ -1,0 +1,798 @@
+/*
+ * numa_oracle.c -- plain, slow, FP64 CPU oracle for the NUMA spectral-element
+ * right-hand side, direct stiffness summation and SSP-RK3 step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this library.  The product path
+ * (the HIP library) shares no code, header, table or helper with it.
+ *
+ * Every routine follows the paper (Mueller et al., "Strong scaling for
+ * numerical weather prediction at petascale with the atmospheric model NUMA",
+ * IJHPCA 2016) section by section:
+ *   - Lagrange basis on Lobatto points:        Sec. "Spatial Discretization", Eq. (expansion)
+ *   - strong form with diagonal mass matrix:   Eq. (discstrongform)
+ *   - derivative contractions + chain rule:    Eq. (derivatives) (garbled index/metric
+ *                                              read as the standard chain rule)
+ *   - DSS weighted by element volume, M^-1:    text after Eq. (derivatives); Code example 1
+ *   - explicit RK stage update ("update q"):   Sec. "Time Discretization"; Code example 1
+ * Readings where the paper is silent (variable set, EOS form, reference
+ * atmosphere, no-flux projection, SSP-RK3, mesh numbering) are listed in the
+ * design notes of the repository; each is restated at the routine using it.
+ *
+ * Loops are plain and in the paper's order.  Build: gcc -O2 -ffp-contract=off
+ * (no FMA contraction), optional -fopenmp (parallel over elements or over
+ * unique nodes only; results do not depend on the thread count).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_MAXP 9 /* N <= 8 */
+
+typedef struct {
+    int32_t kind;        /* 0 = box, 1 = cubed-sphere shell */
+    int32_t N;           /* polynomial order p of the paper */
+    int32_t ne[3];       /* box: nx, ny, nz; shell: ne (per cube edge), unused, nz */
+    int32_t periodic[3]; /* box only: x and y must be periodic; z either */
+    double extent[3];    /* box: Lx, Ly, H; shell: a (radius), unused, H */
+    double h0;           /* box terrain amplitude */
+} or_mesh_desc;
+
+typedef struct {
+    double R, cp, g0, p0;
+    double T0; /* box: theta0 of the isentropic reference; shell: isothermal T */
+} or_phys;
+
+typedef struct {
+    int32_t kind;     /* 0 rest, 1 cosine bubble (box), 2 zonal jet + gaussian blob (shell) */
+    double amp;       /* bubble / blob amplitude [K] */
+    double radius;    /* bubble radius [m]; blob horizontal e-folding length [m] */
+    double c[3];      /* bubble centre x,y,z [m]; blob lon, lat [rad], height [m] */
+    double lz;        /* blob vertical e-folding length [m] */
+    double jet_u0;    /* jet speed [m/s] */
+    double noise_amp; /* scale applied to the standard-normal noise on u, v, w */
+} or_ic_desc;
+
+typedef struct {
+    or_mesh_desc m;
+    or_phys ph;
+    int N, P, np;
+    int64_t ne, nl, nu, nh, nk;
+    double xi[OR_MAXP], w[OR_MAXP], D[OR_MAXP * OR_MAXP];
+    int32_t *G;      /* [ne][np] gather map: element-local -> unique */
+    double *xl;      /* [3][nl] element-local coordinates */
+    double *xu;      /* [3][nu] unique-node coordinates */
+    double *met;     /* [10][nl] xi_x xi_y xi_z eta_x eta_y eta_z zeta_x zeta_y zeta_z J*w */
+    double *M;       /* [nu] diagonal mass matrix */
+    double *ref;     /* [3][nu] rho_bar, theta_bar, p_bar */
+    double *grav;    /* [3][nu] gravity vector */
+    double *nrm;     /* [3][nu] outward unit normal at no-flux nodes, 0 elsewhere */
+    int32_t *isbnd;  /* [nu] 1 at no-flux boundary nodes */
+    int64_t *off;    /* [nu+1] inverse map offsets */
+    int64_t *cp;     /* [nl] copies of each unique node, ascending e*np+l */
+    int dtheta;      /* theta_bar varies in space (shell): its gradient enters R_theta */
+} or_ctx;
+
+static const double OR_PI = 3.14159265358979323846;
+
+/* ------------------------------------------------------------------------ */
+/* Legendre polynomial P_n(x) and derivative by the three-term recurrence.   */
+static void legendre(int n, double x, double *Pn, double *dPn, double *Pn1)
+{
+    double p0 = 1.0, p1 = x, d0 = 0.0, d1 = 1.0;
+    if (n == 0) { *Pn = 1.0; *dPn = 0.0; *Pn1 = 0.0; return; }
+    for (int k = 1; k < n; k++) {
+        double p2 = ((2.0 * k + 1.0) * x * p1 - k * p0) / (k + 1.0);
+        double d2 = d0 + (2.0 * k + 1.0) * p1;
+        p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+    }
+    *Pn = p1; *dPn = d1; *Pn1 = p0;
+}
+
+/*
+ * GLL nodes, weights and derivative matrix (Sec. "Spatial Discretization":
+ * Lobatto points, Lagrange basis psi_i, derivative dpsi_m/dxi at xi_i).
+ * Nodes: -1, +1 and the roots of q(x) = P_{N-1}(x) - x P_N(x) (proportional to
+ * (1-x^2) P_N'(x)), by Newton from the Chebyshev-Lobatto points.
+ * Weights: w_i = 2 / (N (N+1) P_N(x_i)^2).
+ * D_im = dpsi_m/dxi (xi_i) = P_N(x_i) / (P_N(x_m) (x_i - x_m)), i != m;
+ * D_00 = -N(N+1)/4, D_NN = N(N+1)/4, other diagonal entries 0.
+ * D is row-major: D[i*(N+1)+m].
+ */
+int or_gll(int N, double *xi, double *w, double *D)
+{
+    if (N < 1 || N > 8) return -1;
+    int P = N + 1;
+    for (int i = 0; i <= N; i++) xi[i] = -cos(OR_PI * i / N);
+    for (int i = 1; i < N; i++) {
+        double x = xi[i];
+        for (int it = 0; it < 100; it++) {
+            double pn, dpn, pn1, pm, dpm, pm1;
+            legendre(N, x, &pn, &dpn, &pn1);
+            legendre(N - 1, x, &pm, &dpm, &pm1);
+            double q = pm - x * pn;
+            double dq = dpm - pn - x * dpn;
+            double dx = q / dq;
+            x -= dx;
+            if (fabs(dx) < 1e-16) break;
+        }
+        xi[i] = x;
+    }
+    xi[0] = -1.0; xi[N] = 1.0;
+    for (int i = 0; i < P / 2; i++) { double s = 0.5 * (xi[N - i] - xi[i]); xi[i] = -s; xi[N - i] = s; }
+    if (N % 2 == 0) xi[N / 2] = 0.0;
+    double PN[OR_MAXP];
+    for (int i = 0; i <= N; i++) {
+        double pn, dpn, pn1;
+        legendre(N, xi[i], &pn, &dpn, &pn1);
+        PN[i] = pn;
+        w[i] = 2.0 / (N * (N + 1.0) * pn * pn);
+    }
+    for (int i = 0; i <= N; i++)
+        for (int m = 0; m <= N; m++) {
+            double d;
+            if (i != m) d = PN[i] / (PN[m] * (xi[i] - xi[m]));
+            else if (i == 0) d = -N * (N + 1.0) / 4.0;
+            else if (i == N) d = N * (N + 1.0) / 4.0;
+            else d = 0.0;
+            D[i * P + m] = d;
+        }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mesh numbering.  Local node l = i + P(j + P k); unique ids follow a global
+ * lattice (CG storage: one copy per unique grid point).
+ *
+ * Box: e = ex + nx(ey + ny ez); lattice g = (ex N + i, ey N + j, ez N + k),
+ * wrapped in periodic directions; id = gi + ni (gj + nj gk).
+ *
+ * Shell: a cube surface lattice (X,Y,Z) in {0..L}^3, L = ne N.  Face f maps
+ * (s,t) in {0..L}^2 to: f0 (L,s,t), f1 (L-s,L,t), f2 (0,L-s,t), f3 (s,0,t),
+ * f4 (s,t,L), f5 (t,s,0).  Horizontal ids are given in first-occurrence order
+ * over f, then t, then s; id = h + nh gk.  e = ex + ne(ey + ne(f + 6 ez)).
+ */
+static void face_lattice(int f, int L, int s, int t, int *X, int *Y, int *Z)
+{
+    switch (f) {
+    case 0: *X = L; *Y = s; *Z = t; break;
+    case 1: *X = L - s; *Y = L; *Z = t; break;
+    case 2: *X = 0; *Y = L - s; *Z = t; break;
+    case 3: *X = s; *Y = 0; *Z = t; break;
+    case 4: *X = s; *Y = t; *Z = L; break;
+    default: *X = t; *Y = s; *Z = 0; break;
+    }
+}
+
+static int check_desc(const or_mesh_desc *d)
+{
+    if (d->N < 1 || d->N > 8) return -1;
+    if (d->kind == 0) {
+        for (int a = 0; a < 3; a++) if (d->ne[a] < 1) return -1;
+        if (!d->periodic[0] || !d->periodic[1]) return -1;
+        for (int a = 0; a < 3; a++) if (d->periodic[a] && d->ne[a] < 2) return -1;
+        return 0;
+    }
+    if (d->kind == 1) return (d->ne[0] >= 1 && d->ne[2] >= 1) ? 0 : -1;
+    return -1;
+}
+
+/* coordinate of lattice index c in [0, ncell*N] along one direction:
+ * the element (clamped to the last) and its local node */
+static void lattice_split(int64_t c, int N, int ncell, int *ec, int *ic)
+{
+    int64_t e = c / N;
+    if (e > ncell - 1) e = ncell - 1;
+    *ec = (int)e;
+    *ic = (int)(c - (int64_t)N * e);
+}
+
+static void box_point(const or_ctx *C, int64_t gi, int64_t gj, int64_t gk, double *x, double *y, double *z)
+{
+    const or_mesh_desc *d = &C->m;
+    int N = C->N, e, i;
+    lattice_split(gi, N, d->ne[0], &e, &i);
+    double xx = d->extent[0] * (e + (1.0 + C->xi[i]) / 2.0) / d->ne[0];
+    lattice_split(gj, N, d->ne[1], &e, &i);
+    double yy = d->extent[1] * (e + (1.0 + C->xi[i]) / 2.0) / d->ne[1];
+    lattice_split(gk, N, d->ne[2], &e, &i);
+    double zz = d->extent[2] * (e + (1.0 + C->xi[i]) / 2.0) / d->ne[2];
+    /* terrain-following map z' = z + h(x,y) (1 - z/H) */
+    double h = d->h0 * sin(2.0 * OR_PI * xx / d->extent[0]) * sin(2.0 * OR_PI * yy / d->extent[1]);
+    *x = xx; *y = yy; *z = zz + h * (1.0 - zz / d->extent[2]);
+}
+
+/* equiangular gnomonic node from the surface lattice and radial lattice index */
+static void shell_point(const or_ctx *C, int X, int Y, int Z, int64_t gk, double *x, double *y, double *z)
+{
+    const or_mesh_desc *d = &C->m;
+    int N = C->N, ne = d->ne[0], e, i;
+    int lat[3] = {X, Y, Z};
+    double Pv[3];
+    for (int a = 0; a < 3; a++) {
+        lattice_split(lat[a], N, ne, &e, &i);
+        double alpha = (OR_PI / 2.0) * (e + (1.0 + C->xi[i]) / 2.0) / ne - OR_PI / 4.0;
+        Pv[a] = tan(alpha);
+    }
+    double nrm = sqrt(Pv[0] * Pv[0] + Pv[1] * Pv[1] + Pv[2] * Pv[2]);
+    lattice_split(gk, N, d->ne[2], &e, &i);
+    double r = d->extent[0] + d->extent[2] * (e + (1.0 + C->xi[i]) / 2.0) / d->ne[2];
+    *x = r * Pv[0] / nrm; *y = r * Pv[1] / nrm; *z = r * Pv[2] / nrm;
+}
+
+int or_counts(const or_mesh_desc *d, int64_t *n_elem, int64_t *n_unique, int64_t *n_horiz)
+{
+    if (check_desc(d)) return -1;
+    int N = d->N;
+    if (d->kind == 0) {
+        int64_t ni = d->periodic[0] ? (int64_t)d->ne[0] * N : (int64_t)d->ne[0] * N + 1;
+        int64_t nj = d->periodic[1] ? (int64_t)d->ne[1] * N : (int64_t)d->ne[1] * N + 1;
+        int64_t nk = d->periodic[2] ? (int64_t)d->ne[2] * N : (int64_t)d->ne[2] * N + 1;
+        *n_elem = (int64_t)d->ne[0] * d->ne[1] * d->ne[2];
+        *n_horiz = ni * nj;
+        *n_unique = ni * nj * nk;
+    } else {
+        int64_t L = (int64_t)d->ne[0] * N;
+        *n_elem = 6 * (int64_t)d->ne[0] * d->ne[0] * d->ne[2];
+        *n_horiz = 6 * L * L + 2;
+        *n_unique = *n_horiz * ((int64_t)d->ne[2] * N + 1);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+static void build_numbering(or_ctx *C)
+{
+    const or_mesh_desc *d = &C->m;
+    int N = C->N, P = C->P, np = C->np;
+    if (d->kind == 0) {
+        int nx = d->ne[0], ny = d->ne[1], nz = d->ne[2];
+        int64_t ni = d->periodic[0] ? (int64_t)nx * N : (int64_t)nx * N + 1;
+        int64_t nj = d->periodic[1] ? (int64_t)ny * N : (int64_t)ny * N + 1;
+        int64_t nk = d->periodic[2] ? (int64_t)nz * N : (int64_t)nz * N + 1;
+        for (int ez = 0; ez < nz; ez++)
+            for (int ey = 0; ey < ny; ey++)
+                for (int ex = 0; ex < nx; ex++) {
+                    int64_t e = ex + (int64_t)nx * (ey + (int64_t)ny * ez);
+                    for (int k = 0; k < P; k++)
+                        for (int j = 0; j < P; j++)
+                            for (int i = 0; i < P; i++) {
+                                int64_t gi = (int64_t)ex * N + i, gj = (int64_t)ey * N + j, gk = (int64_t)ez * N + k;
+                                if (d->periodic[0]) gi %= ni;
+                                if (d->periodic[1]) gj %= nj;
+                                if (d->periodic[2]) gk %= nk;
+                                C->G[e * np + i + P * (j + P * k)] = (int32_t)(gi + ni * (gj + nj * gk));
+                            }
+                }
+        C->nk = nk;
+    } else {
+        int ne = d->ne[0], nz = d->ne[2];
+        int L = ne * N;
+        int64_t L1 = L + 1;
+        int32_t *hid = (int32_t *)malloc(sizeof(int32_t) * L1 * L1 * L1);
+        for (int64_t a = 0; a < L1 * L1 * L1; a++) hid[a] = -1;
+        int32_t next = 0;
+        for (int f = 0; f < 6; f++)
+            for (int t = 0; t <= L; t++)
+                for (int s = 0; s <= L; s++) {
+                    int X, Y, Z;
+                    face_lattice(f, L, s, t, &X, &Y, &Z);
+                    int64_t a = X + L1 * (Y + L1 * Z);
+                    if (hid[a] < 0) hid[a] = next++;
+                }
+        int64_t nh = C->nh;
+        for (int ez = 0; ez < nz; ez++)
+            for (int f = 0; f < 6; f++)
+                for (int ey = 0; ey < ne; ey++)
+                    for (int ex = 0; ex < ne; ex++) {
+                        int64_t e = ex + (int64_t)ne * (ey + (int64_t)ne * (f + 6 * (int64_t)ez));
+                        for (int k = 0; k < P; k++)
+                            for (int j = 0; j < P; j++)
+                                for (int i = 0; i < P; i++) {
+                                    int X, Y, Z;
+                                    face_lattice(f, L, ex * N + i, ey * N + j, &X, &Y, &Z);
+                                    int64_t h = hid[X + L1 * (Y + L1 * Z)];
+                                    int64_t gk = (int64_t)ez * N + k;
+                                    C->G[e * np + i + P * (j + P * k)] = (int32_t)(h + nh * gk);
+                                }
+                    }
+        /* unique coordinates: any lattice point (the first occurrence) */
+        for (int f = 0; f < 6; f++)
+            for (int t = 0; t <= L; t++)
+                for (int s = 0; s <= L; s++) {
+                    int X, Y, Z;
+                    face_lattice(f, L, s, t, &X, &Y, &Z);
+                    int64_t h = hid[X + L1 * (Y + L1 * Z)];
+                    for (int64_t gk = 0; gk < C->nk; gk++) {
+                        double x, y, z;
+                        shell_point(C, X, Y, Z, gk, &x, &y, &z);
+                        int64_t I = h + nh * gk;
+                        C->xu[I] = x; C->xu[C->nu + I] = y; C->xu[2 * C->nu + I] = z;
+                    }
+                }
+        /* element-local coordinates from the same lattice: copies agree bitwise */
+        for (int ez = 0; ez < nz; ez++)
+            for (int f = 0; f < 6; f++)
+                for (int ey = 0; ey < ne; ey++)
+                    for (int ex = 0; ex < ne; ex++) {
+                        int64_t e = ex + (int64_t)ne * (ey + (int64_t)ne * (f + 6 * (int64_t)ez));
+                        for (int k = 0; k < P; k++)
+                            for (int j = 0; j < P; j++)
+                                for (int i = 0; i < P; i++) {
+                                    int X, Y, Z;
+                                    face_lattice(f, L, ex * N + i, ey * N + j, &X, &Y, &Z);
+                                    double x, y, z;
+                                    shell_point(C, X, Y, Z, (int64_t)ez * N + k, &x, &y, &z);
+                                    int64_t g = e * np + i + P * (j + P * k);
+                                    C->xl[g] = x; C->xl[C->nl + g] = y; C->xl[2 * C->nl + g] = z;
+                                }
+                    }
+        free(hid);
+    }
+    if (d->kind == 0) {
+        /* element-local coordinates (unwrapped) and unique coordinates (wrapped lattice) */
+        int nx = d->ne[0], ny = d->ne[1], nz = d->ne[2];
+        for (int ez = 0; ez < nz; ez++)
+            for (int ey = 0; ey < ny; ey++)
+                for (int ex = 0; ex < nx; ex++) {
+                    int64_t e = ex + (int64_t)nx * (ey + (int64_t)ny * ez);
+                    for (int k = 0; k < P; k++)
+                        for (int j = 0; j < P; j++)
+                            for (int i = 0; i < P; i++) {
+                                double x, y, z;
+                                box_point(C, (int64_t)ex * N + i, (int64_t)ey * N + j, (int64_t)ez * N + k, &x, &y, &z);
+                                int64_t g = e * np + i + P * (j + P * k);
+                                C->xl[g] = x; C->xl[C->nl + g] = y; C->xl[2 * C->nl + g] = z;
+                            }
+                }
+        int64_t ni = d->periodic[0] ? (int64_t)nx * N : (int64_t)nx * N + 1;
+        int64_t nj = d->periodic[1] ? (int64_t)ny * N : (int64_t)ny * N + 1;
+        for (int64_t gk = 0; gk < C->nk; gk++)
+            for (int64_t gj = 0; gj < nj; gj++)
+                for (int64_t gi = 0; gi < ni; gi++) {
+                    double x, y, z;
+                    box_point(C, gi, gj, gk, &x, &y, &z);
+                    int64_t I = gi + ni * (gj + nj * gk);
+                    C->xu[I] = x; C->xu[C->nu + I] = y; C->xu[2 * C->nu + I] = z;
+                }
+    }
+}
+
+/* Inverse map: copies of each unique node in ascending (e*np + l). */
+static void build_inverse(or_ctx *C)
+{
+    int64_t *cnt = (int64_t *)calloc(C->nu + 1, sizeof(int64_t));
+    for (int64_t g = 0; g < C->nl; g++) cnt[C->G[g] + 1]++;
+    C->off[0] = 0;
+    for (int64_t I = 0; I < C->nu; I++) C->off[I + 1] = C->off[I] + cnt[I + 1];
+    int64_t *fill = (int64_t *)calloc(C->nu, sizeof(int64_t));
+    for (int64_t g = 0; g < C->nl; g++) {
+        int64_t I = C->G[g];
+        C->cp[C->off[I] + fill[I]++] = g;
+    }
+    free(cnt); free(fill);
+}
+
+/*
+ * Metric terms (computed once, Eq. (derivatives) and the remark after it):
+ * A = d(x,y,z)/d(xi,eta,zeta) by derivative-matrix contractions of the nodal
+ * coordinates (isoparametric), J = det A, inverse metric = adj(A)/J.
+ * Stored with J w_i w_j w_k (the weight of Eq. (discstrongform)).
+ */
+static int build_metric(or_ctx *C)
+{
+    int P = C->P, np = C->np;
+    int bad = 0;
+#pragma omp parallel for reduction(| : bad)
+    for (int64_t e = 0; e < C->ne; e++) {
+        const double *X = C->xl + e * np, *Y = C->xl + C->nl + e * np, *Z = C->xl + 2 * C->nl + e * np;
+        for (int k = 0; k < P; k++)
+            for (int j = 0; j < P; j++)
+                for (int i = 0; i < P; i++) {
+                    int l = i + P * (j + P * k);
+                    double xa = 0, xb = 0, xc = 0, ya = 0, yb = 0, yc = 0, za = 0, zb = 0, zc = 0;
+                    for (int m = 0; m < P; m++) {
+                        int la = m + P * (j + P * k), lb = i + P * (m + P * k), lc = i + P * (j + P * m);
+                        xa += C->D[i * P + m] * X[la]; ya += C->D[i * P + m] * Y[la]; za += C->D[i * P + m] * Z[la];
+                        xb += C->D[j * P + m] * X[lb]; yb += C->D[j * P + m] * Y[lb]; zb += C->D[j * P + m] * Z[lb];
+                        xc += C->D[k * P + m] * X[lc]; yc += C->D[k * P + m] * Y[lc]; zc += C->D[k * P + m] * Z[lc];
+                    }
+                    double J = xa * (yb * zc - yc * zb) - xb * (ya * zc - yc * za) + xc * (ya * zb - yb * za);
+                    if (!(J > 0.0)) bad = 1;
+                    double inv[9];
+                    inv[0] = (yb * zc - yc * zb) / J; /* xi_x   */
+                    inv[1] = (xc * zb - xb * zc) / J; /* xi_y   */
+                    inv[2] = (xb * yc - xc * yb) / J; /* xi_z   */
+                    inv[3] = (yc * za - ya * zc) / J; /* eta_x  */
+                    inv[4] = (xa * zc - xc * za) / J; /* eta_y  */
+                    inv[5] = (xc * ya - xa * yc) / J; /* eta_z  */
+                    inv[6] = (ya * zb - yb * za) / J; /* zeta_x */
+                    inv[7] = (xb * za - xa * zb) / J; /* zeta_y */
+                    inv[8] = (xa * yb - xb * ya) / J; /* zeta_z */
+                    int64_t g = e * np + l;
+                    for (int c = 0; c < 9; c++) C->met[c * C->nl + g] = inv[c];
+                    C->met[9 * C->nl + g] = J * C->w[i] * C->w[j] * C->w[k];
+                }
+    }
+    return bad ? -1 : 0;
+}
+
+/* Diagonal mass matrix M_I = sum over copies of w_ijk J^e (Eq. (discstrongform)). */
+static void build_mass(or_ctx *C)
+{
+#pragma omp parallel for
+    for (int64_t I = 0; I < C->nu; I++) {
+        double s = 0.0;
+        for (int64_t c = C->off[I]; c < C->off[I + 1]; c++) s += C->met[9 * C->nl + C->cp[c]];
+        C->M[I] = s;
+    }
+}
+
+/*
+ * Hydrostatic reference state at unique nodes (reading: the paper's equation
+ * set is not in the text; a hydrostatically balanced reference with the
+ * perturbation variables rho', u, v, w, theta').
+ * Box: isentropic, theta = T0, Exner pi = 1 - g0 z/(cp T0), p = p0 pi^(cp/R),
+ *      rho = p/(R T0 pi).
+ * Shell: isothermal T0 with g(r) = g0 (a/r)^2: p = p0 exp(-(g0 a/(R T0))(1 - a/r)),
+ *      rho = p/(R T0), theta = T0 (p0/p)^(R/cp).
+ * In both, p_bar is then re-evaluated from the equation of state
+ * p = p0 (R rho theta / p0)^gamma, so that p' is exactly 0 when rho', theta' are 0.
+ */
+static void build_reference(or_ctx *C)
+{
+    const or_phys *ph = &C->ph;
+    double cv = ph->cp - ph->R, gamma = ph->cp / cv;
+    int64_t nu = C->nu;
+    for (int64_t I = 0; I < nu; I++) {
+        double x = C->xu[I], y = C->xu[nu + I], z = C->xu[2 * nu + I];
+        double rb, tb, pcf;
+        if (C->m.kind == 0) {
+            double pi = 1.0 - ph->g0 * z / (ph->cp * ph->T0);
+            pcf = ph->p0 * pow(pi, ph->cp / ph->R);
+            rb = pcf / (ph->R * ph->T0 * pi);
+            tb = ph->T0;
+            C->grav[I] = 0.0; C->grav[nu + I] = 0.0; C->grav[2 * nu + I] = -ph->g0;
+        } else {
+            double a = C->m.extent[0];
+            double r = sqrt(x * x + y * y + z * z);
+            pcf = ph->p0 * exp(-(ph->g0 * a / (ph->R * ph->T0)) * (1.0 - a / r));
+            rb = pcf / (ph->R * ph->T0);
+            tb = ph->T0 * pow(ph->p0 / pcf, ph->R / ph->cp);
+            double gr = ph->g0 * (a / r) * (a / r);
+            C->grav[I] = -gr * x / r; C->grav[nu + I] = -gr * y / r; C->grav[2 * nu + I] = -gr * z / r;
+        }
+        C->ref[I] = rb;
+        C->ref[nu + I] = tb;
+        C->ref[2 * nu + I] = ph->p0 * pow(ph->R * rb * tb / ph->p0, gamma);
+    }
+}
+
+/*
+ * No-flux boundary nodes (reading: the paper does not state the boundary
+ * condition): bottom and top radial layers when z is not periodic.
+ * Box: top normal +z; bottom normal (-h_x, -h_y, 1)/|.| of the analytic terrain.
+ * Shell: radial unit vector at both.
+ */
+static void build_normals(or_ctx *C)
+{
+    int64_t nu = C->nu;
+    memset(C->nrm, 0, sizeof(double) * 3 * nu);
+    memset(C->isbnd, 0, sizeof(int32_t) * nu);
+    if (C->m.kind == 0 && C->m.periodic[2]) return;
+    for (int64_t I = 0; I < nu; I++) {
+        int64_t gk = I / C->nh;
+        if (gk != 0 && gk != C->nk - 1) continue;
+        double x = C->xu[I], y = C->xu[nu + I], z = C->xu[2 * nu + I];
+        double n0, n1, n2;
+        if (C->m.kind == 0) {
+            if (gk == 0) {
+                double Lx = C->m.extent[0], Ly = C->m.extent[1], h0 = C->m.h0;
+                double hx = h0 * (2.0 * OR_PI / Lx) * cos(2.0 * OR_PI * x / Lx) * sin(2.0 * OR_PI * y / Ly);
+                double hy = h0 * (2.0 * OR_PI / Ly) * sin(2.0 * OR_PI * x / Lx) * cos(2.0 * OR_PI * y / Ly);
+                double s = sqrt(hx * hx + hy * hy + 1.0);
+                n0 = -hx / s; n1 = -hy / s; n2 = 1.0 / s;
+            } else { n0 = 0.0; n1 = 0.0; n2 = 1.0; }
+        } else {
+            double r = sqrt(x * x + y * y + z * z);
+            n0 = x / r; n1 = y / r; n2 = z / r;
+        }
+        C->nrm[I] = n0; C->nrm[nu + I] = n1; C->nrm[2 * nu + I] = n2;
+        C->isbnd[I] = 1;
+    }
+}
+
+void or_destroy(or_ctx *C)
+{
+    if (!C) return;
+    free(C->G); free(C->xl); free(C->xu); free(C->met); free(C->M); free(C->ref);
+    free(C->grav); free(C->nrm); free(C->isbnd); free(C->off); free(C->cp);
+    free(C);
+}
+
+or_ctx *or_create(const or_mesh_desc *d, const or_phys *ph)
+{
+    if (check_desc(d)) return NULL;
+    or_ctx *C = (or_ctx *)calloc(1, sizeof(or_ctx));
+    C->m = *d; C->ph = *ph;
+    C->N = d->N; C->P = d->N + 1; C->np = C->P * C->P * C->P;
+    or_counts(d, &C->ne, &C->nu, &C->nh);
+    C->nl = C->ne * C->np;
+    C->nk = C->nu / C->nh;
+    C->dtheta = (d->kind == 1);
+    or_gll(C->N, C->xi, C->w, C->D);
+    C->G = (int32_t *)malloc(sizeof(int32_t) * C->nl);
+    C->xl = (double *)malloc(sizeof(double) * 3 * C->nl);
+    C->xu = (double *)malloc(sizeof(double) * 3 * C->nu);
+    C->met = (double *)malloc(sizeof(double) * 10 * C->nl);
+    C->M = (double *)malloc(sizeof(double) * C->nu);
+    C->ref = (double *)malloc(sizeof(double) * 3 * C->nu);
+    C->grav = (double *)malloc(sizeof(double) * 3 * C->nu);
+    C->nrm = (double *)malloc(sizeof(double) * 3 * C->nu);
+    C->isbnd = (int32_t *)malloc(sizeof(int32_t) * C->nu);
+    C->off = (int64_t *)malloc(sizeof(int64_t) * (C->nu + 1));
+    C->cp = (int64_t *)malloc(sizeof(int64_t) * C->nl);
+    build_numbering(C);
+    build_inverse(C);
+    if (build_metric(C)) { or_destroy(C); return NULL; }
+    build_mass(C);
+    build_reference(C);
+    build_normals(C);
+    return C;
+}
+
+void or_info(const or_ctx *C, int64_t *out /* ne, nl, nu, nh, nk */)
+{
+    out[0] = C->ne; out[1] = C->nl; out[2] = C->nu; out[3] = C->nh; out[4] = C->nk;
+}
+
+/* copy an internal array out: 0 G (int32 [nl]), 1 xl [3][nl], 2 xu [3][nu],
+ * 3 metric [10][nl], 4 M [nu], 5 ref [3][nu], 6 gravity [3][nu], 7 normals [3][nu],
+ * 8 isbnd (int32 [nu]), 9 gll (xi, w, D) */
+int or_get(const or_ctx *C, int what, void *out)
+{
+    switch (what) {
+    case 0: memcpy(out, C->G, sizeof(int32_t) * C->nl); return 0;
+    case 1: memcpy(out, C->xl, sizeof(double) * 3 * C->nl); return 0;
+    case 2: memcpy(out, C->xu, sizeof(double) * 3 * C->nu); return 0;
+    case 3: memcpy(out, C->met, sizeof(double) * 10 * C->nl); return 0;
+    case 4: memcpy(out, C->M, sizeof(double) * C->nu); return 0;
+    case 5: memcpy(out, C->ref, sizeof(double) * 3 * C->nu); return 0;
+    case 6: memcpy(out, C->grav, sizeof(double) * 3 * C->nu); return 0;
+    case 7: memcpy(out, C->nrm, sizeof(double) * 3 * C->nu); return 0;
+    case 8: memcpy(out, C->isbnd, sizeof(int32_t) * C->nu); return 0;
+    case 9: {
+        double *o = (double *)out;
+        memcpy(o, C->xi, sizeof(double) * C->P);
+        memcpy(o + C->P, C->w, sizeof(double) * C->P);
+        memcpy(o + 2 * C->P, C->D, sizeof(double) * C->P * C->P);
+        return 0;
+    }
+    default: return -1;
+    }
+}
+
+/* replace the reference state (for invariance checks on custom backgrounds) */
+int or_set(or_ctx *C, int what, const void *in)
+{
+    switch (what) {
+    case 5: memcpy(C->ref, in, sizeof(double) * 3 * C->nu); return 0;
+    case 6: memcpy(C->grav, in, sizeof(double) * 3 * C->nu); return 0;
+    default: return -1;
+    }
+}
+
+/* no-flux projection u <- u - (u.n) n at boundary nodes (reading) */
+static void project_noflux(const or_ctx *C, double *u, double *v, double *w)
+{
+    int64_t nu = C->nu;
+    for (int64_t I = 0; I < nu; I++) {
+        if (!C->isbnd[I]) continue;
+        double n0 = C->nrm[I], n1 = C->nrm[nu + I], n2 = C->nrm[2 * nu + I];
+        double dn = u[I] * n0 + v[I] * n1 + w[I] * n2;
+        u[I] -= dn * n0; v[I] -= dn * n1; w[I] -= dn * n2;
+    }
+}
+
+/*
+ * Initial state at unique nodes (workload definition, not part of the method).
+ * q = [5][nu]: rho', u, v, w, theta'.  The potential-temperature perturbation
+ * is balanced by rho' = -rho_bar theta'/(theta_bar + theta') so that the
+ * pressure is unperturbed.  noise: [3][nu] standard normals or NULL.
+ */
+int or_init_state(const or_ctx *C, const or_ic_desc *ic, const double *noise, double *q)
+{
+    int64_t nu = C->nu;
+    for (int64_t I = 0; I < nu; I++) {
+        double x = C->xu[I], y = C->xu[nu + I], z = C->xu[2 * nu + I];
+        double tp = 0.0, u = 0.0, v = 0.0, w = 0.0;
+        if (ic->kind == 1) {
+            double dx = x - ic->c[0], dy = y - ic->c[1], dz = z - ic->c[2];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (r < ic->radius) tp = ic->amp * (1.0 + cos(OR_PI * r / ic->radius)) / 2.0;
+        } else if (ic->kind == 2) {
+            double a = C->m.extent[0];
+            double r = sqrt(x * x + y * y + z * z);
+            double lon = atan2(y, x), lat = asin(z / r);
+            double cl = cos(lat);
+            u = ic->jet_u0 * cl * cl * (-sin(lon));
+            v = ic->jet_u0 * cl * cl * cos(lon);
+            w = 0.0;
+            double cs = sin(lat) * sin(ic->c[1]) + cos(lat) * cos(ic->c[1]) * cos(lon - ic->c[0]);
+            if (cs > 1.0) cs = 1.0;
+            if (cs < -1.0) cs = -1.0;
+            double dist = a * acos(cs);
+            double hz = (r - a - ic->c[2]) / ic->lz;
+            double hd = dist / ic->radius;
+            tp = ic->amp * exp(-hd * hd - hz * hz);
+        }
+        if (noise) {
+            u += ic->noise_amp * noise[I];
+            v += ic->noise_amp * noise[nu + I];
+            w += ic->noise_amp * noise[2 * nu + I];
+        }
+        double rb = C->ref[I], tb = C->ref[nu + I];
+        q[I] = -rb * tp / (tb + tp);
+        q[nu + I] = u; q[2 * nu + I] = v; q[3 * nu + I] = w;
+        q[4 * nu + I] = tp;
+    }
+    project_noflux(C, q + nu, q + 2 * nu, q + 3 * nu);
+    return 0;
+}
+
+/*
+ * Element-wise right-hand side (the paper's create_rhs, Eq. (discstrongform)
+ * and Eq. (derivatives)), perturbation form of the inviscid compressible Euler
+ * equations with a hydrostatic reference (grad p_bar = rho_bar g):
+ *   R_rho'   = -div(rho u)
+ *   R_u      = -(u.grad)u - grad(p')/rho + (rho'/rho) g
+ *   R_theta' = -u.grad(theta') - u.grad(theta_bar)
+ * with rho = rho_bar + rho', and the pressure perturbation from the equation of
+ * state p = p0 (R rho theta/p0)^gamma written without cancellation:
+ *   Delta = rho' theta_bar + rho_bar theta' + rho' theta',
+ *   p' = p_bar expm1(gamma log1p(Delta/(rho_bar theta_bar))).
+ * Differentiated nodal fields (all in one pass per direction):
+ *   rho u, rho v, rho w, u, v, w, theta', p'  (and theta_bar on the shell).
+ * Output: C[v][e][l] = J w_ijk R_v at every element-local node.
+ */
+int or_rhs(const or_ctx *C, const double *q, double *Cout)
+{
+    int P = C->P, np = C->np;
+    int64_t nu = C->nu, nl = C->nl;
+    double cv = C->ph.cp - C->ph.R, gamma = C->ph.cp / cv;
+    int nf = C->dtheta ? 9 : 8;
+#pragma omp parallel for
+    for (int64_t e = 0; e < C->ne; e++) {
+        double F[9][OR_MAXP * OR_MAXP * OR_MAXP];
+        double rp[OR_MAXP * OR_MAXP * OR_MAXP], rho[OR_MAXP * OR_MAXP * OR_MAXP];
+        double U[3][OR_MAXP * OR_MAXP * OR_MAXP], gv[3][OR_MAXP * OR_MAXP * OR_MAXP];
+        for (int l = 0; l < np; l++) {
+            int64_t I = C->G[e * np + l];
+            double r1 = q[I], u = q[nu + I], v = q[2 * nu + I], w = q[3 * nu + I], tp = q[4 * nu + I];
+            double rb = C->ref[I], tb = C->ref[nu + I], pb = C->ref[2 * nu + I];
+            double rh = rb + r1;
+            double dl = r1 * tb + rb * tp + r1 * tp;
+            F[0][l] = rh * u; F[1][l] = rh * v; F[2][l] = rh * w;
+            F[3][l] = u; F[4][l] = v; F[5][l] = w;
+            F[6][l] = tp;
+            F[7][l] = pb * expm1(gamma * log1p(dl / (rb * tb)));
+            F[8][l] = tb;
+            rp[l] = r1; rho[l] = rh;
+            U[0][l] = u; U[1][l] = v; U[2][l] = w;
+            gv[0][l] = C->grav[I]; gv[1][l] = C->grav[nu + I]; gv[2][l] = C->grav[2 * nu + I];
+        }
+        for (int k = 0; k < P; k++)
+            for (int j = 0; j < P; j++)
+                for (int i = 0; i < P; i++) {
+                    int l = i + P * (j + P * k);
+                    int64_t g = e * np + l;
+                    double mx[9];
+                    for (int c = 0; c < 9; c++) mx[c] = C->met[c * nl + g];
+                    double dx[9], dy[9], dz[9];
+                    for (int f = 0; f < nf; f++) {
+                        double a = 0.0, b = 0.0, c = 0.0;
+                        for (int m = 0; m < P; m++) {
+                            a += C->D[i * P + m] * F[f][m + P * (j + P * k)];
+                            b += C->D[j * P + m] * F[f][i + P * (m + P * k)];
+                            c += C->D[k * P + m] * F[f][i + P * (j + P * m)];
+                        }
+                        /* chain rule: d/dx = d/dxi xi_x + d/deta eta_x + d/dzeta zeta_x */
+                        dx[f] = a * mx[0] + b * mx[3] + c * mx[6];
+                        dy[f] = a * mx[1] + b * mx[4] + c * mx[7];
+                        dz[f] = a * mx[2] + b * mx[5] + c * mx[8];
+                    }
+                    double u = U[0][l], v = U[1][l], w = U[2][l];
+                    double b = rp[l] / rho[l];
+                    double R[5];
+                    R[0] = -(dx[0] + dy[1] + dz[2]);
+                    R[1] = -(u * dx[3] + v * dy[3] + w * dz[3]) - dx[7] / rho[l] + b * gv[0][l];
+                    R[2] = -(u * dx[4] + v * dy[4] + w * dz[4]) - dy[7] / rho[l] + b * gv[1][l];
+                    R[3] = -(u * dx[5] + v * dy[5] + w * dz[5]) - dz[7] / rho[l] + b * gv[2][l];
+                    R[4] = -(u * dx[6] + v * dy[6] + w * dz[6]);
+                    if (C->dtheta) R[4] -= u * dx[8] + v * dy[8] + w * dz[8];
+                    double Jw = C->met[9 * nl + g];
+                    for (int s = 0; s < 5; s++) Cout[s * nl + g] = Jw * R[s];
+                }
+    }
+    return 0;
+}
+
+/*
+ * Direct stiffness summation (text after Eq. (derivatives)): sum the element
+ * contributions at each unique node, gathered over its copies in ascending
+ * (e, l) order; flags bit 0: divide by the mass matrix M (weighted by the
+ * element volumes); bit 1: no-flux projection of components 1..3 (nvar == 5).
+ * cin = [nvar][nl], out = [nvar][nu].
+ */
+int or_dss(const or_ctx *C, int nvar, const double *cin, int flags, double *out)
+{
+    int64_t nu = C->nu, nl = C->nl;
+#pragma omp parallel for
+    for (int64_t I = 0; I < nu; I++) {
+        for (int v = 0; v < nvar; v++) {
+            double s = 0.0;
+            for (int64_t c = C->off[I]; c < C->off[I + 1]; c++) s += cin[v * nl + C->cp[c]];
+            if (flags & 1) s = s / C->M[I];
+            out[v * nu + I] = s;
+        }
+    }
+    if ((flags & 2) && nvar == 5) project_noflux(C, out + nu, out + 2 * nu, out + 3 * nu);
+    return 0;
+}
+
+/*
+ * SSP-RK3 stage in Shu-Osher form (reading: the paper's five-stage scheme has
+ * no coefficients in the text; "update q" of Code example 1):
+ *   q_out = a_s qn + b_s (qs + dt R), (a,b) = (0,1), (3/4,1/4), (1/3,2/3).
+ */
+int or_rk_stage(const or_ctx *C, int stage, double dt, const double *qn, const double *qs, const double *R, double *qout)
+{
+    int64_t n = 5 * C->nu;
+    for (int64_t a = 0; a < n; a++) {
+        double y = qs[a] + dt * R[a];
+        if (stage == 0) qout[a] = y;
+        else if (stage == 1) qout[a] = 0.75 * qn[a] + 0.25 * y;
+        else qout[a] = (1.0 / 3.0) * qn[a] + (2.0 / 3.0) * y;
+    }
+    return 0;
+}
+
+/* right-hand side R(q) = DSS_M(create_rhs(q)) with the no-flux projection */
+static void full_rhs(const or_ctx *C, const double *q, double *cbuf, double *R)
+{
+    or_rhs(C, q, cbuf);
+    or_dss(C, 5, cbuf, 3, R);
+}
+
+/* nsteps SSP-RK3 steps in place on q ([5][nu]); Code example 1 time loop */
+int or_step(const or_ctx *C, double dt, int nsteps, double *q)
+{
+    int64_t n = 5 * C->nu;
+    double *cbuf = (double *)malloc(sizeof(double) * 5 * C->nl);
+    double *R = (double *)malloc(sizeof(double) * n);
+    double *qs = (double *)malloc(sizeof(double) * n);
+    if (!cbuf || !R || !qs) { free(cbuf); free(R); free(qs); return -2; }
+    for (int s = 0; s < nsteps; s++) {
+        full_rhs(C, q, cbuf, R);
+        or_rk_stage(C, 0, dt, q, q, R, qs);
+        full_rhs(C, qs, cbuf, R);
+        or_rk_stage(C, 1, dt, q, qs, R, qs);
+        full_rhs(C, qs, cbuf, R);
+        or_rk_stage(C, 2, dt, q, qs, R, q);
+    }
+    free(cbuf); free(R); free(qs);
+    return 0;
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
