@@ -1,0 +1,179 @@
+/*
+ * numa.h -- C ABI of the MI355X (gfx950) hot path of the NUMA spectral-element
+ * dynamical core (Mueller et al., "Strong scaling for numerical weather
+ * prediction at petascale with the atmospheric model NUMA", IJHPCA 2016).
+ *
+ * The path: the explicit right-hand side of the compressible Euler equations
+ * in perturbation form (rho', u, v, w, theta') on hexahedral spectral elements
+ * with Gauss-Lobatto-Legendre (GLL) quadrature of order N (Sec. "Spatial
+ * Discretization", Eq. (discstrongform), Eq. (derivatives)); the direct
+ * stiffness summation (DSS) weighted by the diagonal mass matrix; and an
+ * explicit Runge-Kutta stage update (Sec. "Time Discretization"; Code example 1).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Status: every function returns int32_t: NUMA_OK (0) or a negative code.
+ *   numa_last_error() returns a thread-local message for the last failure.
+ *   Nothing aborts, throws or exits across this boundary.
+ * - Device work is asynchronous on the caller's stream (a hipStream_t passed
+ *   as void*; NULL is the default stream).  Device faults surface at the next
+ *   synchronising call, as in HIP.  Argument errors are detected on the host
+ *   before anything is enqueued.
+ * - Memory: the library never allocates device memory.  The caller allocates
+ *   one workspace of numa_mesh_workspace_bytes() and binds it with
+ *   numa_mesh_attach_workspace(); states and outputs are caller-owned device
+ *   buffers.  The mesh handle owns only host memory.
+ * - Layouts: unique-node (CG storage) fields are structure-of-arrays
+ *   [nvar][n_unique] FP64.  Element-local (E-vector, DG storage) fields are
+ *   [nvar][n_elem][(N+1)^3] FP64 with local node l = i + (N+1)(j + (N+1)k).
+ *   The state q is [5][n_unique]: rho', u, v, w, theta'.
+ * - Threading: a handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef NUMA_H
+#define NUMA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NUMA_OK 0
+#define NUMA_EINVAL -1      /* bad argument: null pointer, order, sizes, state of the handle */
+#define NUMA_ENOMEM -2      /* workspace missing or too small */
+#define NUMA_EDEVICE -3     /* a HIP runtime call failed */
+#define NUMA_EUNSUPPORTED -4
+
+#define NUMA_MESH_BOX 0     /* periodic in x and y; z periodic or bounded by no-flux walls */
+#define NUMA_MESH_SHELL 1   /* equiangular cubed-sphere shell, no-flux bottom and top */
+
+#define NUMA_PREC_FP64 0    /* everything in FP64 */
+#define NUMA_PREC_MIXED 1   /* contractions, metric products and fluxes in FP32 */
+
+#define NUMA_DSS_MASS 1     /* divide the summed contributions by the mass matrix */
+#define NUMA_DSS_NOFLUX 2   /* project components 1..3 of a 5-variable field at walls */
+
+/* numa_export selectors */
+#define NUMA_FIELD_MASS 0        /* [n_unique] diagonal mass matrix M */
+#define NUMA_FIELD_REF 1         /* [3][n_unique] rho_bar, theta_bar, p_bar */
+#define NUMA_FIELD_COORDS 2      /* [3][n_unique] x, y, z of the unique nodes */
+#define NUMA_FIELD_METRIC 3      /* [10][n_local] xi_x..zeta_z (row-major inverse Jacobian), J w */
+#define NUMA_FIELD_GRAVITY 4     /* [3][n_unique] gravity vector */
+#define NUMA_FIELD_LOCAL_COORDS 5 /* [3][n_local] element-local node coordinates */
+
+typedef struct numa_mesh *numa_mesh_t;
+
+/*
+ * Mesh description.  order = N, the polynomial order p of the paper (N+1 GLL
+ * points per direction), 1 <= N <= 8.
+ * Box: ne = (nx, ny, nz) elements, periodic = (1, 1, 0 or 1), each periodic
+ *   direction needs ne >= 2; extent = (Lx, Ly, H) in m; terrain_amp h0 gives
+ *   the terrain-following map z' = z + h0 sin(2 pi x/Lx) sin(2 pi y/Ly)(1 - z/H).
+ * Shell: ne = (ne, ignored, nz): ne x ne elements per cube face, nz radial
+ *   layers; extent = (a, ignored, H): inner radius and depth.
+ */
+typedef struct numa_mesh_desc {
+    int32_t kind;
+    int32_t order;
+    int32_t ne[3];
+    int32_t periodic[3];
+    double extent[3];
+    double terrain_amp;
+} numa_mesh_desc;
+
+/* Gas and reference-atmosphere constants.  T0: theta0 of the isentropic box
+ * reference, or the temperature of the isothermal shell reference. */
+typedef struct numa_phys {
+    double R, cp, g0, p0, T0;
+} numa_phys;
+
+/* Initial perturbation over the reference state (workload definition).
+ * kind 0: rest; 1: cosine bubble theta' = amp (1 + cos(pi r/radius))/2 for
+ * r < radius around c = (x, y, z); 2 (shell): zonal jet jet_u0 cos^2(lat) and a
+ * gaussian theta' blob of e-folding lengths (radius, lz) at c = (lon, lat, height).
+ * rho' = -rho_bar theta'/(theta_bar + theta') keeps the pressure unperturbed.
+ * noise_amp scales the optional standard-normal noise added to u, v, w. */
+typedef struct numa_ic {
+    int32_t kind;
+    double amp, radius;
+    double c[3];
+    double lz, jet_u0, noise_amp;
+} numa_ic;
+
+/* Thread-local description of the last error (never NULL). */
+const char *numa_last_error(void);
+
+/* GLL nodes xi[N+1], weights w[N+1], derivative matrix D[(N+1)^2] row-major,
+ * D[i*(N+1)+m] = dpsi_m/dxi at xi_i (Sec. "Spatial Discretization").  Host only. */
+int32_t numa_gll(int32_t order, double *xi, double *w, double *D);
+
+/* Build the host mesh: numbering, element -> unique gather map and its inverse
+ * (the paper's adjacency lookup table that enumerates the CG nodes, Sec. "Mesh
+ * generation and load balancing").  Host only.  *out receives the handle. */
+int32_t numa_mesh_create(const numa_mesh_desc *d, numa_mesh_t *out);
+int32_t numa_mesh_destroy(numa_mesh_t m);
+
+/* Sizes: elements, element-local nodes, unique nodes, unique nodes per level
+ * (horizontal), levels.  Any pointer may be NULL. */
+int32_t numa_mesh_info(numa_mesh_t m, int64_t *n_elem, int64_t *n_local, int64_t *n_unique,
+                       int64_t *n_horiz, int64_t *n_levels);
+
+/* Host copy of the gather map: host_out[e*(N+1)^3 + l] = unique id.  Host only. */
+int32_t numa_mesh_gather_map(numa_mesh_t m, int32_t *host_out);
+
+/* Device workspace needed for the precisions in prec_mask (bit 0: FP64 path,
+ * bit 1: mixed path).  The FP64 data (geometry, reference, maps, scratch) is
+ * always included. */
+int32_t numa_mesh_workspace_bytes(numa_mesh_t m, int32_t prec_mask, uint64_t *bytes);
+
+/* Bind a caller-owned device buffer (256-byte aligned) as the workspace.
+ * The buffer must outlive every call on the handle. */
+int32_t numa_mesh_attach_workspace(numa_mesh_t m, void *dev_ptr, uint64_t bytes, int32_t prec_mask);
+
+/* Geometry (computed once, remark after Eq. (derivatives)): uploads the maps,
+ * computes element-local coordinates, the metric terms and J w by derivative
+ * contractions of the coordinates (isoparametric), the mass matrix
+ * M_I = sum_e w_ijk J^e (Eq. (discstrongform)) and its inverse, the reference
+ * state, gravity and wall normals, into the workspace.  Asynchronous. */
+int32_t numa_geometry(numa_mesh_t m, const numa_phys *ph, void *stream);
+
+/* Copy an internal field (NUMA_FIELD_*) to a caller device buffer. */
+int32_t numa_export(numa_mesh_t m, int32_t what, void *dev_out, void *stream);
+
+/* Initial state q [5][n_unique] (device) from ic; noise: device [3][n_unique]
+ * standard normals or NULL.  Velocity is projected onto the walls. */
+int32_t numa_init_state(numa_mesh_t m, const numa_ic *ic, const double *noise, double *q, void *stream);
+
+/* Element-wise right-hand side (the paper's create_rhs): from the unique state
+ * q [5][n_unique] to the element-local contributions c_elem [5][n_elem][(N+1)^3]
+ * = J w_ijk R at every element-local node, with
+ *   R_rho' = -div(rho u),  R_u = -(u.grad)u - grad(p')/rho + (rho'/rho) g,
+ *   R_theta' = -u.grad(theta') [- u.grad(theta_bar) on the shell],
+ * derivatives by Eq. (derivatives) (chain rule through the metric terms).
+ * prec: NUMA_PREC_FP64 or NUMA_PREC_MIXED (requires a mixed workspace).
+ * q and c_elem must not overlap. */
+int32_t numa_rhs(numa_mesh_t m, int32_t prec, const double *q, double *c_elem, void *stream);
+
+/* Direct stiffness summation of an element-local field c_elem [nvar][n_local]
+ * into out [nvar][n_unique]: the sum over the copies of each unique node, in
+ * ascending element-local order; NUMA_DSS_MASS divides by M; NUMA_DSS_NOFLUX
+ * (nvar == 5) removes the wall-normal part of components 1..3. */
+int32_t numa_dss(numa_mesh_t m, int32_t nvar, const double *c_elem, double *out, int32_t flags,
+                 void *stream);
+
+/* SSP-RK3 stage s in 0..2 (Shu-Osher form), pointwise over [5][n_unique]:
+ * qout = a_s qn + b_s (qs + dt r), (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3).
+ * qout may alias qs or qn; qn is not read for s = 0. */
+int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn, const double *qs,
+                      const double *r, double *qout, void *stream);
+
+/* nsteps SSP-RK3 steps in place on q [5][n_unique] (device), each stage being
+ * rhs -> DSS (mass, no-flux) -> stage update, fused into the library's stage
+ * kernels.  Uses the workspace scratch; equals the composition of numa_rhs,
+ * numa_dss and numa_rk_stage up to rounding. */
+int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double *q, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NUMA_H */

@@ -65,6 +65,7 @@ def lib():
         L.or_counts.argtypes = [ct.POINTER(_MeshDesc), P, P, P]
         L.or_init_state.argtypes = [P, ct.POINTER(_IC), P, P]
         L.or_rhs.argtypes = [P, P, P]
+        L.or_rhs_scale.argtypes = [P, P, P]
         L.or_dss.argtypes = [P, ct.c_int, P, ct.c_int, P]
         L.or_rk_stage.argtypes = [P, ct.c_int, ct.c_double, P, P, P, P]
         L.or_step.argtypes = [P, ct.c_double, ct.c_int, P]
@@ -180,6 +181,13 @@ class OracleMesh:
         q = np.ascontiguousarray(q, dtype=np.float64).reshape(5, self.n_unique)
         out = np.zeros((5, self.n_local))
         lib().or_rhs(self._h, _p(q), _p(out))
+        return out
+
+    def rhs_scale(self, q: np.ndarray) -> np.ndarray:
+        """J w times the sum of |individual terms| of each R (conditioning scale)."""
+        q = np.ascontiguousarray(q, dtype=np.float64).reshape(5, self.n_unique)
+        out = np.zeros((5, self.n_local))
+        lib().or_rhs_scale(self._h, _p(q), _p(out))
         return out
 
     def dss(self, cin: np.ndarray, flags: int = 1) -> np.ndarray:

@@ -66,6 +66,8 @@ typedef struct {
     int32_t *G;      /* [ne][np] gather map: element-local -> unique */
     double *xl;      /* [3][nl] element-local coordinates */
     double *xu;      /* [3][nu] unique-node coordinates */
+    double *dl, *hl; /* shell: [3][nl] unit radial direction, [nl] height above the inner radius */
+    double *du, *hu; /* shell: the same at unique nodes */
     double *met;     /* [10][nl] xi_x xi_y xi_z eta_x eta_y eta_z zeta_x zeta_y zeta_z J*w */
     double *M;       /* [nu] diagonal mass matrix */
     double *ref;     /* [3][nu] rho_bar, theta_bar, p_bar */
@@ -206,8 +208,11 @@ static void box_point(const or_ctx *C, int64_t gi, int64_t gj, int64_t gk, doubl
     *x = xx; *y = yy; *z = zz + h * (1.0 - zz / d->extent[2]);
 }
 
-/* equiangular gnomonic node from the surface lattice and radial lattice index */
-static void shell_point(const or_ctx *C, int X, int Y, int Z, int64_t gk, double *x, double *y, double *z)
+/* equiangular gnomonic node from the surface lattice (X,Y,Z) and radial
+ * lattice index gk: unit direction dir = P/|P| with P = (tan alpha(X),
+ * tan alpha(Y), tan alpha(Z)), height hgt above the inner radius a, and the
+ * position (a + hgt) dir. */
+static void shell_point(const or_ctx *C, int X, int Y, int Z, int64_t gk, double *dir, double *hgt, double *pos)
 {
     const or_mesh_desc *d = &C->m;
     int N = C->N, ne = d->ne[0], e, i;
@@ -220,8 +225,13 @@ static void shell_point(const or_ctx *C, int X, int Y, int Z, int64_t gk, double
     }
     double nrm = sqrt(Pv[0] * Pv[0] + Pv[1] * Pv[1] + Pv[2] * Pv[2]);
     lattice_split(gk, N, d->ne[2], &e, &i);
-    double r = d->extent[0] + d->extent[2] * (e + (1.0 + C->xi[i]) / 2.0) / d->ne[2];
-    *x = r * Pv[0] / nrm; *y = r * Pv[1] / nrm; *z = r * Pv[2] / nrm;
+    double h = d->extent[2] * (e + (1.0 + C->xi[i]) / 2.0) / d->ne[2];
+    double r = d->extent[0] + h;
+    for (int a = 0; a < 3; a++) {
+        dir[a] = Pv[a] / nrm;
+        pos[a] = r * dir[a];
+    }
+    *hgt = h;
 }
 
 int or_counts(const or_mesh_desc *d, int64_t *n_elem, int64_t *n_unique, int64_t *n_horiz)
@@ -308,10 +318,14 @@ static void build_numbering(or_ctx *C)
                     face_lattice(f, L, s, t, &X, &Y, &Z);
                     int64_t h = hid[X + L1 * (Y + L1 * Z)];
                     for (int64_t gk = 0; gk < C->nk; gk++) {
-                        double x, y, z;
-                        shell_point(C, X, Y, Z, gk, &x, &y, &z);
+                        double dir[3], hgt, pos[3];
+                        shell_point(C, X, Y, Z, gk, dir, &hgt, pos);
                         int64_t I = h + nh * gk;
-                        C->xu[I] = x; C->xu[C->nu + I] = y; C->xu[2 * C->nu + I] = z;
+                        for (int a = 0; a < 3; a++) {
+                            C->xu[a * C->nu + I] = pos[a];
+                            C->du[a * C->nu + I] = dir[a];
+                        }
+                        C->hu[I] = hgt;
                     }
                 }
         /* element-local coordinates from the same lattice: copies agree bitwise */
@@ -325,10 +339,14 @@ static void build_numbering(or_ctx *C)
                                 for (int i = 0; i < P; i++) {
                                     int X, Y, Z;
                                     face_lattice(f, L, ex * N + i, ey * N + j, &X, &Y, &Z);
-                                    double x, y, z;
-                                    shell_point(C, X, Y, Z, (int64_t)ez * N + k, &x, &y, &z);
+                                    double dir[3], hgt, pos[3];
+                                    shell_point(C, X, Y, Z, (int64_t)ez * N + k, dir, &hgt, pos);
                                     int64_t g = e * np + i + P * (j + P * k);
-                                    C->xl[g] = x; C->xl[C->nl + g] = y; C->xl[2 * C->nl + g] = z;
+                                    for (int a = 0; a < 3; a++) {
+                                        C->xl[a * C->nl + g] = pos[a];
+                                        C->dl[a * C->nl + g] = dir[a];
+                                    }
+                                    C->hl[g] = hgt;
                                 }
                     }
         free(hid);
@@ -382,6 +400,12 @@ static void build_inverse(or_ctx *C)
  * A = d(x,y,z)/d(xi,eta,zeta) by derivative-matrix contractions of the nodal
  * coordinates (isoparametric), J = det A, inverse metric = adj(A)/J.
  * Stored with J w_i w_j w_k (the weight of Eq. (discstrongform)).
+ * On the shell the nodal coordinates are x = (a + h_k) d_ij, so the same sums
+ * are taken factor by factor: d/dxi and d/deta contract the unit directions
+ * (the radius is constant along them), d/dzeta contracts the heights h (the
+ * direction is constant along it, and the contraction annihilates the constant
+ * radius a).  This avoids rounding the coordinates at the planet's radius
+ * before differencing them over elements a few km deep.
  */
 static int build_metric(or_ctx *C)
 {
@@ -395,11 +419,25 @@ static int build_metric(or_ctx *C)
                 for (int i = 0; i < P; i++) {
                     int l = i + P * (j + P * k);
                     double xa = 0, xb = 0, xc = 0, ya = 0, yb = 0, yc = 0, za = 0, zb = 0, zc = 0;
-                    for (int m = 0; m < P; m++) {
-                        int la = m + P * (j + P * k), lb = i + P * (m + P * k), lc = i + P * (j + P * m);
-                        xa += C->D[i * P + m] * X[la]; ya += C->D[i * P + m] * Y[la]; za += C->D[i * P + m] * Z[la];
-                        xb += C->D[j * P + m] * X[lb]; yb += C->D[j * P + m] * Y[lb]; zb += C->D[j * P + m] * Z[lb];
-                        xc += C->D[k * P + m] * X[lc]; yc += C->D[k * P + m] * Y[lc]; zc += C->D[k * P + m] * Z[lc];
+                    if (C->m.kind == 0) {
+                        for (int m = 0; m < P; m++) {
+                            int la = m + P * (j + P * k), lb = i + P * (m + P * k), lc = i + P * (j + P * m);
+                            xa += C->D[i * P + m] * X[la]; ya += C->D[i * P + m] * Y[la]; za += C->D[i * P + m] * Z[la];
+                            xb += C->D[j * P + m] * X[lb]; yb += C->D[j * P + m] * Y[lb]; zb += C->D[j * P + m] * Z[lb];
+                            xc += C->D[k * P + m] * X[lc]; yc += C->D[k * P + m] * Y[lc]; zc += C->D[k * P + m] * Z[lc];
+                        }
+                    } else {
+                        const double *DX = C->dl + e * np, *DY = C->dl + C->nl + e * np, *DZ = C->dl + 2 * C->nl + e * np;
+                        const double *Hh = C->hl + e * np;
+                        double r = C->m.extent[0] + Hh[l], hz = 0.0;
+                        for (int m = 0; m < P; m++) {
+                            int la = m + P * (j + P * k), lb = i + P * (m + P * k), lc = i + P * (j + P * m);
+                            xa += C->D[i * P + m] * DX[la]; ya += C->D[i * P + m] * DY[la]; za += C->D[i * P + m] * DZ[la];
+                            xb += C->D[j * P + m] * DX[lb]; yb += C->D[j * P + m] * DY[lb]; zb += C->D[j * P + m] * DZ[lb];
+                            hz += C->D[k * P + m] * Hh[lc];
+                        }
+                        xa *= r; ya *= r; za *= r; xb *= r; yb *= r; zb *= r;
+                        xc = hz * DX[l]; yc = hz * DY[l]; zc = hz * DZ[l];
                     }
                     double J = xa * (yb * zc - yc * zb) - xb * (ya * zc - yc * za) + xc * (ya * zb - yb * za);
                     if (!(J > 0.0)) bad = 1;
@@ -458,13 +496,14 @@ static void build_reference(or_ctx *C)
             tb = ph->T0;
             C->grav[I] = 0.0; C->grav[nu + I] = 0.0; C->grav[2 * nu + I] = -ph->g0;
         } else {
+            /* heights from the radial lattice: 1 - a/r = h/r without cancellation */
             double a = C->m.extent[0];
-            double r = sqrt(x * x + y * y + z * z);
-            pcf = ph->p0 * exp(-(ph->g0 * a / (ph->R * ph->T0)) * (1.0 - a / r));
+            double h = C->hu[I], r = a + h;
+            pcf = ph->p0 * exp(-(ph->g0 * a / (ph->R * ph->T0)) * (h / r));
             rb = pcf / (ph->R * ph->T0);
             tb = ph->T0 * pow(ph->p0 / pcf, ph->R / ph->cp);
             double gr = ph->g0 * (a / r) * (a / r);
-            C->grav[I] = -gr * x / r; C->grav[nu + I] = -gr * y / r; C->grav[2 * nu + I] = -gr * z / r;
+            C->grav[I] = -gr * C->du[I]; C->grav[nu + I] = -gr * C->du[nu + I]; C->grav[2 * nu + I] = -gr * C->du[2 * nu + I];
         }
         C->ref[I] = rb;
         C->ref[nu + I] = tb;
@@ -498,8 +537,7 @@ static void build_normals(or_ctx *C)
                 n0 = -hx / s; n1 = -hy / s; n2 = 1.0 / s;
             } else { n0 = 0.0; n1 = 0.0; n2 = 1.0; }
         } else {
-            double r = sqrt(x * x + y * y + z * z);
-            n0 = x / r; n1 = y / r; n2 = z / r;
+            n0 = C->du[I]; n1 = C->du[nu + I]; n2 = C->du[2 * nu + I];
         }
         C->nrm[I] = n0; C->nrm[nu + I] = n1; C->nrm[2 * nu + I] = n2;
         C->isbnd[I] = 1;
@@ -511,6 +549,7 @@ void or_destroy(or_ctx *C)
     if (!C) return;
     free(C->G); free(C->xl); free(C->xu); free(C->met); free(C->M); free(C->ref);
     free(C->grav); free(C->nrm); free(C->isbnd); free(C->off); free(C->cp);
+    free(C->dl); free(C->hl); free(C->du); free(C->hu);
     free(C);
 }
 
@@ -536,6 +575,12 @@ or_ctx *or_create(const or_mesh_desc *d, const or_phys *ph)
     C->isbnd = (int32_t *)malloc(sizeof(int32_t) * C->nu);
     C->off = (int64_t *)malloc(sizeof(int64_t) * (C->nu + 1));
     C->cp = (int64_t *)malloc(sizeof(int64_t) * C->nl);
+    if (d->kind == 1) {
+        C->dl = (double *)malloc(sizeof(double) * 3 * C->nl);
+        C->hl = (double *)malloc(sizeof(double) * C->nl);
+        C->du = (double *)malloc(sizeof(double) * 3 * C->nu);
+        C->hu = (double *)malloc(sizeof(double) * C->nu);
+    }
     build_numbering(C);
     build_inverse(C);
     if (build_metric(C)) { or_destroy(C); return NULL; }
@@ -615,18 +660,19 @@ int or_init_state(const or_ctx *C, const or_ic_desc *ic, const double *noise, do
             double r = sqrt(dx * dx + dy * dy + dz * dz);
             if (r < ic->radius) tp = ic->amp * (1.0 + cos(OR_PI * r / ic->radius)) / 2.0;
         } else if (ic->kind == 2) {
+            /* zonal jet and a gaussian blob at great-circle distance d (haversine form) */
             double a = C->m.extent[0];
-            double r = sqrt(x * x + y * y + z * z);
-            double lon = atan2(y, x), lat = asin(z / r);
+            double dx0 = C->du[I], dy0 = C->du[nu + I], dz0 = C->du[2 * nu + I];
+            double lon = atan2(dy0, dx0), lat = asin(dz0);
             double cl = cos(lat);
             u = ic->jet_u0 * cl * cl * (-sin(lon));
             v = ic->jet_u0 * cl * cl * cos(lon);
             w = 0.0;
-            double cs = sin(lat) * sin(ic->c[1]) + cos(lat) * cos(ic->c[1]) * cos(lon - ic->c[0]);
-            if (cs > 1.0) cs = 1.0;
-            if (cs < -1.0) cs = -1.0;
-            double dist = a * acos(cs);
-            double hz = (r - a - ic->c[2]) / ic->lz;
+            double s1 = sin(0.5 * (lat - ic->c[1])), s2 = sin(0.5 * (lon - ic->c[0]));
+            double hv = s1 * s1 + cos(lat) * cos(ic->c[1]) * s2 * s2;
+            if (hv > 1.0) hv = 1.0;
+            double dist = 2.0 * a * asin(sqrt(hv));
+            double hz = (C->hu[I] - ic->c[2]) / ic->lz;
             double hd = dist / ic->radius;
             tp = ic->amp * exp(-hd * hd - hz * hz);
         }
@@ -659,7 +705,7 @@ int or_init_state(const or_ctx *C, const or_ic_desc *ic, const double *noise, do
  *   rho u, rho v, rho w, u, v, w, theta', p'  (and theta_bar on the shell).
  * Output: C[v][e][l] = J w_ijk R_v at every element-local node.
  */
-int or_rhs(const or_ctx *C, const double *q, double *Cout)
+static int rhs_impl(const or_ctx *C, const double *q, double *Cout, int scale)
 {
     int P = C->P, np = C->np;
     int64_t nu = C->nu, nl = C->nl;
@@ -708,18 +754,34 @@ int or_rhs(const or_ctx *C, const double *q, double *Cout)
                     double u = U[0][l], v = U[1][l], w = U[2][l];
                     double b = rp[l] / rho[l];
                     double R[5];
-                    R[0] = -(dx[0] + dy[1] + dz[2]);
-                    R[1] = -(u * dx[3] + v * dy[3] + w * dz[3]) - dx[7] / rho[l] + b * gv[0][l];
-                    R[2] = -(u * dx[4] + v * dy[4] + w * dz[4]) - dy[7] / rho[l] + b * gv[1][l];
-                    R[3] = -(u * dx[5] + v * dy[5] + w * dz[5]) - dz[7] / rho[l] + b * gv[2][l];
-                    R[4] = -(u * dx[6] + v * dy[6] + w * dz[6]);
-                    if (C->dtheta) R[4] -= u * dx[8] + v * dy[8] + w * dz[8];
+                    if (!scale) {
+                        R[0] = -(dx[0] + dy[1] + dz[2]);
+                        R[1] = -(u * dx[3] + v * dy[3] + w * dz[3]) - dx[7] / rho[l] + b * gv[0][l];
+                        R[2] = -(u * dx[4] + v * dy[4] + w * dz[4]) - dy[7] / rho[l] + b * gv[1][l];
+                        R[3] = -(u * dx[5] + v * dy[5] + w * dz[5]) - dz[7] / rho[l] + b * gv[2][l];
+                        R[4] = -(u * dx[6] + v * dy[6] + w * dz[6]);
+                        if (C->dtheta) R[4] -= u * dx[8] + v * dy[8] + w * dz[8];
+                    } else {
+                        /* magnitudes of the individual terms: the scale that rounding acts on */
+                        R[0] = fabs(dx[0]) + fabs(dy[1]) + fabs(dz[2]);
+                        R[1] = fabs(u * dx[3]) + fabs(v * dy[3]) + fabs(w * dz[3]) + fabs(dx[7] / rho[l]) + fabs(b * gv[0][l]);
+                        R[2] = fabs(u * dx[4]) + fabs(v * dy[4]) + fabs(w * dz[4]) + fabs(dy[7] / rho[l]) + fabs(b * gv[1][l]);
+                        R[3] = fabs(u * dx[5]) + fabs(v * dy[5]) + fabs(w * dz[5]) + fabs(dz[7] / rho[l]) + fabs(b * gv[2][l]);
+                        R[4] = fabs(u * dx[6]) + fabs(v * dy[6]) + fabs(w * dz[6]);
+                        if (C->dtheta) R[4] += fabs(u * dx[8]) + fabs(v * dy[8]) + fabs(w * dz[8]);
+                    }
                     double Jw = C->met[9 * nl + g];
                     for (int s = 0; s < 5; s++) Cout[s * nl + g] = Jw * R[s];
                 }
     }
     return 0;
 }
+
+int or_rhs(const or_ctx *C, const double *q, double *Cout) { return rhs_impl(C, q, Cout, 0); }
+
+/* J w times the sum of the magnitudes of the individual terms of each R
+ * (same layout as or_rhs): the conditioning scale of a near-cancelled R. */
+int or_rhs_scale(const or_ctx *C, const double *q, double *Cout) { return rhs_impl(C, q, Cout, 1); }
 
 /*
  * Direct stiffness summation (text after Eq. (derivatives)): sum the element

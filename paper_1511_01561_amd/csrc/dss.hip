@@ -1,0 +1,145 @@
+// Direct stiffness summation, mass-matrix inverse, no-flux projection and the
+// SSP-RK3 stage update (the pointwise part of each stage in Code example 1:
+// "DSS and multiply with inverse mass matrix", "update q").
+//
+// The summation is a gather over the inverse of the element -> unique map:
+// each unique node sums its element-local copies in ascending order.  No
+// atomics, no colouring and no barriers are needed, and the result does not
+// depend on scheduling (the paper avoids atomics by re-ordering elements and
+// adding barriers; a gather removes the race altogether).
+#include "numa_internal.h"
+
+namespace numa {
+namespace {
+
+struct PointArgs {
+    const int32_t *off, *idx;
+    const double *Minv, *nrm;
+    int64_t nl, nu, nh;
+    int walls;
+};
+
+PointArgs point_args(const Mesh &m)
+{
+    PointArgs p;
+    p.off = m.dv.off;
+    p.idx = m.dv.idx;
+    p.Minv = m.dv.Minv;
+    p.nrm = m.dv.nrm;
+    p.nl = m.nl;
+    p.nu = m.nu;
+    p.nh = m.nh;
+    p.walls = m.walls ? 1 : 0;
+    return p;
+}
+
+// remove the wall-normal component of (r1, r2, r3) at bottom/top nodes
+__device__ inline void noflux(const PointArgs &p, int64_t I, double &r1, double &r2, double &r3)
+{
+    if (!p.walls) return;
+    int side;
+    int64_t h;
+    if (I < p.nh) { side = 0; h = I; }
+    else if (I >= p.nu - p.nh) { side = 1; h = I - (p.nu - p.nh); }
+    else return;
+    const double *n = p.nrm + side * 3 * p.nh + h;
+    double n0 = n[0], n1 = n[p.nh], n2 = n[2 * p.nh];
+    double dn = r1 * n0 + r2 * n1 + r3 * n2;
+    r1 -= dn * n0;
+    r2 -= dn * n1;
+    r3 -= dn * n2;
+}
+
+__global__ void k_dss(PointArgs p, int nvar, const double *cin, double *out, int flags)
+{
+    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= p.nu) return;
+    const int32_t b = p.off[I], en = p.off[I + 1];
+    double r[5] = {0, 0, 0, 0, 0};
+    const bool mass = flags & NUMA_DSS_MASS;
+    const double mi = mass ? p.Minv[I] : 1.0;
+    for (int v0 = 0; v0 < nvar; v0 += 5) {
+        int nv = nvar - v0 < 5 ? nvar - v0 : 5;
+        for (int v = 0; v < nv; ++v) r[v] = 0.0;
+        for (int32_t c = b; c < en; ++c) {
+            int64_t cc = p.idx[c];
+            for (int v = 0; v < nv; ++v) r[v] += cin[(v0 + v) * p.nl + cc];
+        }
+        if (mass)
+            for (int v = 0; v < nv; ++v) r[v] *= mi;
+        if ((flags & NUMA_DSS_NOFLUX) && nvar == 5) noflux(p, I, r[1], r[2], r[3]);
+        for (int v = 0; v < nv; ++v) out[(v0 + v) * p.nu + I] = r[v];
+    }
+}
+
+__device__ inline double rk_combine(int stage, double qn, double y)
+{
+    if (stage == 0) return y;
+    if (stage == 1) return 0.75 * qn + 0.25 * y;
+    return (1.0 / 3.0) * qn + (2.0 / 3.0) * y;
+}
+
+__global__ void k_rk_stage(int64_t n, int stage, double dt, const double *qn, const double *qs,
+                           const double *r, double *qout)
+{
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= n) return;
+    double y = qs[a] + dt * r[a];
+    qout[a] = rk_combine(stage, stage == 0 ? 0.0 : qn[a], y);
+}
+
+// DSS (mass-weighted) + no-flux + stage update for all five variables of one
+// unique node; qout may alias qs or qn (each node is read then written by one lane).
+__global__ void k_finish(PointArgs p, int stage, double dt, const double *qn, const double *qs,
+                         const double *evec, double *qout)
+{
+    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= p.nu) return;
+    const int32_t b = p.off[I], en = p.off[I + 1];
+    double r[5] = {0, 0, 0, 0, 0};
+    for (int32_t c = b; c < en; ++c) {
+        int64_t cc = p.idx[c];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) r[v] += evec[v * p.nl + cc];
+    }
+    const double mi = p.Minv[I];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) r[v] *= mi;
+    noflux(p, I, r[1], r[2], r[3]);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        double y = qs[v * p.nu + I] + dt * r[v];
+        qout[v * p.nu + I] = rk_combine(stage, stage == 0 ? 0.0 : qn[v * p.nu + I], y);
+    }
+}
+
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+int32_t launch_dss(Mesh &m, int32_t nvar, const double *cin, double *out, int32_t flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dss, dim3(nblocks(m.nu, 256)), dim3(256), 0, s, point_args(m), nvar, cin, out, flags);
+    NUMA_HIP(hipGetLastError());
+    return NUMA_OK;
+}
+
+int32_t launch_rk_stage(Mesh &m, int32_t stage, double dt, const double *qn, const double *qs, const double *r,
+                        double *qout, hipStream_t s)
+{
+    int64_t n = 5 * m.nu;
+    hipLaunchKernelGGL(k_rk_stage, dim3(nblocks(n, 256)), dim3(256), 0, s, n, stage, dt, qn, qs, r, qout);
+    NUMA_HIP(hipGetLastError());
+    return NUMA_OK;
+}
+
+int32_t launch_finish(Mesh &m, int32_t stage, double dt, const double *qn, const double *qs, const double *evec,
+                      double *qout, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finish, dim3(nblocks(m.nu, 256)), dim3(256), 0, s, point_args(m), stage, dt, qn, qs, evec,
+                       qout);
+    NUMA_HIP(hipGetLastError());
+    return NUMA_OK;
+}
+
+}  // namespace numa

@@ -1,0 +1,89 @@
+// Internal declarations of libnuma: the host mesh, the workspace layout and
+// the kernel-launch entry points shared by the HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "numa.h"
+
+namespace numa {
+
+constexpr int kMaxP = 9;  // N <= 8
+
+void set_error(const char *fmt, ...);
+
+// Returns NUMA_EDEVICE (with the message recorded) if a HIP call failed.
+#define NUMA_HIP(call)                                                                        \
+    do {                                                                                      \
+        hipError_t _e = (call);                                                               \
+        if (_e != hipSuccess) {                                                               \
+            ::numa::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(_e), __FILE__, \
+                              __LINE__);                                                      \
+            return NUMA_EDEVICE;                                                              \
+        }                                                                                     \
+    } while (0)
+
+// Device pointers into the caller's workspace.
+struct DeviceView {
+    int32_t *G = nullptr;      // [n_elem][np] gather map
+    int32_t *off = nullptr;    // [n_unique+1] inverse map offsets
+    int32_t *idx = nullptr;    // [n_local] copies (e*np + l), ascending per unique node
+    int32_t *hlat = nullptr;   // shell: [n_horiz][3] surface lattice of each horizontal node
+    double *met = nullptr;     // [n_elem][10][np] inverse metric (9) and J w
+    float *met32 = nullptr;    // same, FP32 (mixed path)
+    double *ref = nullptr;     // [3][n_unique] rho_bar, theta_bar, p_bar
+    double *M = nullptr;       // [n_unique]
+    double *Minv = nullptr;    // [n_unique]
+    double *grav = nullptr;    // shell: [3][n_unique]
+    double *nrm = nullptr;     // [2][3][n_horiz] bottom and top wall normals
+    double *xu = nullptr;      // [3][n_unique] unique coordinates
+    double *evec = nullptr;    // [5][n_local] element-local scratch (E-vector)
+    double *qs = nullptr;      // [5][n_unique] stage state scratch
+    double *D64 = nullptr;     // [(N+1)^2] derivative matrix
+    float *D32 = nullptr;      // same, FP32
+};
+
+struct Mesh {
+    numa_mesh_desc d{};
+    int N = 0, P = 0, np = 0;
+    int64_t ne = 0, nl = 0, nu = 0, nh = 0, nk = 0;
+    int64_t ni = 0, nj = 0;  // box lattice extents
+    bool walls = false;      // no-flux bottom and top
+    double xi[kMaxP]{}, w[kMaxP]{}, D[kMaxP * kMaxP]{};
+    std::vector<int32_t> G, off, idx, hlat;
+    std::vector<float> D32;
+    // workspace
+    char *ws = nullptr;
+    uint64_t ws_bytes = 0;
+    int32_t prec_mask = 0;
+    DeviceView dv;
+    bool uploaded = false, geom = false;
+    numa_phys ph{};
+    double gamma = 0.0;
+};
+
+// Host GLL (nodes, weights, derivative matrix); returns false for bad order.
+bool gll(int N, double *xi, double *w, double *D);
+
+// Host mesh construction (numbering, gather map, inverse map).
+int32_t build_mesh(Mesh &m);
+
+// Workspace layout: computes byte offsets, fills dv when base != nullptr.
+uint64_t layout_workspace(Mesh &m, int32_t prec_mask, char *base);
+
+// Kernel launchers (return NUMA_OK or NUMA_EDEVICE).
+int32_t launch_geometry(Mesh &m, hipStream_t s);
+int32_t launch_export(Mesh &m, int32_t what, void *out, hipStream_t s);
+int32_t launch_init_state(Mesh &m, const numa_ic &ic, const double *noise, double *q, hipStream_t s);
+int32_t launch_rhs(Mesh &m, int32_t prec, const double *q, double *evec, hipStream_t s);
+int32_t launch_dss(Mesh &m, int32_t nvar, const double *cin, double *out, int32_t flags, hipStream_t s);
+int32_t launch_rk_stage(Mesh &m, int32_t stage, double dt, const double *qn, const double *qs,
+                        const double *r, double *qout, hipStream_t s);
+int32_t launch_finish(Mesh &m, int32_t stage, double dt, const double *qn, const double *qs,
+                      const double *evec, double *qout, hipStream_t s);
+
+}  // namespace numa

@@ -1,0 +1,207 @@
+"""Thin ctypes binding of libnuma (include/numa.h), same names as the C ABI.
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  torch supplies device memory (the workspace and the state tensors)
+and the stream (torch.cuda.current_stream()).  If libnuma.so has not been
+built, loading fails with an error; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnuma.so")
+
+NUMA_OK = 0
+MESH_BOX, MESH_SHELL = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+DSS_MASS, DSS_NOFLUX = 1, 2
+FIELD_MASS, FIELD_REF, FIELD_COORDS, FIELD_METRIC, FIELD_GRAVITY, FIELD_LOCAL_COORDS = range(6)
+
+EXPORTED = ["numa_last_error", "numa_gll", "numa_mesh_create", "numa_mesh_destroy", "numa_mesh_info",
+            "numa_mesh_gather_map", "numa_mesh_workspace_bytes", "numa_mesh_attach_workspace",
+            "numa_geometry", "numa_export", "numa_init_state", "numa_rhs", "numa_dss",
+            "numa_rk_stage", "numa_step"]
+
+
+class numa_mesh_desc(ct.Structure):
+    _fields_ = [("kind", ct.c_int32), ("order", ct.c_int32), ("ne", ct.c_int32 * 3),
+                ("periodic", ct.c_int32 * 3), ("extent", ct.c_double * 3), ("terrain_amp", ct.c_double)]
+
+
+class numa_phys(ct.Structure):
+    _fields_ = [("R", ct.c_double), ("cp", ct.c_double), ("g0", ct.c_double), ("p0", ct.c_double),
+                ("T0", ct.c_double)]
+
+
+class numa_ic(ct.Structure):
+    _fields_ = [("kind", ct.c_int32), ("amp", ct.c_double), ("radius", ct.c_double), ("c", ct.c_double * 3),
+                ("lz", ct.c_double), ("jet_u0", ct.c_double), ("noise_amp", ct.c_double)]
+
+
+class NumaError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libnuma.so (built in-tree by paper_1511_01561_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise NumaError("libnuma.so is not built (run python -m paper_1511_01561_amd.build); "
+                        "there is no CPU fallback")
+    L = ct.CDLL(LIB_PATH)
+    P, I32, I64, D = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_double
+    sig = {
+        "numa_last_error": (ct.c_char_p, []),
+        "numa_gll": (I32, [I32, P, P, P]),
+        "numa_mesh_create": (I32, [ct.POINTER(numa_mesh_desc), ct.POINTER(P)]),
+        "numa_mesh_destroy": (I32, [P]),
+        "numa_mesh_info": (I32, [P, P, P, P, P, P]),
+        "numa_mesh_gather_map": (I32, [P, P]),
+        "numa_mesh_workspace_bytes": (I32, [P, I32, ct.POINTER(ct.c_uint64)]),
+        "numa_mesh_attach_workspace": (I32, [P, P, ct.c_uint64, I32]),
+        "numa_geometry": (I32, [P, ct.POINTER(numa_phys), P]),
+        "numa_export": (I32, [P, I32, P, P]),
+        "numa_init_state": (I32, [P, ct.POINTER(numa_ic), P, P, P]),
+        "numa_rhs": (I32, [P, I32, P, P, P]),
+        "numa_dss": (I32, [P, I32, P, P, I32, P]),
+        "numa_rk_stage": (I32, [P, I32, D, P, P, P, P, P]),
+        "numa_step": (I32, [P, I32, D, I32, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def check(rc: int) -> None:
+    if rc != NUMA_OK:
+        raise NumaError("libnuma error %d: %s" % (rc, lib().numa_last_error().decode()))
+
+
+def numa_gll(order: int):
+    import numpy as np
+    xi = np.zeros(order + 1); w = np.zeros(order + 1); D = np.zeros((order + 1, order + 1))
+    check(lib().numa_gll(order, xi.ctypes.data, w.ctypes.data, D.ctypes.data))
+    return xi, w, D
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ct.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous() and t.dtype.is_floating_point, "device FP64 contiguous tensor expected"
+    return ct.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """A mesh handle with its device workspace (a torch uint8 tensor)."""
+
+    def __init__(self, mesh: dict, phys: dict, prec_mask: int = 3, device="cuda:0", stream=None):
+        import torch
+        self.device = torch.device(device)
+        d = numa_mesh_desc()
+        d.kind = int(mesh["kind"]); d.order = int(mesh["N"])
+        for a in range(3):
+            d.ne[a] = int(mesh["ne"][a]); d.periodic[a] = int(mesh["periodic"][a])
+            d.extent[a] = float(mesh["extent"][a])
+        d.terrain_amp = float(mesh.get("h0", 0.0))
+        self._desc = d
+        h = ct.c_void_p()
+        check(lib().numa_mesh_create(ct.byref(d), ct.byref(h)))
+        self._h = h
+        vals = [ct.c_int64() for _ in range(5)]
+        check(lib().numa_mesh_info(h, *[ct.byref(v) for v in vals]))
+        self.n_elem, self.n_local, self.n_unique, self.n_horiz, self.n_levels = (v.value for v in vals)
+        self.N = d.order
+        self.np = (self.N + 1) ** 3
+        nb = ct.c_uint64()
+        check(lib().numa_mesh_workspace_bytes(h, prec_mask, ct.byref(nb)))
+        self.workspace_bytes = nb.value
+        self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        check(lib().numa_mesh_attach_workspace(h, ct.c_void_p(base + off), nb.value, prec_mask))
+        ph = numa_phys()
+        for k in ("R", "cp", "g0", "p0", "T0"):
+            setattr(ph, k, float(phys[k]))
+        self._phys = ph
+        check(lib().numa_geometry(h, ct.byref(ph), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.numa_mesh_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    # -- host -----------------------------------------------------------------
+    def gather_map(self):
+        import numpy as np
+        out = np.zeros((self.n_elem, self.np), dtype=np.int32)
+        check(lib().numa_mesh_gather_map(self._h, out.ctypes.data))
+        return out
+
+    # -- device ---------------------------------------------------------------
+    def _empty(self, *shape):
+        import torch
+        return torch.empty(*shape, dtype=torch.float64, device=self.device)
+
+    def export(self, what: int, stream=None):
+        nu, nl = self.n_unique, self.n_local
+        shape = {FIELD_MASS: (nu,), FIELD_REF: (3, nu), FIELD_COORDS: (3, nu), FIELD_METRIC: (10, nl),
+                 FIELD_GRAVITY: (3, nu), FIELD_LOCAL_COORDS: (3, nl)}[what]
+        out = self._empty(*shape)
+        check(lib().numa_export(self._h, what, _ptr(out), _stream(stream)))
+        return out
+
+    def init_state(self, ic: dict, noise=None, stream=None):
+        d = numa_ic()
+        d.kind = int(ic.get("kind", 0)); d.amp = float(ic.get("amp", 0.0)); d.radius = float(ic.get("radius", 1.0))
+        c = ic.get("centre", (0.0, 0.0, 0.0))
+        for a in range(3):
+            d.c[a] = float(c[a])
+        d.lz = float(ic.get("lz", 1.0)); d.jet_u0 = float(ic.get("jet_u0", 0.0))
+        d.noise_amp = float(ic.get("noise_amp", 0.0))
+        q = self._empty(5, self.n_unique)
+        check(lib().numa_init_state(self._h, ct.byref(d), _ptr(noise), _ptr(q), _stream(stream)))
+        return q
+
+    def rhs(self, q, prec=PREC_FP64, out=None, stream=None):
+        if out is None:
+            out = self._empty(5, self.n_local)
+        check(lib().numa_rhs(self._h, prec, _ptr(q), _ptr(out), _stream(stream)))
+        return out
+
+    def dss(self, c_elem, flags=DSS_MASS, out=None, stream=None):
+        nvar = c_elem.numel() // self.n_local
+        if out is None:
+            out = self._empty(nvar, self.n_unique)
+        check(lib().numa_dss(self._h, nvar, _ptr(c_elem), _ptr(out), flags, _stream(stream)))
+        return out
+
+    def rk_stage(self, stage, dt, qn, qs, r, out=None, stream=None):
+        if out is None:
+            out = self._empty(5, self.n_unique)
+        check(lib().numa_rk_stage(self._h, stage, float(dt), _ptr(qn), _ptr(qs), _ptr(r), _ptr(out),
+                                  _stream(stream)))
+        return out
+
+    def step(self, q, dt, nsteps, prec=PREC_FP64, stream=None):
+        """nsteps SSP-RK3 steps in place on q (device [5][n_unique] FP64)."""
+        check(lib().numa_step(self._h, prec, float(dt), int(nsteps), _ptr(q), _stream(stream)))
+        return q
