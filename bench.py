@@ -23,7 +23,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = {
-    "rhs": os.path.join(ROOT, "paper_1511_01561_amd", "csrc", "rhs.hip"),
+    "stage": os.path.join(ROOT, "paper_1511_01561_amd", "csrc", "rhs.hip"),
 }
 
 
@@ -36,13 +36,24 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def algorithmic_bytes_rhs(nu, nl, prec):
-    """Minimum HBM bytes of one element-RHS launch: the unique state (5 x 8 B)
-    and reference (3 x 8 B) read once, the gather map (4 B), metric terms and
-    J w (10 x 8 B, or 10 x 4 B mixed) per element-local node, and the
-    element-local contributions written once (5 x 8 B per element-local node)."""
-    met = 40 if prec == "mixed" else 80
-    return nu * (40 + 24) + nl * (4 + met + 40)
+def element_bytes(nu, nl, prec):
+    """Algorithmic HBM bytes of one launch of the element kernel of a fused
+    stage: the unique state (5 x 8 B) and reference (3 x 8 B) read once; per
+    element-local node the gather map (4 B), the metric terms with J w
+    (10 x 8 B, or 10 x 4 B mixed) and the contribution written once
+    (5 x 8 B, or 5 x 4 B mixed)."""
+    met, contrib = (40, 20) if prec == "mixed" else (80, 40)
+    return nu * (40 + 24) + nl * (4 + met + contrib)
+
+
+def finish_bytes(nu, nl, n_wall, prec):
+    """Algorithmic bytes of one finish launch (averaged over the 3 stages):
+    the node order (4 B) and copy offsets (8 B) per unique node, the copy list
+    (4 B) and contribution (5 x 8 B or 5 x 4 B) per element-local node, M^-1
+    (8 B), the stage state, q^n (2 of 3 stages) and the new state (5 x 8 B
+    each) per unique node, and the wall normals."""
+    contrib = 20 if prec == "mixed" else 40
+    return nu * (4 + 8 + 8 + 40 + 40 * 2.0 / 3.0 + 40) + nl * (4 + contrib) + n_wall * 24
 
 
 def load_traffic(kernel, workload):
@@ -90,8 +101,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--rhs-launches", type=int, default=30)
     ap.add_argument("--small", action="store_true", help="4x4x4 box instead of the one-GPU workload")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
@@ -143,26 +155,48 @@ def main():
                      speedup_vs_fp64=wall_s / mw, dtype="f32 contractions / f64 state")
         _log("mixed: %.3f ms/step, speedup %.2f" % (mixed["ms_per_step"], mixed["speedup_vs_fp64"]))
 
-    # dominant kernel alone, same launch configuration as inside the step,
-    # timed with events on the stream it is launched on
-    evec = torch.empty(5, g.n_local, dtype=torch.float64, device="cuda:0")
-    for _ in range(3):
-        g.rhs(q0, out=evec)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.rhs_launches):
-        g.rhs(q0, out=evec)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    rhs_s = e0.elapsed_time(e1) / 1e3 / args.rhs_launches
-    alg = algorithmic_bytes_rhs(g.n_unique, g.n_local, "fp64")
-    achieved = alg / rhs_s / 1e9
-    _log("rhs kernel: %.1f us/launch, %.0f GB/s algorithmic" % (rhs_s * 1e6, achieved))
-    traffic = load_traffic("rhs", workload)
-    roofline = dict(kernel="k_rhs<4,double>", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+    # the dominant kernel: per-launch durations of the two stage kernels from
+    # HIP events the library records on the stream it launches them on
+    n_wall = 0 if mm["periodic"][2] else 2 * g.n_horiz
+    prof = {}
+    for prec, name in ((numa.PREC_FP64, "fp64"), (numa.PREC_MIXED, "mixed")):
+        if name == "mixed" and args.no_mixed:
+            continue
+        q = q0.clone()
+        g.step(q, dt, 1, prec=prec)
+        torch.cuda.synchronize()
+        g.profile(True)
+        g.step(q, dt, args.steps, prec=prec)
+        el_ms, el_n, fin_ms, fin_n = g.profile_read()
+        g.profile(False)
+        prof[name] = (el_ms / el_n * 1e-3, fin_ms / fin_n * 1e-3)
+        _log("%s stage kernels: element %.1f us, finish %.1f us per launch"
+             % (name, prof[name][0] * 1e6, prof[name][1] * 1e6))
+    el_s, fin_s = prof["fp64"]
+    alg = element_bytes(g.n_unique, g.n_local, "fp64")
+    achieved = alg / el_s / 1e9
+    fin_alg = finish_bytes(g.n_unique, g.n_local, n_wall, "fp64")
+    _log("element kernel %.0f GB/s algorithmic; finish kernel %.0f GB/s" % (achieved, fin_alg / fin_s / 1e9))
+    traffic = load_traffic("stage", workload)
+    roofline = dict(kernel="k_rhs<4,double> (element kernel of the fused stage)", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=achieved / HBM_PEAK_GBS, traffic=traffic, algorithmic_bytes=alg,
-                    avg_launch_us=rhs_s * 1e6)
+                    avg_launch_us=el_s * 1e6,
+                    finish_kernel=dict(avg_launch_us=fin_s * 1e6, algorithmic_bytes=fin_alg,
+                                       achieved=fin_alg / fin_s / 1e9))
+    if "mixed" in prof and mixed is not None:
+        malg = element_bytes(g.n_unique, g.n_local, "mixed")
+        mixed["element_kernel"] = dict(avg_launch_us=prof["mixed"][0] * 1e6, algorithmic_bytes=malg,
+                                       achieved=malg / prof["mixed"][0] / 1e9)
+
+    if args.copy_probe:
+        n = args.copy_probe * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        _log("copy probe: 3 x %d MiB device copies" % args.copy_probe)
+        del src, dst
 
     cpu = None
     if not args.no_cpu:

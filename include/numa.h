@@ -168,10 +168,23 @@ int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn,
                       const double *r, double *qout, void *stream);
 
 /* nsteps SSP-RK3 steps in place on q [5][n_unique] (device), each stage being
- * rhs -> DSS (mass, no-flux) -> stage update, fused into the library's stage
- * kernels.  Uses the workspace scratch; equals the composition of numa_rhs,
- * numa_dss and numa_rk_stage up to rounding. */
+ * rhs -> DSS (mass, no-flux) -> stage update, fused into two kernels: the
+ * element kernel updates nodes that have a single copy and stores the other
+ * copies' contributions by unique node; the finish kernel sums them in
+ * ascending element-local order (the order of numa_dss), applies M^-1, the
+ * wall projection and the update.  Uses the workspace scratch; equals the
+ * composition of numa_rhs, numa_dss and numa_rk_stage up to rounding.
+ * The stream must not run other work on q or the workspace meanwhile. */
 int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double *q, void *stream);
+
+/* Per-kernel timing of numa_step: while enabled, numa_step records HIP events
+ * on the caller's stream around each launch of its two stage kernels (the
+ * element kernel and the DSS/update finish).  numa_profile(m, 1) starts a new
+ * accumulation, numa_profile(m, 0) stops recording.  numa_profile_read waits
+ * for the recorded events and writes out[0] = total element-kernel ms,
+ * out[1] = its launches, out[2] = total finish ms, out[3] = its launches. */
+int32_t numa_profile(numa_mesh_t m, int32_t enable);
+int32_t numa_profile_read(numa_mesh_t m, double *out);
 
 #ifdef __cplusplus
 }

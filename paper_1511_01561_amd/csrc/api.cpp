@@ -106,6 +106,8 @@ int32_t numa_mesh_create(const numa_mesh_desc *d, numa_mesh_t *out)
 
 int32_t numa_mesh_destroy(numa_mesh_t m)
 {
+    if (m)
+        for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
     delete m;
     return NUMA_OK;
 }
@@ -276,6 +278,32 @@ int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn,
     return numa::launch_rk_stage(*m, stage, dt, qn, qs, r, qout, as_stream(stream));
 }
 
+// one fused stage: element kernel then finish kernel, optionally bracketed by events
+static int32_t run_stage(numa_mesh_t m, int32_t prec, int32_t stage, double dt, const double *qn, const double *qs,
+                         double *qout, hipStream_t s)
+{
+    int32_t rc;
+    auto mark = [&](std::vector<std::pair<int, int>> &log, bool begin) -> int32_t {
+        if (!m->profiling) return NUMA_OK;
+        if (m->ev_used == m->ev_pool.size()) {
+            hipEvent_t e;
+            NUMA_HIP(hipEventCreate(&e));
+            m->ev_pool.push_back(e);
+        }
+        int id = (int)m->ev_used++;
+        NUMA_HIP(hipEventRecord(m->ev_pool[id], s));
+        if (begin) log.push_back({id, -1});
+        else log.back().second = id;
+        return NUMA_OK;
+    };
+    if ((rc = mark(m->ev_elem, true))) return rc;
+    if ((rc = numa::launch_stage_elements(*m, prec, stage, dt, qn, qs, qout, s))) return rc;
+    if ((rc = mark(m->ev_elem, false))) return rc;
+    if ((rc = mark(m->ev_fin, true))) return rc;
+    if ((rc = numa::launch_stage_finish(*m, prec, stage, dt, qn, qs, qout, s))) return rc;
+    return mark(m->ev_fin, false);
+}
+
 int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double *q, void *stream)
 {
     int32_t rc = need_ready(m, "numa_step");
@@ -286,14 +314,48 @@ int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double
         return NUMA_EINVAL;
     }
     hipStream_t s = as_stream(stream);
-    double *qs = m->dv.qs, *ev = m->dv.evec;
+    double *qs = m->dv.qs;
     for (int n = 0; n < nsteps; ++n) {
-        if ((rc = numa::launch_rhs(*m, prec, q, ev, s))) return rc;
-        if ((rc = numa::launch_finish(*m, 0, dt, q, q, ev, qs, s))) return rc;
-        if ((rc = numa::launch_rhs(*m, prec, qs, ev, s))) return rc;
-        if ((rc = numa::launch_finish(*m, 1, dt, q, qs, ev, qs, s))) return rc;
-        if ((rc = numa::launch_rhs(*m, prec, qs, ev, s))) return rc;
-        if ((rc = numa::launch_finish(*m, 2, dt, q, qs, ev, q, s))) return rc;
+        if ((rc = run_stage(m, prec, 0, dt, q, q, qs, s))) return rc;
+        if ((rc = run_stage(m, prec, 1, dt, q, qs, qs, s))) return rc;
+        if ((rc = run_stage(m, prec, 2, dt, q, qs, q, s))) return rc;
+    }
+    return NUMA_OK;
+}
+
+int32_t numa_profile(numa_mesh_t m, int32_t enable)
+{
+    if (!m) {
+        set_error("numa_profile: null mesh handle");
+        return NUMA_EINVAL;
+    }
+    m->profiling = enable != 0;
+    m->ev_elem.clear();
+    m->ev_fin.clear();
+    m->ev_used = 0;
+    return NUMA_OK;
+}
+
+int32_t numa_profile_read(numa_mesh_t m, double *out)
+{
+    if (!m || !out) {
+        set_error("numa_profile_read: null argument");
+        return NUMA_EINVAL;
+    }
+    const std::vector<std::pair<int, int>> *logs[2] = {&m->ev_elem, &m->ev_fin};
+    for (int k = 0; k < 2; ++k) {
+        double total = 0.0;
+        int n = 0;
+        for (auto &pr : *logs[k]) {
+            if (pr.second < 0) continue;
+            NUMA_HIP(hipEventSynchronize(m->ev_pool[pr.second]));
+            float ms = 0.0f;
+            NUMA_HIP(hipEventElapsedTime(&ms, m->ev_pool[pr.first], m->ev_pool[pr.second]));
+            total += ms;
+            ++n;
+        }
+        out[2 * k] = total;
+        out[2 * k + 1] = n;
     }
     return NUMA_OK;
 }

@@ -52,7 +52,7 @@ __device__ inline void noflux(const PointArgs &p, int64_t I, double &r1, double 
 
 __global__ void k_dss(PointArgs p, int nvar, const double *cin, double *out, int flags)
 {
-    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t I = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (I >= p.nu) return;
     const int32_t b = p.off[I], en = p.off[I + 1];
     double r[5] = {0, 0, 0, 0, 0};
@@ -88,19 +88,26 @@ __global__ void k_rk_stage(int64_t n, int stage, double dt, const double *qn, co
     qout[a] = rk_combine(stage, stage == 0 ? 0.0 : qn[a], y);
 }
 
-// DSS (mass-weighted) + no-flux + stage update for all five variables of one
-// unique node; qout may alias qs or qn (each node is read then written by one lane).
-__global__ void k_finish(PointArgs p, int stage, double dt, const double *qn, const double *qs,
-                         const double *evec, double *qout)
+// Second half of a fused stage: DSS (mass-weighted), no-flux projection and
+// the stage update of every unique node.  Lanes walk the nodes in
+// first-occurrence order of the element scan (own[]), so a block gathers the
+// contributions of a few adjacent elements that its XCD has just read, and
+// its state reads and writes merge into whole cache lines across consecutive
+// blocks.  Copies are summed in ascending element-local order.  qout may alias
+// qs or qn (one lane per node).
+template <typename T>
+__global__ void k_stage_finish(PointArgs p, const int32_t *own, const int32_t *toff, const int32_t *tidx,
+                               const T *ev, int stage, double dt, const double *qn, const double *qs, double *qout)
 {
-    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= p.nu) return;
-    const int32_t b = p.off[I], en = p.off[I + 1];
+    int64_t t = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (t >= p.nu) return;
+    const int64_t I = own[t];
+    const int32_t b = toff[t], en = toff[t + 1];
     double r[5] = {0, 0, 0, 0, 0};
     for (int32_t c = b; c < en; ++c) {
-        int64_t cc = p.idx[c];
+        const int64_t cc = tidx[c];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) r[v] += evec[v * p.nl + cc];
+        for (int v = 0; v < 5; ++v) r[v] += (double)ev[v * p.nl + cc];
     }
     const double mi = p.Minv[I];
 #pragma unroll
@@ -133,11 +140,15 @@ int32_t launch_rk_stage(Mesh &m, int32_t stage, double dt, const double *qn, con
     return NUMA_OK;
 }
 
-int32_t launch_finish(Mesh &m, int32_t stage, double dt, const double *qn, const double *qs, const double *evec,
-                      double *qout, hipStream_t s)
+int32_t launch_stage_finish(Mesh &m, int32_t prec, int32_t stage, double dt, const double *qn, const double *qs,
+                            double *qout, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finish, dim3(nblocks(m.nu, 256)), dim3(256), 0, s, point_args(m), stage, dt, qn, qs, evec,
-                       qout);
+    if (prec == NUMA_PREC_MIXED)
+        hipLaunchKernelGGL(k_stage_finish<float>, dim3(nblocks(m.nu, 256)), dim3(256), 0, s, point_args(m), m.dv.own,
+                           m.dv.toff, m.dv.tidx, m.dv.ev32, stage, dt, qn, qs, qout);
+    else
+        hipLaunchKernelGGL(k_stage_finish<double>, dim3(nblocks(m.nu, 256)), dim3(256), 0, s, point_args(m), m.dv.own,
+                           m.dv.toff, m.dv.tidx, m.dv.ev64, stage, dt, qn, qs, qout);
     NUMA_HIP(hipGetLastError());
     return NUMA_OK;
 }

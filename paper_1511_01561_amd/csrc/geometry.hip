@@ -384,6 +384,9 @@ int32_t launch_geometry(Mesh &m, hipStream_t s)
         NUMA_HIP(hipMemcpyAsync(v.off, m.off.data(), 4 * (m.nu + 1), hipMemcpyHostToDevice, s));
         NUMA_HIP(hipMemcpyAsync(v.idx, m.idx.data(), 4 * m.nl, hipMemcpyHostToDevice, s));
         if (v.hlat) NUMA_HIP(hipMemcpyAsync(v.hlat, m.hlat.data(), 12 * m.nh, hipMemcpyHostToDevice, s));
+        NUMA_HIP(hipMemcpyAsync(v.own, m.own.data(), 4 * m.nu, hipMemcpyHostToDevice, s));
+        NUMA_HIP(hipMemcpyAsync(v.toff, m.toff.data(), 4 * (m.nu + 1), hipMemcpyHostToDevice, s));
+        NUMA_HIP(hipMemcpyAsync(v.tidx, m.tidx.data(), 4 * m.nl, hipMemcpyHostToDevice, s));
         m.D32.assign(m.D, m.D + m.P * m.P);
         NUMA_HIP(hipMemcpyAsync(v.D64, m.D, 8 * m.P * m.P, hipMemcpyHostToDevice, s));
         NUMA_HIP(hipMemcpyAsync(v.D32, m.D32.data(), 4 * m.P * m.P, hipMemcpyHostToDevice, s));

@@ -226,6 +226,32 @@ int32_t build_mesh(Mesh &m)
     m.idx.resize(m.nl);
     std::vector<int32_t> cur(m.off.begin(), m.off.end() - 1);
     for (int64_t c = 0; c < m.nl; ++c) m.idx[cur[m.G[c]]++] = (int32_t)c;
+    // unique ids in first-occurrence order of the element scan: grouped by the
+    // element that first touches them, which is the order the stage finish
+    // walks so that its gathers stay within a few adjacent element regions
+    m.own.resize(m.nu);
+    {
+        std::vector<uint8_t> seen(m.nu, 0);
+        int64_t n = 0;
+        for (int64_t c = 0; c < m.nl; ++c) {
+            const int32_t I = m.G[c];
+            if (!seen[I]) {
+                seen[I] = 1;
+                m.own[n++] = I;
+            }
+        }
+    }
+    // the inverse map re-indexed in that order (copies of node own[t] at
+    // tidx[toff[t] .. toff[t+1]), still ascending)
+    m.toff.resize(m.nu + 1);
+    m.tidx.resize(m.nl);
+    m.toff[0] = 0;
+    for (int64_t t = 0; t < m.nu; ++t) {
+        const int32_t I = m.own[t];
+        int32_t o = m.toff[t];
+        for (int32_t c = m.off[I]; c < m.off[I + 1]; ++c) m.tidx[o++] = m.idx[c];
+        m.toff[t + 1] = o;
+    }
     return NUMA_OK;
 }
 
@@ -252,7 +278,11 @@ uint64_t layout_workspace(Mesh &m, int32_t prec_mask, char *base)
     if (m.d.kind == NUMA_MESH_SHELL) v.grav = (double *)take(24ull * m.nu);
     v.nrm = (double *)take(48ull * m.nh);
     v.xu = (double *)take(24ull * m.nu);
-    v.evec = (double *)take(40ull * m.nl);
+    v.own = (int32_t *)take(4ull * m.nu);
+    v.toff = (int32_t *)take(4ull * (m.nu + 1));
+    v.tidx = (int32_t *)take(4ull * m.nl);
+    v.ev64 = (double *)take(40ull * m.nl);
+    if (prec_mask & 2) v.ev32 = (float *)take(20ull * m.nl);
     v.qs = (double *)take(40ull * m.nu);
     v.D64 = (double *)take(8ull * kMaxP * kMaxP);
     v.D32 = (float *)take(4ull * kMaxP * kMaxP);

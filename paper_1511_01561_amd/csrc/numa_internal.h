@@ -16,6 +16,18 @@ constexpr int kMaxP = 9;  // N <= 8
 
 void set_error(const char *fmt, ...);
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Remap the block index so that every XCD walks one contiguous range of the
+// work items (elements or unique nodes): neighbours that share cache lines are
+// then fetched once into the same L2 instead of once per XCD.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblocks)
+{
+    const int64_t q = nblocks / kXcds, r = nblocks % kXcds;
+    const int64_t x = b % kXcds, slot = b / kXcds;
+    return x * q + (x < r ? x : r) + slot;
+}
+
 // Returns NUMA_EDEVICE (with the message recorded) if a HIP call failed.
 #define NUMA_HIP(call)                                                                        \
     do {                                                                                      \
@@ -41,7 +53,11 @@ struct DeviceView {
     double *grav = nullptr;    // shell: [3][n_unique]
     double *nrm = nullptr;     // [2][3][n_horiz] bottom and top wall normals
     double *xu = nullptr;      // [3][n_unique] unique coordinates
-    double *evec = nullptr;    // [5][n_local] element-local scratch (E-vector)
+    int32_t *own = nullptr;    // [n_unique] unique ids in first-occurrence order of the element scan
+    int32_t *toff = nullptr;   // [n_unique+1] copy offsets in that order
+    int32_t *tidx = nullptr;   // [n_local] copies (e*np + l), ascending per node, in that order
+    double *ev64 = nullptr;    // [5][n_local] element contributions of a fused stage, FP64 path
+    float *ev32 = nullptr;     // same, mixed path
     double *qs = nullptr;      // [5][n_unique] stage state scratch
     double *D64 = nullptr;     // [(N+1)^2] derivative matrix
     float *D32 = nullptr;      // same, FP32
@@ -56,6 +72,12 @@ struct Mesh {
     double xi[kMaxP]{}, w[kMaxP]{}, D[kMaxP * kMaxP]{};
     std::vector<int32_t> G, off, idx, hlat;
     std::vector<float> D32;
+    std::vector<int32_t> own, toff, tidx;
+    // optional event timing of the stage kernels (numa_profile)
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> ev_elem, ev_fin;  // indices into ev_pool
+    size_t ev_used = 0;
     // workspace
     char *ws = nullptr;
     uint64_t ws_bytes = 0;
@@ -83,7 +105,9 @@ int32_t launch_rhs(Mesh &m, int32_t prec, const double *q, double *evec, hipStre
 int32_t launch_dss(Mesh &m, int32_t nvar, const double *cin, double *out, int32_t flags, hipStream_t s);
 int32_t launch_rk_stage(Mesh &m, int32_t stage, double dt, const double *qn, const double *qs,
                         const double *r, double *qout, hipStream_t s);
-int32_t launch_finish(Mesh &m, int32_t stage, double dt, const double *qn, const double *qs,
-                      const double *evec, double *qout, hipStream_t s);
+int32_t launch_stage_elements(Mesh &m, int32_t prec, int32_t stage, double dt, const double *qn, const double *qs,
+                              double *qout, hipStream_t s);
+int32_t launch_stage_finish(Mesh &m, int32_t prec, int32_t stage, double dt, const double *qn, const double *qs,
+                            double *qout, hipStream_t s);
 
 }  // namespace numa

@@ -22,7 +22,7 @@ FIELD_MASS, FIELD_REF, FIELD_COORDS, FIELD_METRIC, FIELD_GRAVITY, FIELD_LOCAL_CO
 EXPORTED = ["numa_last_error", "numa_gll", "numa_mesh_create", "numa_mesh_destroy", "numa_mesh_info",
             "numa_mesh_gather_map", "numa_mesh_workspace_bytes", "numa_mesh_attach_workspace",
             "numa_geometry", "numa_export", "numa_init_state", "numa_rhs", "numa_dss",
-            "numa_rk_stage", "numa_step"]
+            "numa_rk_stage", "numa_step", "numa_profile", "numa_profile_read"]
 
 
 class numa_mesh_desc(ct.Structure):
@@ -73,6 +73,8 @@ def lib():
         "numa_dss": (I32, [P, I32, P, P, I32, P]),
         "numa_rk_stage": (I32, [P, I32, D, P, P, P, P, P]),
         "numa_step": (I32, [P, I32, D, I32, P, P]),
+        "numa_profile": (I32, [P, I32]),
+        "numa_profile_read": (I32, [P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -200,6 +202,15 @@ class Mesh:
         check(lib().numa_rk_stage(self._h, stage, float(dt), _ptr(qn), _ptr(qs), _ptr(r), _ptr(out),
                                   _stream(stream)))
         return out
+
+    def profile(self, enable: bool):
+        check(lib().numa_profile(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(element-kernel ms total, launches, finish ms total, launches)"""
+        out = (ct.c_double * 4)()
+        check(lib().numa_profile_read(self._h, out))
+        return tuple(out)
 
     def step(self, q, dt, nsteps, prec=PREC_FP64, stream=None):
         """nsteps SSP-RK3 steps in place on q (device [5][n_unique] FP64)."""
