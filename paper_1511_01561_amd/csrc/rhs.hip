@@ -22,13 +22,28 @@ namespace {
 
 template <typename T>
 struct RhsArgs {
-    const int32_t *G;
+    const int32_t *G;  // gather map (shell); the box computes unique ids from its lattice
     const double *q, *ref, *grav;
     const T *met;
     const T *D;
     int64_t nl, nu;
     double gamma, g0;
+    int nx, ny;          // box: elements along x and y
+    int64_t ni, nj, nk;  // box: lattice extents (x, y periodic)
 };
+
+// unique id of local node (i, j, k) of box element e: the element's lattice
+// corner plus the local offset, wrapped in the periodic directions
+template <int N, typename T>
+__device__ __forceinline__ int64_t box_unique(const RhsArgs<T> &a, int64_t e, int i, int j, int k)
+{
+    const int64_t ex = e % a.nx, ey = (e / a.nx) % a.ny, ez = e / ((int64_t)a.nx * a.ny);
+    int64_t gi = ex * N + i, gj = ey * N + j, gk = ez * N + k;
+    if (gi == a.ni) gi = 0;
+    if (gj == a.nj) gj = 0;
+    if (gk == a.nk) gk = 0;
+    return gi + a.ni * (gj + a.nj * gk);
+}
 
 template <int N>
 constexpr int block_threads() { return (((N + 1) * (N + 1) * (N + 1) + 63) / 64) * 64; }
@@ -62,7 +77,12 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
         for (int c = 0; c < 10; ++c) mx[c] = mp[c * NP];
     }
     if (act) {
-        I = a.G[e * NP + l];
+        if constexpr (SHELL) {
+            I = a.G[e * NP + l];
+        } else {
+            constexpr int P_ = N + 1;
+            I = box_unique<N, T>(a, e, l % P_, (l / P_) % P_, l / (P_ * P_));
+        }
         rp = a.q[I];
         u = a.q[a.nu + I];
         v = a.q[2 * a.nu + I];
@@ -172,6 +192,11 @@ void launch_t(Mesh &m, const T *met, const T *D, const double *q, TO *out, hipSt
     a.nu = m.nu;
     a.gamma = m.gamma;
     a.g0 = m.ph.g0;
+    a.nx = m.d.ne[0];
+    a.ny = m.d.ne[1];
+    a.ni = m.ni;
+    a.nj = m.nj;
+    a.nk = m.d.periodic[2] ? m.nk : -1;  // only a periodic z wraps
     switch (m.N) {
     case 1: launch_n<1, T, TO>(m, a, out, s); break;
     case 2: launch_n<2, T, TO>(m, a, out, s); break;

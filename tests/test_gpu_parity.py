@@ -343,3 +343,29 @@ def test_full_size_step_parity(full):
     qh = p.host(qg)
     print("full increment", group_err(qh - q0, qo - q0))
     assert_groups(qh, qo, TOL64, "full 2-step state")
+
+
+# ------------------------------------------- fused step across orders/meshes
+@pytest.mark.parametrize("N,ne,perz", [(1, (8, 4, 3), 0), (2, (8, 4, 3), 0), (3, (8, 3, 2), 0), (4, (8, 4, 2), 1),
+                                       (5, (4, 3, 2), 0), (6, (4, 2, 2), 0), (7, (4, 2, 2), 1), (8, (4, 2, 2), 0),
+                                       (4, (6, 4, 3), 0), (3, (5, 2, 2), 1)])
+def test_step_parity_orders_and_meshes(torch_cuda, oracle_mod, N, ne, perz):
+    """Covers the box finish kernel for every order (including periodic z and
+    the top-wall layer) and the generic finish when nx is not a multiple of
+    the block's x-segment (nx = 6 at N = 4, nx = 5 at N = 3)."""
+    wl = inputs.box_workload(*ne, N, 1.2e4, 9e3, 6e3, terrain=300.0, bubble_centre=(6e3, 4.5e3, 2.5e3),
+                             bubble_radius=2.5e3, periodic_z=bool(perz))
+    p = Pair(wl, oracle_mod)
+    q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, N))
+    qo = p.o.step(q0, 0.05, 2)
+    qg = p.dev(q0)
+    p.g.step(qg, 0.05, 2)
+    qh = p.host(qg)
+    assert_groups(qh, qo, TOL64, "step N=%d ne=%s perz=%d" % (N, ne, perz))
+    # and the mixed path stays within the mixed tolerance of the FP64 result
+    from paper_1511_01561_amd import numa
+    qm = p.dev(q0)
+    p.g.step(qm, 0.05, 2, prec=numa.PREC_MIXED)
+    e = group_err(p.host(qm) - q0, qo - q0)
+    print("mixed 2-step increment", {k: "%.1e" % v for k, v in e.items()})
+    assert max(e.values()) < 1e-4
