@@ -23,7 +23,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = {
-    "stage": os.path.join(ROOT, "paper_1511_01561_amd", "csrc", "rhs.hip"),
+    "stage": [os.path.join(ROOT, "paper_1511_01561_amd", "csrc", f) for f in ("kernels.h", "batch.hip")],
 }
 
 
@@ -31,9 +31,12 @@ def _log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def source_hash(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def source_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def element_bytes(nu, nl, prec):
@@ -94,6 +97,48 @@ def cpu_baseline(wl, budget_s=15.0):
                        % (steps, oracle.num_threads(), el))
 
 
+def serving(n_req, budget_gb, precs, loads=(0.5, 0.8), seed=0):
+    """Ensemble serving: requests of box meshes {8^3, 16^3, 32x32x8, 64x64x16}
+    with N in {3, 4, 5, 6} and K = 50 SSP-RK3 steps.  First back-to-back (all
+    requests available at once) to measure the capacity C in requests/s, then
+    Poisson arrivals at rate load*C for p50/p99 latency (arrival to completion)."""
+    import torch
+    from paper_1511_01561_amd import inputs
+    from paper_1511_01561_amd.serve import GpuExecutor, Request, Server
+
+    def make(rate, s):
+        return [Request(id=r["id"], arrival=r["arrival"], workload=r["workload"], noise_seed=r["noise_seed"],
+                        steps=r["steps"]) for r in inputs.serving_requests(n_req, s, rate)]
+
+    out = {"requests": n_req, "budget_gb": budget_gb, "steps_per_request": 50,
+           "mix": "box {8^3, 16^3, 32x32x8, 64x64x16} x N {3,4,5,6}, uniform"}
+    for prec, name in precs:
+        ex = GpuExecutor(prec=prec)
+        srv = Server(ex, budget_bytes=int(budget_gb * 2 ** 30))
+        b2b = make(1.0, seed)
+        srv.prewarm(b2b)
+        st = srv.run(b2b, realtime=False)
+        cap = n_req / st.wall
+        rec = {"capacity_req_per_s": cap, "throughput_updates_per_s": st.updates / st.wall,
+               "back_to_back_wall_s": st.wall, "max_active": st.max_active}
+        _log("serving %s: capacity %.2f req/s, %.3e updates/s, max %d active" % (name, cap, st.updates / st.wall,
+                                                                                st.max_active))
+        for load in loads:
+            reqs = make(load * cap, seed + 1)
+            srv.prewarm(reqs)
+            st = srv.run(reqs, realtime=True)
+            rec["load_%.1f" % load] = {"rate_req_per_s": load * cap, "p50_s": st.percentile(50),
+                                       "p99_s": st.percentile(99), "throughput_updates_per_s": st.updates / st.wall,
+                                       "max_active": st.max_active, "peak_gb": st.peak_bytes / 2 ** 30}
+            _log("serving %s at %.1f C: p50 %.3f s, p99 %.3f s" % (name, load, st.percentile(50), st.percentile(99)))
+        ex.drop_graphs()
+        out[name] = rec
+        del ex, srv
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +147,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--small", action="store_true", help="4x4x4 box instead of the one-GPU workload")
+    ap.add_argument("--serve-requests", type=int, default=100, help="requests per serving run (0: skip)")
+    ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -178,7 +225,7 @@ def main():
     fin_alg = finish_bytes(g.n_unique, g.n_local, n_wall, "fp64")
     _log("element kernel %.0f GB/s algorithmic; finish kernel %.0f GB/s" % (achieved, fin_alg / fin_s / 1e9))
     traffic = load_traffic("stage", workload)
-    roofline = dict(kernel="k_rhs<4,double> (element kernel of the fused stage)", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+    roofline = dict(kernel="k_elem_batch<4,double> (element kernel of the fused stage)", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=achieved / HBM_PEAK_GBS, traffic=traffic, algorithmic_bytes=alg,
                     avg_launch_us=el_s * 1e6,
                     finish_kernel=dict(avg_launch_us=fin_s * 1e6, algorithmic_bytes=fin_alg,
@@ -197,6 +244,13 @@ def main():
         torch.cuda.synchronize()
         _log("copy probe: 3 x %d MiB device copies" % args.copy_probe)
         del src, dst
+
+    serve = None
+    if args.serve_requests > 0:
+        del q0
+        torch.cuda.empty_cache()
+        precs = [(numa.PREC_FP64, "fp64")] + ([] if args.no_mixed else [(numa.PREC_MIXED, "mixed")])
+        serve = serving(args.serve_requests, args.serve_budget_gb, precs)
 
     cpu = None
     if not args.no_cpu:
@@ -220,6 +274,7 @@ def main():
                    "local_nodes": g.n_local, "dt": dt, "integrator": "SSP-RK3", "parallelism": "single GPU"},
         "mixed": mixed,
         "roofline": roofline,
+        "serving": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -177,6 +177,36 @@ int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn,
  * The stream must not run other work on q or the workspace meanwhile. */
 int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double *q, void *stream);
 
+/* ---- Batched stages (continuous batching of independent solves) ----
+ * An item is one solve: a mesh whose geometry may be shared with other items
+ * (read only), its state q [5][n_unique] (device, updated in place), private
+ * device scratch of numa_step_scratch_bytes() (256-byte aligned), and its dt.
+ * numa_step_batch advances all items by nsteps SSP-RK3 steps with one
+ * element launch and one finish launch per stage for every 16 items.  All
+ * items must have the same order and precision, be box meshes whose x element
+ * count is a multiple of the finish segment (4 for N <= 6, 2 for N = 7, 8),
+ * and have distinct states and scratch.  Each item's result is bitwise the
+ * result of numa_step on it alone (the same per-element and per-node code). */
+typedef struct numa_batch_item {
+    numa_mesh_t mesh;
+    double *q;
+    void *scratch;
+    double dt;
+} numa_batch_item;
+
+int32_t numa_step_scratch_bytes(numa_mesh_t m, int32_t prec, uint64_t *bytes);
+int32_t numa_step_batch(const numa_batch_item *items, int32_t n, int32_t prec, int32_t nsteps, void *stream);
+
+/* Capture numa_step_batch(items, n, prec, nsteps) on a non-default stream into
+ * a HIP graph (no memory operations inside); numa_graph_launch replays it on
+ * any stream with the same arguments (the same device buffers), so membership
+ * changes need a new capture.  The items' meshes must not be profiling. */
+typedef struct numa_graph *numa_graph_t;
+int32_t numa_batch_capture(const numa_batch_item *items, int32_t n, int32_t prec, int32_t nsteps, void *stream,
+                           numa_graph_t *out);
+int32_t numa_graph_launch(numa_graph_t g, void *stream);
+int32_t numa_graph_destroy(numa_graph_t g);
+
 /* Per-kernel timing of numa_step: while enabled, numa_step records HIP events
  * on the caller's stream around each launch of its two stage kernels (the
  * element kernel and the DSS/update finish).  numa_profile(m, 1) starts a new

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "numa_internal.h"
 
@@ -26,6 +27,10 @@ using numa::Mesh;
 using numa::set_error;
 
 struct numa_mesh : Mesh {};
+struct numa_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
 
 static inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
@@ -278,30 +283,48 @@ int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn,
     return numa::launch_rk_stage(*m, stage, dt, qn, qs, r, qout, as_stream(stream));
 }
 
-// one fused stage: element kernel then finish kernel, optionally bracketed by events
+// event bracket around a group of launches when the mesh is profiling
+static int32_t mark(numa_mesh_t m, std::vector<std::pair<int, int>> &log, bool begin, hipStream_t s)
+{
+    if (!m || !m->profiling) return NUMA_OK;
+    if (m->ev_used == m->ev_pool.size()) {
+        hipEvent_t e;
+        NUMA_HIP(hipEventCreate(&e));
+        m->ev_pool.push_back(e);
+    }
+    int id = (int)m->ev_used++;
+    NUMA_HIP(hipEventRecord(m->ev_pool[id], s));
+    if (begin) log.push_back({id, -1});
+    else log.back().second = id;
+    return NUMA_OK;
+}
+
+// one fused stage of a batch: element kernels then finish kernels; events are
+// recorded on the first item's mesh when it is profiling
+static int32_t run_batch_stage(const numa::StepItem *items, int n, int32_t prec, int32_t stage, hipStream_t s)
+{
+    numa_mesh_t m0 = static_cast<numa_mesh_t>(const_cast<Mesh *>(items[0].mesh));
+    int32_t rc;
+    if ((rc = mark(m0, m0->ev_elem, true, s))) return rc;
+    if ((rc = numa::launch_batch_stage(items, n, prec, stage, 0, s))) return rc;
+    if ((rc = mark(m0, m0->ev_elem, false, s))) return rc;
+    if ((rc = mark(m0, m0->ev_fin, true, s))) return rc;
+    if ((rc = numa::launch_batch_stage(items, n, prec, stage, 1, s))) return rc;
+    return mark(m0, m0->ev_fin, false, s);
+}
+
+// one fused stage of a single mesh through the general kernels (shell, or a
+// box whose x extent does not fit the batched finish)
 static int32_t run_stage(numa_mesh_t m, int32_t prec, int32_t stage, double dt, const double *qn, const double *qs,
                          double *qout, hipStream_t s)
 {
     int32_t rc;
-    auto mark = [&](std::vector<std::pair<int, int>> &log, bool begin) -> int32_t {
-        if (!m->profiling) return NUMA_OK;
-        if (m->ev_used == m->ev_pool.size()) {
-            hipEvent_t e;
-            NUMA_HIP(hipEventCreate(&e));
-            m->ev_pool.push_back(e);
-        }
-        int id = (int)m->ev_used++;
-        NUMA_HIP(hipEventRecord(m->ev_pool[id], s));
-        if (begin) log.push_back({id, -1});
-        else log.back().second = id;
-        return NUMA_OK;
-    };
-    if ((rc = mark(m->ev_elem, true))) return rc;
+    if ((rc = mark(m, m->ev_elem, true, s))) return rc;
     if ((rc = numa::launch_stage_elements(*m, prec, stage, dt, qn, qs, qout, s))) return rc;
-    if ((rc = mark(m->ev_elem, false))) return rc;
-    if ((rc = mark(m->ev_fin, true))) return rc;
+    if ((rc = mark(m, m->ev_elem, false, s))) return rc;
+    if ((rc = mark(m, m->ev_fin, true, s))) return rc;
     if ((rc = numa::launch_stage_finish(*m, prec, stage, dt, qn, qs, qout, s))) return rc;
-    return mark(m->ev_fin, false);
+    return mark(m, m->ev_fin, false, s);
 }
 
 int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double *q, void *stream)
@@ -315,10 +338,159 @@ int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double
     }
     hipStream_t s = as_stream(stream);
     double *qs = m->dv.qs;
+    if (numa::box_batchable(*m)) {
+        void *ev = prec == NUMA_PREC_MIXED ? (void *)m->dv.ev32 : (void *)m->dv.ev64;
+        numa::StepItem st[3] = {{m, q, q, qs, ev, dt}, {m, q, qs, qs, ev, dt}, {m, q, qs, q, ev, dt}};
+        for (int n = 0; n < nsteps; ++n)
+            for (int k = 0; k < 3; ++k)
+                if ((rc = run_batch_stage(&st[k], 1, prec, k, s))) return rc;
+        return NUMA_OK;
+    }
     for (int n = 0; n < nsteps; ++n) {
         if ((rc = run_stage(m, prec, 0, dt, q, q, qs, s))) return rc;
         if ((rc = run_stage(m, prec, 1, dt, q, qs, qs, s))) return rc;
         if ((rc = run_stage(m, prec, 2, dt, q, qs, q, s))) return rc;
+    }
+    return NUMA_OK;
+}
+
+static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+int32_t numa_step_scratch_bytes(numa_mesh_t m, int32_t prec, uint64_t *bytes)
+{
+    if (!m || !bytes) {
+        set_error("numa_step_scratch_bytes: null argument");
+        return NUMA_EINVAL;
+    }
+    *bytes = align256(40ull * m->nu) + align256((prec == NUMA_PREC_MIXED ? 20ull : 40ull) * m->nl);
+    return NUMA_OK;
+}
+
+static int32_t check_batch(const numa_batch_item *items, int32_t n, int32_t prec, const char *fn)
+{
+    if (!items || n < 1) {
+        set_error("%s: no items", fn);
+        return NUMA_EINVAL;
+    }
+    for (int32_t k = 0; k < n; ++k) {
+        numa_mesh_t m = items[k].mesh;
+        int32_t rc = need_ready(m, fn);
+        if (rc) return rc;
+        if ((rc = check_prec(m, prec, fn))) return rc;
+        if (!numa::box_batchable(*m)) {
+            set_error("%s: item %d: batched stages need a box mesh whose x element count fits the finish segment", fn, k);
+            return NUMA_EUNSUPPORTED;
+        }
+        if (m->N != items[0].mesh->N) {
+            set_error("%s: item %d has order %d, item 0 has %d (one order per batch)", fn, k, m->N, items[0].mesh->N);
+            return NUMA_EINVAL;
+        }
+        if (!items[k].q || !items[k].scratch || reinterpret_cast<uintptr_t>(items[k].scratch) % 256) {
+            set_error("%s: item %d: null state or scratch not 256-byte aligned", fn, k);
+            return NUMA_EINVAL;
+        }
+        for (int32_t j = 0; j < k; ++j)
+            if (items[j].q == items[k].q || items[j].scratch == items[k].scratch) {
+                set_error("%s: items %d and %d share a state or a scratch buffer", fn, j, k);
+                return NUMA_EINVAL;
+            }
+    }
+    return NUMA_OK;
+}
+
+int32_t numa_step_batch(const numa_batch_item *items, int32_t n, int32_t prec, int32_t nsteps, void *stream)
+{
+    int32_t rc = check_batch(items, n, prec, "numa_step_batch");
+    if (rc) return rc;
+    if (nsteps < 0) {
+        set_error("numa_step_batch: negative step count");
+        return NUMA_EINVAL;
+    }
+    hipStream_t s = as_stream(stream);
+    std::vector<numa::StepItem> st(3 * (size_t)n);
+    for (int32_t k = 0; k < n; ++k) {
+        const Mesh *m = items[k].mesh;
+        double *q = items[k].q;
+        double *qs = static_cast<double *>(items[k].scratch);
+        void *ev = static_cast<char *>(items[k].scratch) + align256(40ull * m->nu);
+        st[k] = {m, q, q, qs, ev, items[k].dt};
+        st[n + k] = {m, q, qs, qs, ev, items[k].dt};
+        st[2 * n + k] = {m, q, qs, q, ev, items[k].dt};
+    }
+    for (int32_t step = 0; step < nsteps; ++step)
+        for (int stage = 0; stage < 3; ++stage)
+            if ((rc = run_batch_stage(&st[(size_t)stage * n], n, prec, stage, s))) return rc;
+    return NUMA_OK;
+}
+
+int32_t numa_batch_capture(const numa_batch_item *items, int32_t n, int32_t prec, int32_t nsteps, void *stream,
+                           numa_graph_t *out)
+{
+    if (!out) {
+        set_error("numa_batch_capture: null output");
+        return NUMA_EINVAL;
+    }
+    *out = nullptr;
+    int32_t rc = check_batch(items, n, prec, "numa_batch_capture");
+    if (rc) return rc;
+    if (!stream) {
+        set_error("numa_batch_capture: capture needs a non-default stream");
+        return NUMA_EINVAL;
+    }
+    for (int32_t k = 0; k < n; ++k)
+        if (items[k].mesh->profiling) {
+            set_error("numa_batch_capture: disable numa_profile on the items' meshes first");
+            return NUMA_EINVAL;
+        }
+    hipStream_t s = as_stream(stream);
+    NUMA_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    rc = numa_step_batch(items, n, prec, nsteps, stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc != NUMA_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) {
+        set_error("numa_batch_capture: hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        return NUMA_EDEVICE;
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        set_error("numa_batch_capture: hipGraphInstantiate failed: %s", hipGetErrorString(e));
+        return NUMA_EDEVICE;
+    }
+    numa_graph *h = new (std::nothrow) numa_graph{g, x};
+    if (!h) {
+        (void)hipGraphExecDestroy(x);
+        (void)hipGraphDestroy(g);
+        set_error("numa_batch_capture: out of host memory");
+        return NUMA_ENOMEM;
+    }
+    *out = h;
+    return NUMA_OK;
+}
+
+int32_t numa_graph_launch(numa_graph_t g, void *stream)
+{
+    if (!g) {
+        set_error("numa_graph_launch: null graph");
+        return NUMA_EINVAL;
+    }
+    NUMA_HIP(hipGraphLaunch(g->exec, as_stream(stream)));
+    return NUMA_OK;
+}
+
+int32_t numa_graph_destroy(numa_graph_t g)
+{
+    if (!g) return NUMA_OK;
+    hipError_t e1 = hipGraphExecDestroy(g->exec), e2 = hipGraphDestroy(g->graph);
+    delete g;
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        set_error("numa_graph_destroy: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
+        return NUMA_EDEVICE;
     }
     return NUMA_OK;
 }

@@ -1,0 +1,204 @@
+// Batched fused stages on box meshes: the elements and nodes of several
+// independent solves of the same order advance together, one element launch
+// and one finish launch per stage for the whole batch (continuous batching of
+// ensemble members and regional solves).  Each item brings its own state and
+// private scratch; geometry may be shared between items.  The per-element
+// and per-node arithmetic is the single-mesh code (kernels.h), so an item's
+// result does not depend on what it is batched with.  A single box mesh
+// (numa_step) runs through the same kernels with one item.
+#include <type_traits>
+
+#include "kernels.h"
+
+namespace numa {
+namespace {
+
+using namespace dev;
+
+constexpr int kMaxBatch = 16;  // items per launch (kernel-argument table)
+
+struct BatchItem {
+    const double *qs;  // stage input state [5][nu]
+    double *qout;      // stage output state
+    const double *qn;  // state at the start of the step
+    const double *ref, *Minv, *nrm;
+    const void *met;   // [ne][10][np] of T
+    void *ev;          // [5][nl] of T: contributions of this stage
+    int64_t nl, nu, nh, ni, nj, nkw;  // nkw: lattice extent in z when periodic, else -1
+    int nx, ny, nz, walls;
+    double dt;
+    int64_t eoff, boff;  // first element / finish block of this item in the launch
+};
+
+struct Batch {
+    int n, stage;
+    double gamma, g0;
+    const void *D;
+    BatchItem it[kMaxBatch];
+};
+
+template <int N, typename T>
+__global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
+{
+    constexpr int NP = (N + 1) * (N + 1) * (N + 1);
+    __shared__ T s[8][NP];
+    const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
+    int k = 0;
+    while (k + 1 < B.n && g >= B.it[k + 1].eoff) ++k;
+    const BatchItem &it = B.it[k];
+    const int64_t e = g - it.eoff;
+    RhsArgs<T> a;
+    a.G = nullptr;
+    a.q = it.qs;
+    a.ref = it.ref;
+    a.grav = nullptr;
+    a.met = (const T *)it.met;
+    a.D = (const T *)B.D;
+    a.nl = it.nl;
+    a.nu = it.nu;
+    a.gamma = B.gamma;
+    a.g0 = B.g0;
+    a.nx = it.nx;
+    a.ny = it.ny;
+    a.ni = it.ni;
+    a.nj = it.nj;
+    a.nk = it.nkw;
+    NodeOut<T> o;
+    if (!element_rhs<N, T, false>(a, e, threadIdx.x, s, o)) return;
+    T *p = (T *)it.ev + e * NP + threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) p[v * it.nl] = o.Jw * o.R[v];
+}
+
+template <int N, int SEG, typename T>
+__global__ void k_fin_batch(Batch B)
+{
+    const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
+    int k = 0;
+    while (k + 1 < B.n && g >= B.it[k + 1].boff) ++k;
+    const BatchItem &it = B.it[k];
+    int64_t lb = g - it.boff;
+    const int64_t main_blocks = (int64_t)(it.nx / SEG) * it.ny * it.nz;
+    int kbase = 0, klayers = N;
+    if (lb >= main_blocks) {  // the top wall layer
+        kbase = N;
+        klayers = 1;
+        lb -= main_blocks;
+    }
+    PointArgs p;
+    p.off = nullptr;
+    p.idx = nullptr;
+    p.Minv = it.Minv;
+    p.nrm = it.nrm;
+    p.nl = it.nl;
+    p.nu = it.nu;
+    p.nh = it.nh;
+    p.walls = it.walls;
+    BoxFin b;
+    b.nx = it.nx;
+    b.ny = it.ny;
+    b.nz = it.nz;
+    b.walls = it.walls;
+    b.ni = it.ni;
+    b.nj = it.nj;
+    b.nk = 0;
+    box_finish_node<N, SEG, T>(p, b, (const T *)it.ev, lb, threadIdx.x, kbase, klayers, B.stage, it.dt, it.qn, it.qs,
+                               it.qout);
+}
+
+template <int N, typename T>
+int32_t run_chunk(const StepItem *items, int n, int stage, int phase, hipStream_t s)
+{
+    constexpr int SEG = seg_for<N>();
+    Batch B;
+    B.n = n;
+    B.stage = stage;
+    B.gamma = items[0].mesh->gamma;
+    B.g0 = items[0].mesh->ph.g0;
+    B.D = std::is_same<T, float>::value ? (const void *)items[0].mesh->dv.D32 : (const void *)items[0].mesh->dv.D64;
+    int64_t eo = 0, bo = 0;
+    for (int k = 0; k < n; ++k) {
+        const Mesh &m = *items[k].mesh;
+        BatchItem &it = B.it[k];
+        it.qs = items[k].qs;
+        it.qout = items[k].qout;
+        it.qn = items[k].qn;
+        it.ref = m.dv.ref;
+        it.Minv = m.dv.Minv;
+        it.nrm = m.dv.nrm;
+        it.met = std::is_same<T, float>::value ? (const void *)m.dv.met32 : (const void *)m.dv.met;
+        it.ev = items[k].ev;
+        it.nl = m.nl;
+        it.nu = m.nu;
+        it.nh = m.nh;
+        it.ni = m.ni;
+        it.nj = m.nj;
+        it.nkw = m.d.periodic[2] ? m.nk : -1;
+        it.nx = m.d.ne[0];
+        it.ny = m.d.ne[1];
+        it.nz = m.d.ne[2];
+        it.walls = m.walls ? 1 : 0;
+        it.dt = items[k].dt;
+        it.eoff = eo;
+        it.boff = bo;
+        eo += m.ne;
+        bo += (int64_t)(it.nx / SEG) * it.ny * it.nz + (m.walls ? (int64_t)(it.nx / SEG) * it.ny : 0);
+    }
+    for (int k = n; k < kMaxBatch; ++k) B.it[k] = BatchItem{};
+    if (phase == 0) {
+        hipLaunchKernelGGL((k_elem_batch<N, T>), dim3((unsigned)eo), dim3(block_threads<N>()), 0, s, B);
+    } else {
+        const int threads = ((SEG * N * N * N + 63) / 64) * 64;
+        hipLaunchKernelGGL((k_fin_batch<N, SEG, T>), dim3((unsigned)bo), dim3(threads), 0, s, B);
+    }
+    NUMA_HIP(hipGetLastError());
+    return NUMA_OK;
+}
+
+template <typename T>
+int32_t run_stage_t(const StepItem *items, int n, int stage, int phase, hipStream_t s)
+{
+    for (int c0 = 0; c0 < n; c0 += kMaxBatch) {
+        const int c = n - c0 < kMaxBatch ? n - c0 : kMaxBatch;
+        int32_t rc;
+        switch (items[0].mesh->N) {
+        case 1: rc = run_chunk<1, T>(items + c0, c, stage, phase, s); break;
+        case 2: rc = run_chunk<2, T>(items + c0, c, stage, phase, s); break;
+        case 3: rc = run_chunk<3, T>(items + c0, c, stage, phase, s); break;
+        case 4: rc = run_chunk<4, T>(items + c0, c, stage, phase, s); break;
+        case 5: rc = run_chunk<5, T>(items + c0, c, stage, phase, s); break;
+        case 6: rc = run_chunk<6, T>(items + c0, c, stage, phase, s); break;
+        case 7: rc = run_chunk<7, T>(items + c0, c, stage, phase, s); break;
+        default: rc = run_chunk<8, T>(items + c0, c, stage, phase, s); break;
+        }
+        if (rc) return rc;
+    }
+    return NUMA_OK;
+}
+
+}  // namespace
+
+bool box_batchable(const Mesh &m)
+{
+    if (m.d.kind != NUMA_MESH_BOX) return false;
+    int seg;
+    switch (m.N) {
+    case 1: seg = seg_for<1>(); break;
+    case 2: seg = seg_for<2>(); break;
+    case 3: seg = seg_for<3>(); break;
+    case 4: seg = seg_for<4>(); break;
+    case 5: seg = seg_for<5>(); break;
+    case 6: seg = seg_for<6>(); break;
+    case 7: seg = seg_for<7>(); break;
+    default: seg = seg_for<8>(); break;
+    }
+    return m.d.ne[0] % seg == 0;
+}
+
+int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int32_t stage, int phase, hipStream_t s)
+{
+    if (prec == NUMA_PREC_MIXED) return run_stage_t<float>(items, n, stage, phase, s);
+    return run_stage_t<double>(items, n, stage, phase, s);
+}
+
+}  // namespace numa

@@ -1,0 +1,278 @@
+// Device code shared by the single-mesh and the batched kernels: the per-node
+// element right-hand side, the wall projection, the stage combination and the
+// per-node finish of a fused stage on the box.  Included by the .hip sources.
+#pragma once
+
+#include <cmath>
+
+#include "numa_internal.h"
+
+namespace numa {
+namespace dev {
+
+template <typename T>
+struct RhsArgs {
+    const int32_t *G;  // gather map (shell); the box computes unique ids from its lattice
+    const double *q, *ref, *grav;
+    const T *met;
+    const T *D;
+    int64_t nl, nu;
+    double gamma, g0;
+    int nx, ny;          // box: elements along x and y
+    int64_t ni, nj, nk;  // box: lattice extents (x, y periodic)
+};
+
+// unique id of local node (i, j, k) of box element e: the element's lattice
+// corner plus the local offset, wrapped in the periodic directions
+template <int N, typename T>
+__device__ __forceinline__ int64_t box_unique(const RhsArgs<T> &a, int64_t e, int i, int j, int k)
+{
+    const int64_t ex = e % a.nx, ey = (e / a.nx) % a.ny, ez = e / ((int64_t)a.nx * a.ny);
+    int64_t gi = ex * N + i, gj = ey * N + j, gk = ez * N + k;
+    if (gi == a.ni) gi = 0;
+    if (gj == a.nj) gj = 0;
+    if (gk == a.nk) gk = 0;
+    return gi + a.ni * (gj + a.nj * gk);
+}
+
+template <int N>
+constexpr int block_threads() { return (((N + 1) * (N + 1) * (N + 1) + 63) / 64) * 64; }
+
+// Per-node result of the element RHS.
+template <typename T>
+struct NodeOut {
+    T R[5];     // R_rho', R_u, R_v, R_w, R_theta'
+    T Jw;
+    int64_t I;  // unique id of the node
+    double q[5];
+};
+
+// Gathers the element tile, differentiates it and evaluates R at node l of
+// element e.  Must be called by all lanes of the block (it synchronises);
+// returns false for the padding lanes (l >= (N+1)^3).
+template <int N, typename T, bool SHELL>
+__device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int l, T (*s)[(N + 1) * (N + 1) * (N + 1)],
+                                            NodeOut<T> &o)
+{
+    constexpr int P = N + 1, NP = P * P * P, NF = SHELL ? 9 : 8;
+    const bool act = l < NP;
+    double rp = 0.0, rho = 1.0, u = 0.0, v = 0.0, w = 0.0, tp = 0.0;
+    int64_t I = 0;
+    // metric terms do not depend on the tile: load them before the barrier so
+    // their latency overlaps the state gather and the equation of state
+    T mx[10];
+    if (act) {
+        const T *mp = a.met + e * 10 * NP + l;
+#pragma unroll
+        for (int c = 0; c < 10; ++c) mx[c] = mp[c * NP];
+    }
+    if (act) {
+        if constexpr (SHELL) {
+            I = a.G[e * NP + l];
+        } else {
+            constexpr int P_ = N + 1;
+            I = box_unique<N, T>(a, e, l % P_, (l / P_) % P_, l / (P_ * P_));
+        }
+        rp = a.q[I];
+        u = a.q[a.nu + I];
+        v = a.q[2 * a.nu + I];
+        w = a.q[3 * a.nu + I];
+        tp = a.q[4 * a.nu + I];
+        const double rb = a.ref[I], tb = a.ref[a.nu + I], pb = a.ref[2 * a.nu + I];
+        rho = rb + rp;
+        // p' = p_bar ((rho theta / rho_bar theta_bar)^gamma - 1) without cancellation
+        const double dl = rp * tb + rb * tp + rp * tp;
+        const double pp = pb * expm1(a.gamma * log1p(dl / (rb * tb)));
+        s[0][l] = (T)(rho * u);
+        s[1][l] = (T)(rho * v);
+        s[2][l] = (T)(rho * w);
+        s[3][l] = (T)u;
+        s[4][l] = (T)v;
+        s[5][l] = (T)w;
+        s[6][l] = (T)tp;
+        s[7][l] = (T)pp;
+        if constexpr (SHELL) {
+            // the background theta is differentiated relative to the element's first node
+            const double t0 = a.ref[a.nu + a.G[e * NP]];
+            s[8][l] = (T)(tb - t0);
+        }
+    }
+    __syncthreads();
+    if (!act) return false;
+    const int i = l % P, j = (l / P) % P, k = l / (P * P);
+    T Di[P], Dj[P], Dk[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+        Di[m] = a.D[i * P + m];
+        Dj[m] = a.D[j * P + m];
+        Dk[m] = a.D[k * P + m];
+    }
+    T dx[NF], dy[NF], dz[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        T da = 0, db = 0, dc = 0;
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+            da += Di[m] * s[f][m + P * (j + P * k)];
+            db += Dj[m] * s[f][i + P * (m + P * k)];
+            dc += Dk[m] * s[f][i + P * (j + P * m)];
+        }
+        dx[f] = da * mx[0] + db * mx[3] + dc * mx[6];
+        dy[f] = da * mx[1] + db * mx[4] + dc * mx[7];
+        dz[f] = da * mx[2] + db * mx[5] + dc * mx[8];
+    }
+    const T irho = (T)(1.0 / rho);
+    const T buoy = (T)(rp / rho);
+    T gx = 0, gy = 0, gz = (T)(-a.g0);
+    if constexpr (SHELL) {
+        gx = (T)a.grav[I];
+        gy = (T)a.grav[a.nu + I];
+        gz = (T)a.grav[2 * a.nu + I];
+    }
+    const T uu = (T)u, vv = (T)v, ww = (T)w;
+    o.R[0] = -(dx[0] + dy[1] + dz[2]);
+    o.R[1] = -(uu * dx[3] + vv * dy[3] + ww * dz[3]) - dx[7] * irho + buoy * gx;
+    o.R[2] = -(uu * dx[4] + vv * dy[4] + ww * dz[4]) - dy[7] * irho + buoy * gy;
+    o.R[3] = -(uu * dx[5] + vv * dy[5] + ww * dz[5]) - dz[7] * irho + buoy * gz;
+    o.R[4] = -(uu * dx[6] + vv * dy[6] + ww * dz[6]);
+    if constexpr (SHELL) o.R[4] -= uu * dx[8] + vv * dy[8] + ww * dz[8];
+    o.Jw = mx[9];
+    o.I = I;
+    o.q[0] = rp;
+    o.q[1] = u;
+    o.q[2] = v;
+    o.q[3] = w;
+    o.q[4] = tp;
+    return true;
+}
+
+struct PointArgs {
+    const int32_t *off, *idx;
+    const double *Minv, *nrm;
+    int64_t nl, nu, nh;
+    int walls;
+};
+
+inline PointArgs point_args(const Mesh &m)
+{
+    PointArgs p;
+    p.off = m.dv.off;
+    p.idx = m.dv.idx;
+    p.Minv = m.dv.Minv;
+    p.nrm = m.dv.nrm;
+    p.nl = m.nl;
+    p.nu = m.nu;
+    p.nh = m.nh;
+    p.walls = m.walls ? 1 : 0;
+    return p;
+}
+
+// remove the wall-normal component of (r1, r2, r3) at bottom/top nodes
+__device__ inline void noflux(const PointArgs &p, int64_t I, double &r1, double &r2, double &r3)
+{
+    if (!p.walls) return;
+    int side;
+    int64_t h;
+    if (I < p.nh) { side = 0; h = I; }
+    else if (I >= p.nu - p.nh) { side = 1; h = I - (p.nu - p.nh); }
+    else return;
+    const double *n = p.nrm + side * 3 * p.nh + h;
+    double n0 = n[0], n1 = n[p.nh], n2 = n[2 * p.nh];
+    double dn = r1 * n0 + r2 * n1 + r3 * n2;
+    r1 -= dn * n0;
+    r2 -= dn * n1;
+    r3 -= dn * n2;
+}
+
+// SSP-RK3 stage combination (Shu-Osher form)
+__device__ inline double rk_combine(int stage, double qn, double y)
+{
+    if (stage == 0) return y;
+    if (stage == 1) return 0.75 * qn + 0.25 * y;
+    return (1.0 / 3.0) * qn + (2.0 / 3.0) * y;
+}
+
+// Finish of a fused stage on the box.  A block takes SEG consecutive elements
+// along x of one (ey, ez) and, per element, the lattice nodes whose lower
+// corner it is (local 0 <= i, j, k < N); lanes run along x fastest, so every
+// state read and write covers SEG*N consecutive unique ids.  The copies of a
+// node follow from its lattice position: on an element face along a
+// direction it has two copies (local index 0 of the element above and N of
+// the one below, wrapped when periodic), else one.  A second launch with
+// kbase = N, klayers = 1 covers the top wall layer (a block index of that layer).
+struct BoxFin {
+    int nx, ny, nz, walls;
+    int64_t ni, nj, nk;
+};
+
+template <int N, int SEG, typename T>
+__device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin &b, const T *ev, int64_t blk,
+                                                int lane, int kbase, int klayers, int stage, double dt,
+                                                const double *qn, const double *qs, double *qout)
+{
+    constexpr int P = N + 1, NP = P * P * P, W = SEG * N;
+    if (lane >= W * N * klayers) return;
+    const int64_t nseg = b.nx / SEG;
+    const int64_t sx = blk % nseg, ey = (blk / nseg) % b.ny, ez = kbase == 0 ? blk / (nseg * b.ny) : b.nz - 1;
+    const int a = lane % W, jj = (lane / W) % N, kk = lane / (W * N);
+    const int64_t gi = sx * W + a, gj = ey * N + jj, gk = ez * N + kbase + kk;
+    const int64_t I = gi + b.ni * (gj + b.nj * gk);
+    // copies along each direction: (element index along the direction, local index)
+    int64_t cx[2], cy[2], cz[2];
+    int lx[2], ly[2], lz[2], nxc, nyc, nzc;
+    const int64_t exa = gi / N;
+    if (a % N == 0) {  // gi is a multiple of N: element face in x
+        cx[0] = exa; lx[0] = 0;
+        cx[1] = exa == 0 ? b.nx - 1 : exa - 1; lx[1] = N;
+        nxc = 2;
+    } else {
+        cx[0] = exa; lx[0] = (int)(gi - exa * N);
+        nxc = 1;
+    }
+    if (jj == 0) {
+        cy[0] = ey; ly[0] = 0;
+        cy[1] = ey == 0 ? b.ny - 1 : ey - 1; ly[1] = N;
+        nyc = 2;
+    } else {
+        cy[0] = ey; ly[0] = jj;
+        nyc = 1;
+    }
+    const int kl = kbase + kk;  // local k in element ez
+    if (kl == 0) {
+        if (ez == 0 && b.walls) {
+            cz[0] = 0; lz[0] = 0; nzc = 1;
+        } else {
+            cz[0] = ez; lz[0] = 0;
+            cz[1] = ez == 0 ? b.nz - 1 : ez - 1; lz[1] = N;
+            nzc = 2;
+        }
+    } else {
+        cz[0] = ez; lz[0] = kl; nzc = 1;  // kl == N only for the top wall layer
+    }
+    double r[5] = {0, 0, 0, 0, 0};
+    for (int z = 0; z < nzc; ++z)
+        for (int y = 0; y < nyc; ++y)
+            for (int x = 0; x < nxc; ++x) {
+                const int64_t e = cx[x] + b.nx * (cy[y] + b.ny * cz[z]);
+                const int64_t c = e * NP + lx[x] + P * (ly[y] + P * lz[z]);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) r[v] += (double)ev[v * p.nl + c];
+            }
+    const double mi = p.Minv[I];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) r[v] *= mi;
+    noflux(p, I, r[1], r[2], r[3]);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        double y = qs[v * p.nu + I] + dt * r[v];
+        qout[v * p.nu + I] = rk_combine(stage, stage == 0 ? 0.0 : qn[v * p.nu + I], y);
+    }
+}
+
+// x-segment length of a box finish block: whole 128-byte lines of FP64 state
+// where the block fits in 1024 lanes
+template <int N>
+constexpr int seg_for() { return 4 * N * N * N <= 1024 ? 4 : (2 * N * N * N <= 1024 ? 2 : 1); }
+
+}  // namespace dev
+}  // namespace numa

@@ -105,6 +105,20 @@ int32_t launch_rhs(Mesh &m, int32_t prec, const double *q, double *evec, hipStre
 int32_t launch_dss(Mesh &m, int32_t nvar, const double *cin, double *out, int32_t flags, hipStream_t s);
 int32_t launch_rk_stage(Mesh &m, int32_t stage, double dt, const double *qn, const double *qs,
                         const double *r, double *qout, hipStream_t s);
+// One solve of a batch at one stage: states and the E-vector scratch.
+struct StepItem {
+    const Mesh *mesh;
+    const double *qn, *qs;
+    double *qout;
+    void *ev;
+    double dt;
+};
+
+// Box meshes whose x extent fits the finish block's segment take the batched
+// kernels; phase 0 launches the element kernels, phase 1 the finish kernels.
+bool box_batchable(const Mesh &m);
+int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int32_t stage, int phase, hipStream_t s);
+
 int32_t launch_stage_elements(Mesh &m, int32_t prec, int32_t stage, double dt, const double *qn, const double *qs,
                               double *qout, hipStream_t s);
 int32_t launch_stage_finish(Mesh &m, int32_t prec, int32_t stage, double dt, const double *qn, const double *qs,

@@ -73,6 +73,16 @@ def noise(n_unique: int, seed: int = 0) -> np.ndarray:
     return np.random.Generator(np.random.PCG64(seed)).standard_normal((3, n_unique))
 
 
+def device_noise(n_unique: int, seed: int, device="cuda:0"):
+    """Standard normal draws [3][n_unique] made on the device (torch's
+    counter-based generator seeded with seed): the per-request noise of the
+    serving workload, where the same request is compared with itself."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    return torch.randn((3, n_unique), generator=g, device=device, dtype=torch.float64)
+
+
 def random_state(n_unique: int, seed: int, rho_scale=1e-2, u_scale=1.0, theta_scale=0.5) -> np.ndarray:
     """Arbitrary nodal state [5][n_unique] (rho', u, v, w, theta') for parity
     checks that do not depend on a physical initial condition."""

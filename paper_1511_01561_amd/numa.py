@@ -22,7 +22,8 @@ FIELD_MASS, FIELD_REF, FIELD_COORDS, FIELD_METRIC, FIELD_GRAVITY, FIELD_LOCAL_CO
 EXPORTED = ["numa_last_error", "numa_gll", "numa_mesh_create", "numa_mesh_destroy", "numa_mesh_info",
             "numa_mesh_gather_map", "numa_mesh_workspace_bytes", "numa_mesh_attach_workspace",
             "numa_geometry", "numa_export", "numa_init_state", "numa_rhs", "numa_dss",
-            "numa_rk_stage", "numa_step", "numa_profile", "numa_profile_read"]
+            "numa_rk_stage", "numa_step", "numa_profile", "numa_profile_read", "numa_step_scratch_bytes",
+            "numa_step_batch", "numa_batch_capture", "numa_graph_launch", "numa_graph_destroy"]
 
 
 class numa_mesh_desc(ct.Structure):
@@ -38,6 +39,10 @@ class numa_phys(ct.Structure):
 class numa_ic(ct.Structure):
     _fields_ = [("kind", ct.c_int32), ("amp", ct.c_double), ("radius", ct.c_double), ("c", ct.c_double * 3),
                 ("lz", ct.c_double), ("jet_u0", ct.c_double), ("noise_amp", ct.c_double)]
+
+
+class numa_batch_item(ct.Structure):
+    _fields_ = [("mesh", ct.c_void_p), ("q", ct.c_void_p), ("scratch", ct.c_void_p), ("dt", ct.c_double)]
 
 
 class NumaError(RuntimeError):
@@ -75,6 +80,11 @@ def lib():
         "numa_step": (I32, [P, I32, D, I32, P, P]),
         "numa_profile": (I32, [P, I32]),
         "numa_profile_read": (I32, [P, P]),
+        "numa_step_scratch_bytes": (I32, [P, I32, ct.POINTER(ct.c_uint64)]),
+        "numa_step_batch": (I32, [ct.POINTER(numa_batch_item), I32, I32, I32, P]),
+        "numa_batch_capture": (I32, [ct.POINTER(numa_batch_item), I32, I32, I32, P, ct.POINTER(P)]),
+        "numa_graph_launch": (I32, [P, P]),
+        "numa_graph_destroy": (I32, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -216,3 +226,56 @@ class Mesh:
         """nsteps SSP-RK3 steps in place on q (device [5][n_unique] FP64)."""
         check(lib().numa_step(self._h, prec, float(dt), int(nsteps), _ptr(q), _stream(stream)))
         return q
+
+
+def step_scratch_bytes(mesh: Mesh, prec: int) -> int:
+    nb = ct.c_uint64()
+    check(lib().numa_step_scratch_bytes(mesh._h, prec, ct.byref(nb)))
+    return nb.value
+
+
+def alloc_scratch(mesh: Mesh, prec: int):
+    """Device scratch for one batch item (a torch uint8 tensor, 256-byte aligned view)."""
+    import torch
+    nb = step_scratch_bytes(mesh, prec)
+    buf = torch.empty(nb + 256, dtype=torch.uint8, device=mesh.device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + nb]
+
+
+def _items(items):
+    """items: sequence of (mesh, q, scratch, dt)"""
+    arr = (numa_batch_item * len(items))()
+    for k, (m, q, scr, dt) in enumerate(items):
+        arr[k].mesh = m._h.value if isinstance(m._h, ct.c_void_p) else m._h
+        arr[k].q = q.data_ptr()
+        arr[k].scratch = scr.data_ptr()
+        arr[k].dt = float(dt)
+    return arr
+
+
+def step_batch(items, nsteps: int, prec: int = PREC_FP64, stream=None):
+    """Advance every (mesh, q, scratch, dt) item by nsteps SSP-RK3 steps in
+    batched launches (same order, box meshes)."""
+    arr = _items(items)
+    check(lib().numa_step_batch(arr, len(items), prec, int(nsteps), _stream(stream)))
+
+
+class Graph:
+    """A captured batch step (numa_batch_capture); replay with launch()."""
+
+    def __init__(self, items, nsteps: int, prec: int, stream):
+        arr = _items(items)
+        h = ct.c_void_p()
+        check(lib().numa_batch_capture(arr, len(items), prec, int(nsteps), _stream(stream), ct.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        check(lib().numa_graph_launch(self._h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.numa_graph_destroy(self._h)
+            self._h = None
+
+    __del__ = close

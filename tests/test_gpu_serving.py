@@ -1,0 +1,153 @@
+"""Batched stages, graph replay and the serving loop on the GPU.
+
+The property served requests must keep: each result is the same alone and in
+the mix.  Batched launches run the single-mesh per-element and per-node code
+on each item's own state and scratch, so the comparison is bitwise.
+"""
+import numpy as np
+import pytest
+
+from paper_1511_01561_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def box(n, N, seed=0, nz=None):
+    nz = nz or n
+    Lx, H = n * 6250.0, nz * 1250.0
+    rng = np.random.default_rng(seed)
+    c = (rng.uniform(0, Lx), rng.uniform(0, Lx), rng.uniform(0.25 * H, 0.75 * H))
+    return inputs.box_workload(n, n, nz, N, Lx, Lx, H, terrain=500.0, bubble_centre=c,
+                               bubble_amp=rng.uniform(0.1, 2.0))
+
+
+def make(torch, wl, prec, seed):
+    from paper_1511_01561_amd import numa
+    g = numa.Mesh(wl["mesh"], wl["phys"], prec_mask=3)
+    q = g.init_state(wl["ic"], inputs.device_noise(g.n_unique, seed))
+    return g, q, numa.alloc_scratch(g, prec)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("N", [3, 4, 6])
+def test_batch_equals_alone_bitwise(torch_cuda, prec, N):
+    from paper_1511_01561_amd import numa
+    torch = torch_cuda
+    wls = [box(8, N, 1), box(4, N, 2, nz=3), box(12, N, 3, nz=2)]
+    objs = [make(torch, wl, prec, 10 + k) for k, wl in enumerate(wls)]
+    q0 = [q.clone() for _, q, _ in objs]
+    numa.step_batch([(g, q, s, 0.05) for g, q, s in objs], 3, prec)
+    alone = []
+    for (g, _, _), qi in zip(objs, q0):
+        qa = qi.clone()
+        g.step(qa, 0.05, 3, prec=prec)
+        alone.append(qa)
+    torch.cuda.synchronize()
+    for (g, q, _), qa, qi in zip(objs, alone, q0):
+        assert torch.equal(q, qa)
+        assert not torch.equal(q, qi)
+
+
+def test_batch_shares_geometry_between_items(torch_cuda):
+    """Two ensemble members on one geometry: same as running each alone."""
+    from paper_1511_01561_amd import numa
+    torch = torch_cuda
+    wl = box(8, 4, 5)
+    g = numa.Mesh(wl["mesh"], wl["phys"], prec_mask=1)
+    qa = g.init_state(wl["ic"], inputs.device_noise(g.n_unique, 1))
+    qb = g.init_state(wl["ic"], inputs.device_noise(g.n_unique, 2))
+    ra, rb = qa.clone(), qb.clone()
+    numa.step_batch([(g, qa, numa.alloc_scratch(g, 0), 0.05), (g, qb, numa.alloc_scratch(g, 0), 0.05)], 2, 0)
+    g.step(ra, 0.05, 2)
+    g.step(rb, 0.05, 2)
+    torch.cuda.synchronize()
+    assert torch.equal(qa, ra) and torch.equal(qb, rb) and not torch.equal(qa, qb)
+
+
+def test_more_than_one_launch_chunk(torch_cuda):
+    """18 items exceed one launch's 16-entry table: two chunks per stage."""
+    from paper_1511_01561_amd import numa
+    torch = torch_cuda
+    wl = box(4, 3, 7, nz=2)
+    g = numa.Mesh(wl["mesh"], wl["phys"], prec_mask=1)
+    qs = [g.init_state(wl["ic"], inputs.device_noise(g.n_unique, 100 + k)) for k in range(18)]
+    ref = [q.clone() for q in qs]
+    numa.step_batch([(g, q, numa.alloc_scratch(g, 0), 0.05) for q in qs], 2, 0)
+    for r in ref:
+        g.step(r, 0.05, 2)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(qs, ref))
+
+
+def test_graph_replays_match_eager(torch_cuda):
+    """Replay a captured batch step several times with eager work and
+    synchronisations in between; every replay equals the eager result."""
+    from paper_1511_01561_amd import numa
+    torch = torch_cuda
+    wls = [box(8, 4, 11), box(4, 4, 12, nz=3)]
+    objs = [make(torch, wl, 0, 20 + k) for k, wl in enumerate(wls)]
+    eager = [(g, q.clone(), numa.alloc_scratch(g, 0)) for g, q, _ in objs]
+    s = torch.cuda.Stream()
+    graph = numa.Graph([(g, q, sc, 0.05) for g, q, sc in objs], 1, 0, s)
+    for rep in range(3):
+        graph.launch(s)
+        s.synchronize()
+        numa.step_batch([(g, q, sc, 0.05) for g, q, sc in eager], 1, 0)
+        junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64).sum()   # unrelated eager work
+        torch.cuda.synchronize()
+        for (_, qg, _), (_, qe, _) in zip(objs, eager):
+            assert torch.equal(qg, qe), rep
+    graph.close()
+    del junk
+
+
+def test_batch_argument_errors(torch_cuda):
+    from paper_1511_01561_amd import numa
+    g3, q3, s3 = make(torch_cuda, box(4, 3, 1, nz=2), 0, 1)
+    g4, q4, s4 = make(torch_cuda, box(4, 4, 1, nz=2), 0, 2)
+    with pytest.raises(numa.NumaError):
+        numa.step_batch([(g3, q3, s3, 0.05), (g4, q4, s4, 0.05)], 1, 0)       # two orders
+    with pytest.raises(numa.NumaError):
+        numa.step_batch([(g3, q3, s3, 0.05), (g3, q3, numa.alloc_scratch(g3, 0), 0.05)], 1, 0)  # shared state
+    wl = inputs.box_workload(6, 4, 2, 4, 1e4, 1e4, 5e3)    # nx = 6 does not fit the N = 4 segment (4)
+    g6, q6, s6 = make(torch_cuda, wl, 0, 3)
+    with pytest.raises(numa.NumaError):
+        numa.step_batch([(g6, q6, s6, 0.05)], 1, 0)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_serving_results_same_alone_and_in_the_mix(torch_cuda, prec):
+    """A small stream of mixed requests through the serving loop (continuous
+    batching, graphs, admission by footprint), then each request alone."""
+    from paper_1511_01561_amd import numa
+    from paper_1511_01561_amd.serve import GpuExecutor, Request, Server
+    torch = torch_cuda
+    specs = [(8, 3), (4, 4), (8, 4), (12, 3), (4, 3), (8, 4), (4, 6), (8, 6)]
+    reqs = []
+    for i, (n, N) in enumerate(specs):
+        wl = box(n, N, 30 + i, nz=max(2, n // 2))
+        reqs.append(Request(id=i, arrival=0.0, workload=wl, noise_seed=500 + i, steps=4 + (i % 3)))
+    ex = GpuExecutor(prec=prec)
+    # budget for about three of the larger requests at once, so admission binds
+    budget = 3 * ex.request_bytes(reqs[-1], ex.geometry(reqs[-1]))
+    srv = Server(ex, budget_bytes=budget, keep_states=True)
+    srv.prewarm(reqs)
+    st = srv.run(reqs, realtime=False)
+    assert len(st.latencies) == len(reqs) and st.peak_bytes <= budget
+    assert st.max_active >= 2
+    torch.cuda.synchronize()
+    for r in reqs:
+        g = ex.geometry(r)
+        q = g.init_state(r.workload["ic"], inputs.device_noise(g.n_unique, r.noise_seed))
+        g.step(q, 0.05, r.steps, prec=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(q, r.state), r.id
+    ex.drop_graphs()
