@@ -139,6 +139,73 @@ def serving(n_req, budget_gb, precs, loads=(0.5, 0.8), seed=0):
     return out
 
 
+def group_err(a, b):
+    """max|a - b| / max|b| per variable group (rho'; u, v, w; theta')."""
+    import numpy as np
+    out = {}
+    for g, rows in (("rho", [0]), ("u", [1, 2, 3]), ("theta", [4])):
+        den = float(np.abs(b[rows]).max())
+        out[g] = float(np.abs(a[rows] - b[rows]).max()) / den if den > 0 else 0.0
+    return out
+
+
+def sweep(orders, shell_steps, long_steps, oracle_check=True):
+    """Order sweep on the 64x64x16 terrain box and the 6x32x32x10 shell:
+    FP64 and mixed step time, and the mixed result against FP64 after 1 and
+    `long_steps` steps (FP64 GPU result after 1 step also against the oracle)."""
+    import numpy as np
+    import torch
+    from paper_1511_01561_amd import inputs, numa
+    res = {"box": {}, "shell": None}
+
+    def timed(g, q0, prec, dt, steps=5):
+        q = q0.clone()
+        g.step(q, dt, 1, prec=prec)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        g.step(q, dt, steps, prec=prec)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    def run(wl, dt, nlong, name):
+        mm = wl["mesh"]
+        g = numa.Mesh(mm, wl["phys"], prec_mask=3)
+        nz = torch.as_tensor(inputs.noise(g.n_unique, 0), device="cuda:0") if wl["ic"]["noise_amp"] else None
+        q0 = g.init_state(wl["ic"], nz)
+        t64, tmx = timed(g, q0, numa.PREC_FP64, dt), timed(g, q0, numa.PREC_MIXED, dt)
+        rec = {"unique_nodes": g.n_unique, "local_nodes": g.n_local,
+               "fp64_ms_per_step": 1e3 * t64, "mixed_ms_per_step": 1e3 * tmx, "speedup": t64 / tmx,
+               "fp64_updates_per_s": 3 * g.n_unique / t64, "mixed_updates_per_s": 3 * g.n_unique / tmx}
+        h0 = q0.cpu().numpy()
+        for n in (1, nlong):
+            a, b = q0.clone(), q0.clone()
+            g.step(a, dt, n, prec=numa.PREC_FP64)
+            g.step(b, dt, n, prec=numa.PREC_MIXED)
+            A, B = a.cpu().numpy(), b.cpu().numpy()
+            rec["mixed_vs_fp64_state_%d" % n] = group_err(B, A)
+            rec["mixed_vs_fp64_increment_%d" % n] = group_err(B - h0, A - h0)
+            if n == 1 and oracle_check:
+                import oracle
+                om = oracle.OracleMesh(mm["kind"], mm["N"], mm["ne"], mm["periodic"], mm["extent"], mm["h0"],
+                                       wl["phys"])
+                qo = om.step(h0, dt, 1)
+                rec["fp64_vs_oracle_state_1"] = group_err(A, qo)
+                rec["mixed_vs_oracle_increment_1"] = group_err(B - h0, qo - h0)
+                del om
+        _log("%s: fp64 %.3f ms, mixed %.3f ms (x%.2f); mixed-fp64 after %d steps %s"
+             % (name, rec["fp64_ms_per_step"], rec["mixed_ms_per_step"], rec["speedup"], nlong,
+                {k: "%.1e" % v for k, v in rec["mixed_vs_fp64_state_%d" % nlong].items()}))
+        del g
+        torch.cuda.empty_cache()
+        return rec
+
+    for N in orders:
+        res["box"]["N%d" % N] = run(inputs.gpu_box(N), 0.05, long_steps, "box64x64x16 N=%d" % N)
+    if shell_steps:
+        res["shell"] = run(inputs.shell_workload(32, 10, 4, seed=0), 0.5, shell_steps, "shell6x32x32x10 N=4")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +214,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--small", action="store_true", help="4x4x4 box instead of the one-GPU workload")
+    ap.add_argument("--sweep", action="store_true", help="order sweep and shell instead of the bench line")
     ap.add_argument("--serve-requests", type=int, default=100, help="requests per serving run (0: skip)")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -162,6 +230,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     numa.lib()
+    if args.sweep:
+        print(json.dumps(sweep((3, 4, 5, 6, 8), shell_steps=200, long_steps=100)), flush=True)
+        return
     wl = inputs.small_box() if args.small else inputs.gpu_box()
     mm = wl["mesh"]
     workload = "box%dx%dx%d_N%d_terrain%g" % (*mm["ne"], mm["N"], mm["h0"])
