@@ -39,24 +39,26 @@ def source_hash(paths):
     return h.hexdigest()[:16]
 
 
-def element_bytes(nu, nl, prec):
+def element_bytes(nu, nl, prec, metric):
     """Algorithmic HBM bytes of one launch of the element kernel of a fused
-    stage: the unique state (5 x 8 B) and reference (3 x 8 B) read once; per
-    element-local node the gather map (4 B), the metric terms with J w
-    (10 x 8 B, or 10 x 4 B mixed) and the contribution written once
-    (5 x 8 B, or 5 x 4 B mixed)."""
-    met, contrib = (40, 20) if prec == "mixed" else (80, 40)
-    return nu * (40 + 24) + nl * (4 + met + contrib)
+    stage on the box: the unique state (5 x 8 B) and reference (3 x 8 B) read
+    once; per element-local node the contribution written once (5 x 8 B, or
+    5 x 4 B mixed) and, with the stored metric, the 9 inverse-metric entries
+    and J w (10 x 8 B, or 10 x 4 B mixed).  Unique ids follow from the lattice
+    and a recomputed metric costs no traffic."""
+    contrib = 20 if prec == "mixed" else 40
+    met = 0 if metric == "recompute" else (40 if prec == "mixed" else 80)
+    return nu * (40 + 24) + nl * (met + contrib)
 
 
 def finish_bytes(nu, nl, n_wall, prec):
-    """Algorithmic bytes of one finish launch (averaged over the 3 stages):
-    the node order (4 B) and copy offsets (8 B) per unique node, the copy list
-    (4 B) and contribution (5 x 8 B or 5 x 4 B) per element-local node, M^-1
-    (8 B), the stage state, q^n (2 of 3 stages) and the new state (5 x 8 B
-    each) per unique node, and the wall normals."""
+    """Algorithmic bytes of one finish launch on the box (averaged over the 3
+    stages): per unique node M^-1 (8 B), the stage state, q^n (2 of 3 stages)
+    and the new state (5 x 8 B each); per element-local node its contribution
+    (5 x 8 B, or 5 x 4 B mixed); the wall normals.  Copies follow from the
+    lattice position."""
     contrib = 20 if prec == "mixed" else 40
-    return nu * (4 + 8 + 8 + 40 + 40 * 2.0 / 3.0 + 40) + nl * (4 + contrib) + n_wall * 24
+    return nu * (8 + 40 + 40 * 2.0 / 3.0 + 40) + nl * contrib + n_wall * 24
 
 
 def load_traffic(kernel, workload):
@@ -261,50 +263,55 @@ def main():
         assert torch.isfinite(q).all().item()
         return e0.elapsed_time(e1) / 1e3, wall
 
-    gpu_s, wall_s = timed_steps(numa.PREC_FP64)
-    ms_step = 1e3 * wall_s / args.steps
-    value = g.n_unique * 3 * args.steps / wall_s
-    _log("fp64: %.3f ms/step (events %.3f), %.3e updates/s" % (ms_step, 1e3 * gpu_s / args.steps, value))
-
-    mixed = None
-    if not args.no_mixed:
-        mg, mw = timed_steps(numa.PREC_MIXED)
-        mixed = dict(value=g.n_unique * 3 * args.steps / mw, ms_per_step=1e3 * mw / args.steps,
-                     speedup_vs_fp64=wall_s / mw, dtype="f32 contractions / f64 state")
-        _log("mixed: %.3f ms/step, speedup %.2f" % (mixed["ms_per_step"], mixed["speedup_vs_fp64"]))
-
-    # the dominant kernel: per-launch durations of the two stage kernels from
-    # HIP events the library records on the stream it launches them on
     n_wall = 0 if mm["periodic"][2] else 2 * g.n_horiz
-    prof = {}
-    for prec, name in ((numa.PREC_FP64, "fp64"), (numa.PREC_MIXED, "mixed")):
-        if name == "mixed" and args.no_mixed:
-            continue
-        q = q0.clone()
-        g.step(q, dt, 1, prec=prec)
-        torch.cuda.synchronize()
-        g.profile(True)
-        g.step(q, dt, args.steps, prec=prec)
-        el_ms, el_n, fin_ms, fin_n = g.profile_read()
-        g.profile(False)
-        prof[name] = (el_ms / el_n * 1e-3, fin_ms / fin_n * 1e-3)
-        _log("%s stage kernels: element %.1f us, finish %.1f us per launch"
-             % (name, prof[name][0] * 1e6, prof[name][1] * 1e6))
-    el_s, fin_s = prof["fp64"]
-    alg = element_bytes(g.n_unique, g.n_local, "fp64")
-    achieved = alg / el_s / 1e9
-    fin_alg = finish_bytes(g.n_unique, g.n_local, n_wall, "fp64")
-    _log("element kernel %.0f GB/s algorithmic; finish kernel %.0f GB/s" % (achieved, fin_alg / fin_s / 1e9))
-    traffic = load_traffic("stage", workload)
-    roofline = dict(kernel="k_elem_batch<4,double> (element kernel of the fused stage)", bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=traffic, algorithmic_bytes=alg,
-                    avg_launch_us=el_s * 1e6,
-                    finish_kernel=dict(avg_launch_us=fin_s * 1e6, algorithmic_bytes=fin_alg,
-                                       achieved=fin_alg / fin_s / 1e9))
-    if "mixed" in prof and mixed is not None:
-        malg = element_bytes(g.n_unique, g.n_local, "mixed")
-        mixed["element_kernel"] = dict(avg_launch_us=prof["mixed"][0] * 1e6, algorithmic_bytes=malg,
-                                       achieved=malg / prof["mixed"][0] / 1e9)
+
+    def measure(metric):
+        g.set_metric(numa.METRIC_RECOMPUTE if metric == "recompute" else numa.METRIC_STORED)
+        rec = {}
+        for prec, name in ((numa.PREC_FP64, "fp64"), (numa.PREC_MIXED, "mixed")):
+            if name == "mixed" and args.no_mixed:
+                continue
+            gpu_s, wall_s = timed_steps(prec)
+            r = {"value": g.n_unique * 3 * args.steps / wall_s, "ms_per_step": 1e3 * wall_s / args.steps}
+            # per-launch durations of the two stage kernels, from HIP events the
+            # library records on the stream it launches them on
+            q = q0.clone()
+            g.step(q, dt, 1, prec=prec)
+            torch.cuda.synchronize()
+            g.profile(True)
+            g.step(q, dt, args.steps, prec=prec)
+            el_ms, el_n, fin_ms, fin_n = g.profile_read()
+            g.profile(False)
+            el_s, fin_s = el_ms / el_n * 1e-3, fin_ms / fin_n * 1e-3
+            ea = element_bytes(g.n_unique, g.n_local, name, metric)
+            fa = finish_bytes(g.n_unique, g.n_local, n_wall, name)
+            r["element_kernel"] = {"avg_launch_us": el_s * 1e6, "algorithmic_bytes": ea, "achieved_GBs": ea / el_s / 1e9}
+            r["finish_kernel"] = {"avg_launch_us": fin_s * 1e6, "algorithmic_bytes": fa, "achieved_GBs": fa / fin_s / 1e9}
+            _log("%s metric, %s: %.3f ms/step, %.3e updates/s; element %.1f us (%.0f GB/s), finish %.1f us (%.0f GB/s)"
+                 % (metric, name, r["ms_per_step"], r["value"], el_s * 1e6, ea / el_s / 1e9, fin_s * 1e6,
+                    fa / fin_s / 1e9))
+            rec[name] = r
+        if "mixed" in rec:
+            rec["mixed"]["speedup_vs_fp64"] = rec["fp64"]["ms_per_step"] / rec["mixed"]["ms_per_step"]
+        return rec
+
+    stored = measure("stored")
+    recomp = measure("recompute")
+    head = recomp["fp64"]
+    value, ms_step = head["value"], head["ms_per_step"]
+    mixed = recomp.get("mixed")
+    if mixed is not None:
+        mixed["dtype"] = "f32 contractions / f64 state"
+    # roofline of the dominant kernel of the headline path
+    el, fin = head["element_kernel"], head["finish_kernel"]
+    dom_name, dom = (("k_elem_batch<4,double,recomputed metric>", el) if el["avg_launch_us"] >= fin["avg_launch_us"]
+                     else ("k_fin_batch<4,4,double>", fin))
+    traffic = load_traffic("stage", workload) if dom is el else None
+    roofline = dict(kernel=dom_name, bound="hbm", achieved=dom["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=dom["achieved_GBs"] / HBM_PEAK_GBS, traffic=traffic,
+                    algorithmic_bytes=dom["algorithmic_bytes"], avg_launch_us=dom["avg_launch_us"],
+                    other_kernel=(fin if dom is el else el))
+    g.set_metric(numa.METRIC_RECOMPUTE)
 
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 8
@@ -342,8 +349,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": workload, "elements": g.n_elem, "order": mm["N"], "unique_nodes": g.n_unique,
-                   "local_nodes": g.n_local, "dt": dt, "integrator": "SSP-RK3", "parallelism": "single GPU"},
+                   "local_nodes": g.n_local, "dt": dt, "integrator": "SSP-RK3", "metric": "recomputed each stage",
+                   "parallelism": "single GPU"},
         "mixed": mixed,
+        "stored_metric": stored,
         "roofline": roofline,
         "serving": serve,
         "cpu_baseline": cpu,

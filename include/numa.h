@@ -50,6 +50,9 @@ extern "C" {
 #define NUMA_PREC_FP64 0    /* everything in FP64 */
 #define NUMA_PREC_MIXED 1   /* contractions, metric products and fluxes in FP32 */
 
+#define NUMA_METRIC_STORED 0     /* metric terms and J w read per element-local node */
+#define NUMA_METRIC_RECOMPUTE 1  /* box: recomputed in the element kernel every stage */
+
 #define NUMA_DSS_MASS 1     /* divide the summed contributions by the mass matrix */
 #define NUMA_DSS_NOFLUX 2   /* project components 1..3 of a 5-variable field at walls */
 
@@ -136,6 +139,16 @@ int32_t numa_mesh_attach_workspace(numa_mesh_t m, void *dev_ptr, uint64_t bytes,
  * M_I = sum_e w_ijk J^e (Eq. (discstrongform)) and its inverse, the reference
  * state, gravity and wall normals, into the workspace.  Asynchronous. */
 int32_t numa_geometry(numa_mesh_t m, const numa_phys *ph, void *stream);
+
+/* Metric terms of the element kernels (numa_rhs, numa_step, numa_step_batch).
+ * NUMA_METRIC_STORED (default) reads the 9 inverse-metric entries and J w
+ * computed by numa_geometry at every element-local node.  NUMA_METRIC_RECOMPUTE
+ * (box meshes) recomputes the same isoparametric metric of the
+ * terrain-following map in the kernel every stage from 2(N+1) sines per
+ * element, so the metric costs no memory traffic (the paper's next step,
+ * Sec. "Next Steps": recompute the metric terms in each stage).  Host only;
+ * returns NUMA_EUNSUPPORTED on a shell. */
+int32_t numa_mesh_set_metric(numa_mesh_t m, int32_t mode);
 
 /* Copy an internal field (NUMA_FIELD_*) to a caller device buffer. */
 int32_t numa_export(numa_mesh_t m, int32_t what, void *dev_out, void *stream);

@@ -177,6 +177,24 @@ int32_t numa_mesh_attach_workspace(numa_mesh_t m, void *dev_ptr, uint64_t bytes,
     return NUMA_OK;
 }
 
+int32_t numa_mesh_set_metric(numa_mesh_t m, int32_t mode)
+{
+    if (!m) {
+        set_error("numa_mesh_set_metric: null mesh handle");
+        return NUMA_EINVAL;
+    }
+    if (mode != NUMA_METRIC_STORED && mode != NUMA_METRIC_RECOMPUTE) {
+        set_error("numa_mesh_set_metric: unknown mode %d", mode);
+        return NUMA_EINVAL;
+    }
+    if (mode == NUMA_METRIC_RECOMPUTE && m->d.kind != NUMA_MESH_BOX) {
+        set_error("numa_mesh_set_metric: the recomputed metric is available for box meshes only");
+        return NUMA_EUNSUPPORTED;
+    }
+    m->metric_mode = mode;
+    return NUMA_OK;
+}
+
 int32_t numa_geometry(numa_mesh_t m, const numa_phys *ph, void *stream)
 {
     if (!m || !ph) {
@@ -383,6 +401,10 @@ static int32_t check_batch(const numa_batch_item *items, int32_t n, int32_t prec
         }
         if (m->N != items[0].mesh->N) {
             set_error("%s: item %d has order %d, item 0 has %d (one order per batch)", fn, k, m->N, items[0].mesh->N);
+            return NUMA_EINVAL;
+        }
+        if (m->metric_mode != items[0].mesh->metric_mode) {
+            set_error("%s: item %d uses another metric mode than item 0 (one mode per batch)", fn, k);
             return NUMA_EINVAL;
         }
         if (!items[k].q || !items[k].scratch || reinterpret_cast<uintptr_t>(items[k].scratch) % 256) {

@@ -27,6 +27,7 @@ struct BatchItem {
     int64_t nl, nu, nh, ni, nj, nkw;  // nkw: lattice extent in z when periodic, else -1
     int nx, ny, nz, walls;
     double dt;
+    double Lx, Ly, H, h0;  // box extents and terrain amplitude (recomputed metric)
     int64_t eoff, boff;  // first element / finish block of this item in the launch
 };
 
@@ -34,10 +35,11 @@ struct Batch {
     int n, stage;
     double gamma, g0;
     const void *D;
+    const double *xi, *w, *Dd;  // FP64 GLL nodes, weights, derivative matrix
     BatchItem it[kMaxBatch];
 };
 
-template <int N, typename T>
+template <int N, typename T, int GEO>
 __global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
 {
     constexpr int NP = (N + 1) * (N + 1) * (N + 1);
@@ -63,8 +65,16 @@ __global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
     a.ni = it.ni;
     a.nj = it.nj;
     a.nk = it.nkw;
+    a.nz = it.nz;
+    a.Lx = it.Lx;
+    a.Ly = it.Ly;
+    a.H = it.H;
+    a.h0 = it.h0;
+    a.xi = B.xi;
+    a.w = B.w;
+    a.Dd = B.Dd;
     NodeOut<T> o;
-    if (!element_rhs<N, T, false>(a, e, threadIdx.x, s, o)) return;
+    if (!element_rhs<N, T, false, GEO>(a, e, threadIdx.x, s, o)) return;
     T *p = (T *)it.ev + e * NP + threadIdx.x;
 #pragma unroll
     for (int v = 0; v < 5; ++v) p[v * it.nl] = o.Jw * o.R[v];
@@ -116,6 +126,9 @@ int32_t run_chunk(const StepItem *items, int n, int stage, int phase, hipStream_
     B.gamma = items[0].mesh->gamma;
     B.g0 = items[0].mesh->ph.g0;
     B.D = std::is_same<T, float>::value ? (const void *)items[0].mesh->dv.D32 : (const void *)items[0].mesh->dv.D64;
+    B.xi = items[0].mesh->dv.xi64;
+    B.w = items[0].mesh->dv.w64;
+    B.Dd = items[0].mesh->dv.D64;
     int64_t eo = 0, bo = 0;
     for (int k = 0; k < n; ++k) {
         const Mesh &m = *items[k].mesh;
@@ -139,6 +152,10 @@ int32_t run_chunk(const StepItem *items, int n, int stage, int phase, hipStream_
         it.nz = m.d.ne[2];
         it.walls = m.walls ? 1 : 0;
         it.dt = items[k].dt;
+        it.Lx = m.d.extent[0];
+        it.Ly = m.d.extent[1];
+        it.H = m.d.extent[2];
+        it.h0 = m.d.terrain_amp;
         it.eoff = eo;
         it.boff = bo;
         eo += m.ne;
@@ -146,7 +163,11 @@ int32_t run_chunk(const StepItem *items, int n, int stage, int phase, hipStream_
     }
     for (int k = n; k < kMaxBatch; ++k) B.it[k] = BatchItem{};
     if (phase == 0) {
-        hipLaunchKernelGGL((k_elem_batch<N, T>), dim3((unsigned)eo), dim3(block_threads<N>()), 0, s, B);
+        if (items[0].mesh->metric_mode == NUMA_METRIC_RECOMPUTE)
+            hipLaunchKernelGGL((k_elem_batch<N, T, kMetricBox>), dim3((unsigned)eo), dim3(block_threads<N>()), 0, s, B);
+        else
+            hipLaunchKernelGGL((k_elem_batch<N, T, kMetricStored>), dim3((unsigned)eo), dim3(block_threads<N>()), 0, s,
+                               B);
     } else {
         const int threads = ((SEG * N * N * N + 63) / 64) * 64;
         hipLaunchKernelGGL((k_fin_batch<N, SEG, T>), dim3((unsigned)bo), dim3(threads), 0, s, B);

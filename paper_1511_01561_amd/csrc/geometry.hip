@@ -390,6 +390,8 @@ int32_t launch_geometry(Mesh &m, hipStream_t s)
         m.D32.assign(m.D, m.D + m.P * m.P);
         NUMA_HIP(hipMemcpyAsync(v.D64, m.D, 8 * m.P * m.P, hipMemcpyHostToDevice, s));
         NUMA_HIP(hipMemcpyAsync(v.D32, m.D32.data(), 4 * m.P * m.P, hipMemcpyHostToDevice, s));
+        NUMA_HIP(hipMemcpyAsync(v.xi64, m.xi, 8 * m.P, hipMemcpyHostToDevice, s));
+        NUMA_HIP(hipMemcpyAsync(v.w64, m.w, 8 * m.P, hipMemcpyHostToDevice, s));
         // the pageable-memory copies above must finish before the host vectors can change
         NUMA_HIP(hipStreamSynchronize(s));
         m.uploaded = true;

@@ -18,9 +18,25 @@ struct RhsArgs {
     const T *D;
     int64_t nl, nu;
     double gamma, g0;
-    int nx, ny;          // box: elements along x and y
+    int nx, ny, nz;      // box: elements along x, y, z
     int64_t ni, nj, nk;  // box: lattice extents (x, y periodic)
+    // box metric recomputed in the kernel: extents, terrain amplitude, GLL nodes and weights
+    double Lx, Ly, H, h0;
+    const double *xi, *w, *Dd;  // FP64 nodes, weights, derivative matrix
 };
+
+// Metric of a box element: stored per node (the general path), or recomputed
+// from the terrain-following map z' = z + h(x, y)(1 - z/H).
+enum { kMetricStored = 0, kMetricBox = 1 };
+
+// position of lattice index c (0..ncell*N) in element units, e_c + (1 + xi_i)/2,
+// e_c clamped to the last element (the node coordinates of the mesh numbering)
+__device__ __forceinline__ double lattice_pos(int64_t c, int N, int ncell, const double *xi)
+{
+    int64_t e = c / N;
+    if (e > ncell - 1) e = ncell - 1;
+    return (double)e + (1.0 + xi[c - (int64_t)N * e]) / 2.0;
+}
 
 // unique id of local node (i, j, k) of box element e: the element's lattice
 // corner plus the local offset, wrapped in the periodic directions
@@ -50,21 +66,45 @@ struct NodeOut {
 // Gathers the element tile, differentiates it and evaluates R at node l of
 // element e.  Must be called by all lanes of the block (it synchronises);
 // returns false for the padding lanes (l >= (N+1)^3).
-template <int N, typename T, bool SHELL>
+//
+// GEO == kMetricBox (box meshes): the isoparametric metric of the map
+// x = x(xi), y = y(eta), z' = z(zeta) + h(x, y)(1 - z/H) with
+// h = h0 sin(2 pi x/Lx) sin(2 pi y/Ly) is computed from 2(N+1) sines per
+// element instead of being read: x_xi = Lx/(2 nx), y_eta = Ly/(2 ny),
+// z_xi = (1 - z/H) dh/dxi, z_eta = (1 - z/H) dh/deta (D contractions of the
+// nodal h), z_zeta = (1 - h/H) H/(2 nz); J = x_xi y_eta z_zeta and the inverse
+// has xi_x = 1/x_xi, eta_y = 1/y_eta, zeta = (-z_xi/(x_xi z_zeta),
+// -z_eta/(y_eta z_zeta), 1/z_zeta), all other entries zero.
+template <int N, typename T, bool SHELL, int GEO = kMetricStored>
 __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int l, T (*s)[(N + 1) * (N + 1) * (N + 1)],
                                             NodeOut<T> &o)
 {
     constexpr int P = N + 1, NP = P * P * P, NF = SHELL ? 9 : 8;
+    __shared__ double sn[2 * P];  // GEO == kMetricBox: sin(2 pi x_i/Lx), sin(2 pi y_j/Ly)
     const bool act = l < NP;
     double rp = 0.0, rho = 1.0, u = 0.0, v = 0.0, w = 0.0, tp = 0.0;
     int64_t I = 0;
     // metric terms do not depend on the tile: load them before the barrier so
     // their latency overlaps the state gather and the equation of state
     T mx[10];
-    if (act) {
-        const T *mp = a.met + e * 10 * NP + l;
+    if constexpr (GEO == kMetricStored) {
+        if (act) {
+            const T *mp = a.met + e * 10 * NP + l;
 #pragma unroll
-        for (int c = 0; c < 10; ++c) mx[c] = mp[c * NP];
+            for (int c = 0; c < 10; ++c) mx[c] = mp[c * NP];
+        }
+    } else {
+        if (l < 2 * P) {
+            const double kTwoPi = 6.283185307179586476925286766559;
+            const int64_t ex = e % a.nx, ey = (e / a.nx) % a.ny;
+            if (l < P) {
+                const double x = a.Lx * lattice_pos(ex * N + l, N, a.nx, a.xi) / a.nx;
+                sn[l] = sin(kTwoPi * x / a.Lx);
+            } else {
+                const double y = a.Ly * lattice_pos(ey * N + (l - P), N, a.ny, a.xi) / a.ny;
+                sn[l] = sin(kTwoPi * y / a.Ly);
+            }
+        }
     }
     if (act) {
         if constexpr (SHELL) {
@@ -107,6 +147,29 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
         Dj[m] = a.D[j * P + m];
         Dk[m] = a.D[k * P + m];
     }
+    if constexpr (GEO == kMetricBox) {
+        // D contractions of the nodal sines along xi and eta (FP64)
+        double dsx = 0.0, dsy = 0.0;
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+            dsx += a.Dd[i * P + m] * sn[m];
+            dsy += a.Dd[j * P + m] * sn[P + m];
+        }
+        const int64_t ez = e / ((int64_t)a.nx * a.ny);
+        const double zk = a.H * lattice_pos(ez * N + k, N, a.nz, a.xi) / a.nz;
+        const double h = a.h0 * sn[i] * sn[P + j];
+        const double omz = 1.0 - zk / a.H;
+        const double xa = a.Lx / (2.0 * a.nx), yb = a.Ly / (2.0 * a.ny);
+        const double za = omz * a.h0 * sn[P + j] * dsx, zb = omz * a.h0 * sn[i] * dsy;
+        const double zc = (1.0 - h / a.H) * (a.H / (2.0 * a.nz));
+        const double izc = 1.0 / zc;
+        mx[0] = (T)(1.0 / xa);
+        mx[4] = (T)(1.0 / yb);
+        mx[6] = (T)(-za / xa * izc);
+        mx[7] = (T)(-zb / yb * izc);
+        mx[8] = (T)izc;
+        mx[9] = (T)(xa * yb * zc * (a.w[i] * a.w[j] * a.w[k]));
+    }
     T dx[NF], dy[NF], dz[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -117,9 +180,15 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
             db += Dj[m] * s[f][i + P * (m + P * k)];
             dc += Dk[m] * s[f][i + P * (j + P * m)];
         }
-        dx[f] = da * mx[0] + db * mx[3] + dc * mx[6];
-        dy[f] = da * mx[1] + db * mx[4] + dc * mx[7];
-        dz[f] = da * mx[2] + db * mx[5] + dc * mx[8];
+        if constexpr (GEO == kMetricBox) {
+            dx[f] = da * mx[0] + dc * mx[6];
+            dy[f] = db * mx[4] + dc * mx[7];
+            dz[f] = dc * mx[8];
+        } else {
+            dx[f] = da * mx[0] + db * mx[3] + dc * mx[6];
+            dy[f] = da * mx[1] + db * mx[4] + dc * mx[7];
+            dz[f] = da * mx[2] + db * mx[5] + dc * mx[8];
+        }
     }
     const T irho = (T)(1.0 / rho);
     const T buoy = (T)(rp / rho);

@@ -286,6 +286,8 @@ uint64_t layout_workspace(Mesh &m, int32_t prec_mask, char *base)
     v.qs = (double *)take(40ull * m.nu);
     v.D64 = (double *)take(8ull * kMaxP * kMaxP);
     v.D32 = (float *)take(4ull * kMaxP * kMaxP);
+    v.xi64 = (double *)take(8ull * kMaxP);
+    v.w64 = (double *)take(8ull * kMaxP);
     if (base) m.dv = v;
     return o;
 }

@@ -60,6 +60,8 @@ struct DeviceView {
     float *ev32 = nullptr;     // same, mixed path
     double *qs = nullptr;      // [5][n_unique] stage state scratch
     double *D64 = nullptr;     // [(N+1)^2] derivative matrix
+    double *xi64 = nullptr;    // [N+1] GLL nodes
+    double *w64 = nullptr;     // [N+1] GLL weights
     float *D32 = nullptr;      // same, FP32
 };
 
@@ -84,6 +86,7 @@ struct Mesh {
     int32_t prec_mask = 0;
     DeviceView dv;
     bool uploaded = false, geom = false;
+    int metric_mode = 0;  // NUMA_METRIC_STORED or NUMA_METRIC_RECOMPUTE (box)
     numa_phys ph{};
     double gamma = 0.0;
 };

@@ -22,7 +22,7 @@ namespace {
 
 using namespace dev;
 
-template <int N, typename T, typename TO, bool SHELL>
+template <int N, typename T, typename TO, bool SHELL, int GEO>
 __global__ __launch_bounds__(block_threads<N>()) void k_rhs(RhsArgs<T> a, TO *out)
 {
     constexpr int NP = (N + 1) * (N + 1) * (N + 1), NF = SHELL ? 9 : 8;
@@ -30,7 +30,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_rhs(RhsArgs<T> a, TO *ou
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
     const int l = threadIdx.x;
     NodeOut<T> o;
-    if (!element_rhs<N, T, SHELL>(a, e, l, s, o)) return;
+    if (!element_rhs<N, T, SHELL, GEO>(a, e, l, s, o)) return;
     TO *p = out + e * NP + l;
 #pragma unroll
     for (int v = 0; v < 5; ++v) p[v * a.nl] = (TO)(o.Jw * o.R[v]);
@@ -40,8 +40,12 @@ template <int N, typename T, typename TO>
 void launch_n(Mesh &m, const RhsArgs<T> &a, TO *out, hipStream_t s)
 {
     dim3 grid((unsigned)m.ne), block(block_threads<N>());
-    if (m.d.kind == NUMA_MESH_SHELL) hipLaunchKernelGGL((k_rhs<N, T, TO, true>), grid, block, 0, s, a, out);
-    else hipLaunchKernelGGL((k_rhs<N, T, TO, false>), grid, block, 0, s, a, out);
+    if (m.d.kind == NUMA_MESH_SHELL)
+        hipLaunchKernelGGL((k_rhs<N, T, TO, true, kMetricStored>), grid, block, 0, s, a, out);
+    else if (m.metric_mode == NUMA_METRIC_RECOMPUTE)
+        hipLaunchKernelGGL((k_rhs<N, T, TO, false, kMetricBox>), grid, block, 0, s, a, out);
+    else
+        hipLaunchKernelGGL((k_rhs<N, T, TO, false, kMetricStored>), grid, block, 0, s, a, out);
 }
 
 template <typename T, typename TO>
@@ -60,6 +64,14 @@ void launch_t(Mesh &m, const T *met, const T *D, const double *q, TO *out, hipSt
     a.g0 = m.ph.g0;
     a.nx = m.d.ne[0];
     a.ny = m.d.ne[1];
+    a.nz = m.d.ne[2];
+    a.Lx = m.d.extent[0];
+    a.Ly = m.d.extent[1];
+    a.H = m.d.extent[2];
+    a.h0 = m.d.terrain_amp;
+    a.xi = m.dv.xi64;
+    a.w = m.dv.w64;
+    a.Dd = m.dv.D64;
     a.ni = m.ni;
     a.nj = m.nj;
     a.nk = m.d.periodic[2] ? m.nk : -1;  // only a periodic z wraps

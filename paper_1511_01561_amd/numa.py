@@ -17,13 +17,15 @@ NUMA_OK = 0
 MESH_BOX, MESH_SHELL = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 DSS_MASS, DSS_NOFLUX = 1, 2
+METRIC_STORED, METRIC_RECOMPUTE = 0, 1
 FIELD_MASS, FIELD_REF, FIELD_COORDS, FIELD_METRIC, FIELD_GRAVITY, FIELD_LOCAL_COORDS = range(6)
 
 EXPORTED = ["numa_last_error", "numa_gll", "numa_mesh_create", "numa_mesh_destroy", "numa_mesh_info",
             "numa_mesh_gather_map", "numa_mesh_workspace_bytes", "numa_mesh_attach_workspace",
             "numa_geometry", "numa_export", "numa_init_state", "numa_rhs", "numa_dss",
             "numa_rk_stage", "numa_step", "numa_profile", "numa_profile_read", "numa_step_scratch_bytes",
-            "numa_step_batch", "numa_batch_capture", "numa_graph_launch", "numa_graph_destroy"]
+            "numa_step_batch", "numa_batch_capture", "numa_graph_launch", "numa_graph_destroy",
+            "numa_mesh_set_metric"]
 
 
 class numa_mesh_desc(ct.Structure):
@@ -85,6 +87,7 @@ def lib():
         "numa_batch_capture": (I32, [ct.POINTER(numa_batch_item), I32, I32, I32, P, ct.POINTER(P)]),
         "numa_graph_launch": (I32, [P, P]),
         "numa_graph_destroy": (I32, [P]),
+        "numa_mesh_set_metric": (I32, [P, I32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -212,6 +215,10 @@ class Mesh:
         check(lib().numa_rk_stage(self._h, stage, float(dt), _ptr(qn), _ptr(qs), _ptr(r), _ptr(out),
                                   _stream(stream)))
         return out
+
+    def set_metric(self, mode: int):
+        """METRIC_STORED or METRIC_RECOMPUTE (box meshes)."""
+        check(lib().numa_mesh_set_metric(self._h, mode))
 
     def profile(self, enable: bool):
         check(lib().numa_profile(self._h, 1 if enable else 0))

@@ -1,0 +1,103 @@
+"""The recomputed box metric (NUMA_METRIC_RECOMPUTE) against the FP64 oracle,
+whose metric is the stored isoparametric one: same tolerances as the stored
+path (FP64 1e-12 per variable group, mixed 1e-5)."""
+import numpy as np
+import pytest
+
+from paper_1511_01561_amd import inputs
+from test_gpu_parity import TOL64, TOLMIX, Pair, assert_groups, group_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def terrain_box(N, ne=(4, 3, 3), perz=False, h0=400.0):
+    return inputs.box_workload(*ne, N, 12e3, 9e3, 6e3, terrain=h0, bubble_centre=(6e3, 4.5e3, 2e3),
+                               bubble_radius=2.5e3, periodic_z=perz)
+
+
+def recompute_pair(wl, oracle_mod):
+    from paper_1511_01561_amd import numa
+    p = Pair(wl, oracle_mod)
+    p.g.set_metric(numa.METRIC_RECOMPUTE)
+    return p
+
+
+@pytest.mark.parametrize("N", range(1, 9))
+def test_rhs_parity_recomputed_metric(torch_cuda, oracle_mod, N):
+    p = recompute_pair(terrain_box(N), oracle_mod)
+    q = inputs.random_state(p.nu, seed=40 + N)
+    Co = p.o.rhs(q)
+    assert_groups(p.host(p.g.rhs(p.dev(q))), Co, TOL64, "recomputed rhs N=%d" % N)
+
+
+@pytest.mark.parametrize("N", [3, 4, 6, 8])
+def test_rhs_mixed_recomputed_metric(torch_cuda, oracle_mod, N):
+    from paper_1511_01561_amd import numa
+    p = recompute_pair(terrain_box(N), oracle_mod)
+    q = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 2))
+    Co = p.o.rhs(q)
+    assert_groups(p.host(p.g.rhs(p.dev(q), prec=numa.PREC_MIXED)), Co, TOLMIX, "recomputed mixed rhs N=%d" % N)
+
+
+def test_undeformed_box_recomputed_metric(torch_cuda, oracle_mod):
+    p = recompute_pair(inputs.small_box(), oracle_mod)
+    q = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 0))
+    assert_groups(p.host(p.g.rhs(p.dev(q))), p.o.rhs(q), TOL64, "undeformed recomputed rhs")
+    # rest state stays exactly at rest
+    assert np.all(p.host(p.g.rhs(p.dev(np.zeros((5, p.nu))))) == 0.0)
+
+
+@pytest.mark.parametrize("N,ne,perz", [(2, (8, 4, 3), False), (4, (8, 4, 2), True), (5, (4, 3, 2), False),
+                                       (4, (6, 4, 3), False)])
+def test_step_parity_recomputed_metric(torch_cuda, oracle_mod, N, ne, perz):
+    p = recompute_pair(terrain_box(N, ne, perz), oracle_mod)
+    q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, N))
+    qo = p.o.step(q0, 0.05, 3)
+    qg = p.dev(q0)
+    p.g.step(qg, 0.05, 3)
+    assert_groups(p.host(qg), qo, TOL64, "recomputed step N=%d ne=%s" % (N, ne))
+
+
+def test_full_size_recomputed_metric(torch_cuda, oracle_mod):
+    p = recompute_pair(inputs.gpu_box(), oracle_mod)
+    q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 0))
+    assert_groups(p.host(p.g.rhs(p.dev(q0))), p.o.rhs(q0), TOL64, "full recomputed rhs")
+    qo = p.o.step(q0, 0.05, 2)
+    qg = p.dev(q0)
+    p.g.step(qg, 0.05, 2)
+    assert_groups(p.host(qg), qo, TOL64, "full recomputed 2-step state")
+
+
+def test_recomputed_batch_equals_alone(torch_cuda):
+    from paper_1511_01561_amd import numa
+    torch = torch_cuda
+    objs = []
+    for k, (n, nz) in enumerate(((8, 4), (4, 3), (12, 2))):
+        wl = inputs.box_workload(n, n, nz, 4, n * 6250.0, n * 6250.0, nz * 1250.0, terrain=500.0,
+                                 bubble_centre=(n * 3000.0, n * 3000.0, nz * 600.0))
+        g = numa.Mesh(wl["mesh"], wl["phys"], prec_mask=1)
+        g.set_metric(numa.METRIC_RECOMPUTE)
+        q = g.init_state(wl["ic"], inputs.device_noise(g.n_unique, k))
+        objs.append((g, q, numa.alloc_scratch(g, 0)))
+    alone = [q.clone() for _, q, _ in objs]
+    numa.step_batch([(g, q, s, 0.05) for g, q, s in objs], 2, 0)
+    for (g, _, _), a in zip(objs, alone):
+        g.step(a, 0.05, 2)
+    torch.cuda.synchronize()
+    assert all(torch.equal(q, a) for (_, q, _), a in zip(objs, alone))
+
+
+def test_shell_refuses_recomputed_metric(torch_cuda):
+    from paper_1511_01561_amd import numa
+    wl = inputs.shell_workload(ne=2, nz=1, N=2)
+    g = numa.Mesh(wl["mesh"], wl["phys"], prec_mask=1)
+    with pytest.raises(numa.NumaError):
+        g.set_metric(numa.METRIC_RECOMPUTE)
