@@ -27,7 +27,7 @@ struct BatchItem {
     int64_t nl, nu, nh, ni, nj, nkw;  // nkw: lattice extent in z when periodic, else -1
     int nx, ny, nz, walls;
     double dt;
-    double Lx, Ly, H, h0;  // box extents and terrain amplitude (recomputed metric)
+    BoxMetric bm;  // constants of the recomputed metric
     int64_t eoff, boff;  // first element / finish block of this item in the launch
 };
 
@@ -36,8 +36,10 @@ struct Batch {
     double gamma, g0;
     const void *D;
     const double *xi, *w, *Dd;  // FP64 GLL nodes, weights, derivative matrix
+    double eos[kEosTerms];
     BatchItem it[kMaxBatch];
 };
+static_assert(sizeof(Batch) <= 4096, "the batch table must fit the kernel arguments");
 
 template <int N, typename T, int GEO>
 __global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
@@ -66,10 +68,9 @@ __global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
     a.nj = it.nj;
     a.nk = it.nkw;
     a.nz = it.nz;
-    a.Lx = it.Lx;
-    a.Ly = it.Ly;
-    a.H = it.H;
-    a.h0 = it.h0;
+    a.bm = it.bm;
+#pragma unroll
+    for (int c = 0; c < kEosTerms; ++c) a.eos[c] = B.eos[c];
     a.xi = B.xi;
     a.w = B.w;
     a.Dd = B.Dd;
@@ -129,6 +130,7 @@ int32_t run_chunk(const StepItem *items, int n, int stage, int phase, hipStream_
     B.xi = items[0].mesh->dv.xi64;
     B.w = items[0].mesh->dv.w64;
     B.Dd = items[0].mesh->dv.D64;
+    eos_coeffs(B.gamma, B.eos);
     int64_t eo = 0, bo = 0;
     for (int k = 0; k < n; ++k) {
         const Mesh &m = *items[k].mesh;
@@ -152,10 +154,7 @@ int32_t run_chunk(const StepItem *items, int n, int stage, int phase, hipStream_
         it.nz = m.d.ne[2];
         it.walls = m.walls ? 1 : 0;
         it.dt = items[k].dt;
-        it.Lx = m.d.extent[0];
-        it.Ly = m.d.extent[1];
-        it.H = m.d.extent[2];
-        it.h0 = m.d.terrain_amp;
+        it.bm = box_metric(m);
         it.eoff = eo;
         it.boff = bo;
         eo += m.ne;

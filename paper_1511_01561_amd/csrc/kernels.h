@@ -10,6 +10,55 @@
 namespace numa {
 namespace dev {
 
+// Per-mesh constants of the recomputed box metric (host-computed, so the
+// kernel divides once per node): x_xi = Lx/(2 nx), y_eta = Ly/(2 ny),
+// z_zeta of the undeformed map H/(2 nz), and the angular steps of the terrain.
+struct BoxMetric {
+    double xa, ixa, yb, iyb, zz, inz, iH, h0, kx, ky;  // kx = 2 pi/nx, ky = 2 pi/ny
+};
+
+// (1 + x)^gamma - 1 by its binomial series sum_k c_k x^k, c_1 = gamma,
+// c_{k+1} = c_k (gamma - k)/(k + 1), used for |x| < 1/64 where ten terms leave a
+// truncation error below 1e-19 relative (|c_11| |x|^11 < 1e-22 against
+// |(1 + x)^gamma - 1| > 0.01 |x| for gamma in (1, 2]); otherwise
+// expm1(gamma log1p(x)).  This is the pressure perturbation of the equation of
+// state p = p0 (R rho theta / p0)^gamma about the reference, without cancellation.
+constexpr int kEosTerms = 10;
+__device__ __forceinline__ double eos_rel(double x, double gamma, const double *c)
+{
+    if (fabs(x) < 0.015625) {
+        double r = c[kEosTerms - 1];
+#pragma unroll
+        for (int k = kEosTerms - 2; k >= 0; --k) r = r * x + c[k];
+        return r * x;
+    }
+    return expm1(gamma * log1p(x));
+}
+
+// host: constants of the recomputed metric of a box mesh, series coefficients
+inline BoxMetric box_metric(const Mesh &m)
+{
+    const double kTwoPi = 6.283185307179586476925286766559;
+    BoxMetric b;
+    b.xa = m.d.extent[0] / (2.0 * m.d.ne[0]);
+    b.ixa = 1.0 / b.xa;
+    b.yb = m.d.extent[1] / (2.0 * m.d.ne[1]);
+    b.iyb = 1.0 / b.yb;
+    b.zz = m.d.extent[2] / (2.0 * m.d.ne[2]);
+    b.inz = 1.0 / m.d.ne[2];
+    b.iH = 1.0 / m.d.extent[2];
+    b.h0 = m.d.terrain_amp;
+    b.kx = kTwoPi / m.d.ne[0];
+    b.ky = kTwoPi / m.d.ne[1];
+    return b;
+}
+
+inline void eos_coeffs(double gamma, double *c)
+{
+    c[0] = gamma;
+    for (int k = 1; k < kEosTerms; ++k) c[k] = c[k - 1] * (gamma - k) / (k + 1);
+}
+
 template <typename T>
 struct RhsArgs {
     const int32_t *G;  // gather map (shell); the box computes unique ids from its lattice
@@ -20,9 +69,9 @@ struct RhsArgs {
     double gamma, g0;
     int nx, ny, nz;      // box: elements along x, y, z
     int64_t ni, nj, nk;  // box: lattice extents (x, y periodic)
-    // box metric recomputed in the kernel: extents, terrain amplitude, GLL nodes and weights
-    double Lx, Ly, H, h0;
-    const double *xi, *w, *Dd;  // FP64 nodes, weights, derivative matrix
+    const double *xi, *w, *Dd;  // FP64 GLL nodes, weights, derivative matrix
+    BoxMetric bm;               // box: constants of the recomputed metric
+    double eos[kEosTerms];      // coefficients of the binomial series of (1 + x)^gamma - 1
 };
 
 // Metric of a box element: stored per node (the general path), or recomputed
@@ -80,7 +129,8 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
                                             NodeOut<T> &o)
 {
     constexpr int P = N + 1, NP = P * P * P, NF = SHELL ? 9 : 8;
-    __shared__ double sn[2 * P];  // GEO == kMetricBox: sin(2 pi x_i/Lx), sin(2 pi y_j/Ly)
+    // GEO == kMetricBox: sin(2 pi x_i/Lx), sin(2 pi y_j/Ly), then their D contractions
+    __shared__ double sn[2 * P], dsn[2 * P];
     const bool act = l < NP;
     double rp = 0.0, rho = 1.0, u = 0.0, v = 0.0, w = 0.0, tp = 0.0;
     int64_t I = 0;
@@ -93,36 +143,42 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
 #pragma unroll
             for (int c = 0; c < 10; ++c) mx[c] = mp[c * NP];
         }
-    } else {
-        if (l < 2 * P) {
-            const double kTwoPi = 6.283185307179586476925286766559;
-            const int64_t ex = e % a.nx, ey = (e / a.nx) % a.ny;
-            if (l < P) {
-                const double x = a.Lx * lattice_pos(ex * N + l, N, a.nx, a.xi) / a.nx;
-                sn[l] = sin(kTwoPi * x / a.Lx);
-            } else {
-                const double y = a.Ly * lattice_pos(ey * N + (l - P), N, a.ny, a.xi) / a.ny;
-                sn[l] = sin(kTwoPi * y / a.Ly);
-            }
-        }
     }
     if (act) {
         if constexpr (SHELL) {
             I = a.G[e * NP + l];
         } else {
-            constexpr int P_ = N + 1;
-            I = box_unique<N, T>(a, e, l % P_, (l / P_) % P_, l / (P_ * P_));
+            I = box_unique<N, T>(a, e, l % P, (l / P) % P, l / (P * P));
         }
         rp = a.q[I];
         u = a.q[a.nu + I];
         v = a.q[2 * a.nu + I];
         w = a.q[3 * a.nu + I];
         tp = a.q[4 * a.nu + I];
+    }
+    if constexpr (GEO == kMetricBox) {
+        // the terrain sines along the element's x and y lines, then their D
+        // contractions (once per element; the state loads are in flight)
+        if (l < 2 * P) {
+            const int64_t ex = e % a.nx, ey = (e / a.nx) % a.ny;
+            sn[l] = l < P ? sin(a.bm.kx * lattice_pos(ex * N + l, N, a.nx, a.xi))
+                          : sin(a.bm.ky * lattice_pos(ey * N + (l - P), N, a.ny, a.xi));
+        }
+        __syncthreads();
+        if (l < 2 * P) {
+            const int r = l < P ? l : l - P, b0 = l < P ? 0 : P;
+            double d = 0.0;
+#pragma unroll
+            for (int m = 0; m < P; ++m) d += a.Dd[r * P + m] * sn[b0 + m];
+            dsn[l] = d;
+        }
+    }
+    if (act) {
         const double rb = a.ref[I], tb = a.ref[a.nu + I], pb = a.ref[2 * a.nu + I];
         rho = rb + rp;
         // p' = p_bar ((rho theta / rho_bar theta_bar)^gamma - 1) without cancellation
         const double dl = rp * tb + rb * tp + rp * tp;
-        const double pp = pb * expm1(a.gamma * log1p(dl / (rb * tb)));
+        const double pp = pb * eos_rel(dl / (rb * tb), a.gamma, a.eos);
         s[0][l] = (T)(rho * u);
         s[1][l] = (T)(rho * v);
         s[2][l] = (T)(rho * w);
@@ -148,29 +204,36 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
         Dk[m] = a.D[k * P + m];
     }
     if constexpr (GEO == kMetricBox) {
-        // D contractions of the nodal sines along xi and eta (FP64)
-        double dsx = 0.0, dsy = 0.0;
-#pragma unroll
-        for (int m = 0; m < P; ++m) {
-            dsx += a.Dd[i * P + m] * sn[m];
-            dsy += a.Dd[j * P + m] * sn[P + m];
-        }
+        const BoxMetric &bm = a.bm;
         const int64_t ez = e / ((int64_t)a.nx * a.ny);
-        const double zk = a.H * lattice_pos(ez * N + k, N, a.nz, a.xi) / a.nz;
-        const double h = a.h0 * sn[i] * sn[P + j];
-        const double omz = 1.0 - zk / a.H;
-        const double xa = a.Lx / (2.0 * a.nx), yb = a.Ly / (2.0 * a.ny);
-        const double za = omz * a.h0 * sn[P + j] * dsx, zb = omz * a.h0 * sn[i] * dsy;
-        const double zc = (1.0 - h / a.H) * (a.H / (2.0 * a.nz));
+        const double omz = 1.0 - lattice_pos(ez * N + k, N, a.nz, a.xi) * bm.inz;  // 1 - z/H
+        const double sx = sn[i], sy = sn[P + j];
+        const double h = bm.h0 * sx * sy;
+        const double za = omz * bm.h0 * sy * dsn[i], zb = omz * bm.h0 * sx * dsn[P + j];
+        const double zc = (1.0 - h * bm.iH) * bm.zz;
         const double izc = 1.0 / zc;
-        mx[0] = (T)(1.0 / xa);
-        mx[4] = (T)(1.0 / yb);
-        mx[6] = (T)(-za / xa * izc);
-        mx[7] = (T)(-zb / yb * izc);
+        mx[0] = (T)bm.ixa;
+        mx[4] = (T)bm.iyb;
+        mx[6] = (T)(-za * bm.ixa * izc);
+        mx[7] = (T)(-zb * bm.iyb * izc);
         mx[8] = (T)izc;
-        mx[9] = (T)(xa * yb * zc * (a.w[i] * a.w[j] * a.w[k]));
+        mx[9] = (T)(bm.xa * bm.yb * zc * (a.w[i] * a.w[j] * a.w[k]));
     }
-    T dx[NF], dy[NF], dz[NF];
+    // reference derivatives of every field, then the chain rule through the
+    // metric: for the advected fields directly in contravariant form,
+    // u . grad f = sum_d U_d df/dxi_d with U_d = u . grad(xi_d)
+    const T uu = (T)u, vv = (T)v, ww = (T)w;
+    T Uc[3];
+    if constexpr (GEO == kMetricBox) {
+        Uc[0] = uu * mx[0];
+        Uc[1] = vv * mx[4];
+        Uc[2] = uu * mx[6] + vv * mx[7] + ww * mx[8];
+    } else {
+        Uc[0] = uu * mx[0] + vv * mx[1] + ww * mx[2];
+        Uc[1] = uu * mx[3] + vv * mx[4] + ww * mx[5];
+        Uc[2] = uu * mx[6] + vv * mx[7] + ww * mx[8];
+    }
+    T dd[NF][3];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         T da = 0, db = 0, dc = 0;
@@ -180,31 +243,36 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
             db += Dj[m] * s[f][i + P * (m + P * k)];
             dc += Dk[m] * s[f][i + P * (j + P * m)];
         }
-        if constexpr (GEO == kMetricBox) {
-            dx[f] = da * mx[0] + dc * mx[6];
-            dy[f] = db * mx[4] + dc * mx[7];
-            dz[f] = dc * mx[8];
-        } else {
-            dx[f] = da * mx[0] + db * mx[3] + dc * mx[6];
-            dy[f] = da * mx[1] + db * mx[4] + dc * mx[7];
-            dz[f] = da * mx[2] + db * mx[5] + dc * mx[8];
-        }
+        dd[f][0] = da;
+        dd[f][1] = db;
+        dd[f][2] = dc;
     }
-    const T irho = (T)(1.0 / rho);
-    const T buoy = (T)(rp / rho);
+    // Cartesian derivative d/dx_c of field f (row c of the inverse metric)
+    auto cart = [&](int f, int c) -> T {
+        if constexpr (GEO == kMetricBox) {
+            if (c == 0) return dd[f][0] * mx[0] + dd[f][2] * mx[6];
+            if (c == 1) return dd[f][1] * mx[4] + dd[f][2] * mx[7];
+            return dd[f][2] * mx[8];
+        } else {
+            return dd[f][0] * mx[c] + dd[f][1] * mx[3 + c] + dd[f][2] * mx[6 + c];
+        }
+    };
+    auto adv = [&](int f) -> T { return Uc[0] * dd[f][0] + Uc[1] * dd[f][1] + Uc[2] * dd[f][2]; };
+    const double irho64 = 1.0 / rho;
+    const T irho = (T)irho64;
+    const T buoy = (T)(rp * irho64);
     T gx = 0, gy = 0, gz = (T)(-a.g0);
     if constexpr (SHELL) {
         gx = (T)a.grav[I];
         gy = (T)a.grav[a.nu + I];
         gz = (T)a.grav[2 * a.nu + I];
     }
-    const T uu = (T)u, vv = (T)v, ww = (T)w;
-    o.R[0] = -(dx[0] + dy[1] + dz[2]);
-    o.R[1] = -(uu * dx[3] + vv * dy[3] + ww * dz[3]) - dx[7] * irho + buoy * gx;
-    o.R[2] = -(uu * dx[4] + vv * dy[4] + ww * dz[4]) - dy[7] * irho + buoy * gy;
-    o.R[3] = -(uu * dx[5] + vv * dy[5] + ww * dz[5]) - dz[7] * irho + buoy * gz;
-    o.R[4] = -(uu * dx[6] + vv * dy[6] + ww * dz[6]);
-    if constexpr (SHELL) o.R[4] -= uu * dx[8] + vv * dy[8] + ww * dz[8];
+    o.R[0] = -(cart(0, 0) + cart(1, 1) + cart(2, 2));
+    o.R[1] = -adv(3) - cart(7, 0) * irho + buoy * gx;
+    o.R[2] = -adv(4) - cart(7, 1) * irho + buoy * gy;
+    o.R[3] = -adv(5) - cart(7, 2) * irho + buoy * gz;
+    o.R[4] = -adv(6);
+    if constexpr (SHELL) o.R[4] -= adv(8);
     o.Jw = mx[9];
     o.I = I;
     o.q[0] = rp;

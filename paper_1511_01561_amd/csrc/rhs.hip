@@ -65,10 +65,8 @@ void launch_t(Mesh &m, const T *met, const T *D, const double *q, TO *out, hipSt
     a.nx = m.d.ne[0];
     a.ny = m.d.ne[1];
     a.nz = m.d.ne[2];
-    a.Lx = m.d.extent[0];
-    a.Ly = m.d.extent[1];
-    a.H = m.d.extent[2];
-    a.h0 = m.d.terrain_amp;
+    if (m.d.kind == NUMA_MESH_BOX) a.bm = box_metric(m);
+    eos_coeffs(m.gamma, a.eos);
     a.xi = m.dv.xi64;
     a.w = m.dv.w64;
     a.Dd = m.dv.D64;
