@@ -23,7 +23,7 @@ struct BatchItem {
     const double *qn;  // state at the start of the step
     const double *ref, *Minv, *nrm;
     const void *met;   // [ne][10][np] of T
-    void *ev;          // [5][nl] of T: contributions of this stage
+    void *ev;          // [nl][5] of T: contributions of this stage, node-major
     int64_t nl, nu, nh, ni, nj, nkw;  // nkw: lattice extent in z when periodic, else -1
     int nx, ny, nz, walls;
     double dt;
@@ -75,10 +75,20 @@ __global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
     a.w = B.w;
     a.Dd = B.Dd;
     NodeOut<T> o;
-    if (!element_rhs<N, T, false, GEO>(a, e, threadIdx.x, s, o)) return;
-    T *p = (T *)it.ev + e * NP + threadIdx.x;
+    const int l = threadIdx.x;
+    const bool act = element_rhs<N, T, false, GEO>(a, e, l, s, o);
+    // node-major [n_local][5] output (a copy's five values in one run for the
+    // finish), staged through the tile so that the block writes its 5 (N+1)^3
+    // values as one contiguous, coalesced run
+    __syncthreads();  // every lane has finished reading the tile
+    T *st = &s[0][0];
+    if (act) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) p[v * it.nl] = o.Jw * o.R[v];
+        for (int v = 0; v < 5; ++v) st[l * 5 + v] = o.Jw * o.R[v];
+    }
+    __syncthreads();
+    T *out = (T *)it.ev + e * NP * 5;
+    for (int t = l; t < NP * 5; t += blockDim.x) out[t] = st[t];
 }
 
 template <int N, int SEG, typename T>

@@ -393,7 +393,7 @@ __device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin
                 const int64_t e = cx[x] + b.nx * (cy[y] + b.ny * cz[z]);
                 const int64_t c = e * NP + lx[x] + P * (ly[y] + P * lz[z]);
 #pragma unroll
-                for (int v = 0; v < 5; ++v) r[v] += (double)ev[v * p.nl + c];
+                for (int v = 0; v < 5; ++v) r[v] += (double)ev[c * 5 + v];  // node-major [n_local][5]
             }
     const double mi = p.Minv[I];
 #pragma unroll
