@@ -22,13 +22,17 @@ struct BatchItem {
     double *qout;      // stage output state
     const double *qn;  // state at the start of the step
     const double *ref, *Minv, *nrm;
-    const void *met;   // [ne][10][np] of T
-    void *ev;          // [nl][5] of T: contributions of this stage, node-major
-    int64_t nl, nu, nh, ni, nj, nkw;  // nkw: lattice extent in z when periodic, else -1
-    int nx, ny, nz, walls;
+    const void *met;      // [ne][10][np] of T
+    void *ev;             // [nl][5] of T: contributions of this stage, node-major
+    const double *hcol;   // terrain per element column (recomputed metric)
+    int64_t nu, nh;
+    int ni, nj, nkw;      // lattice extents; nkw: extent in z when periodic, else -1
+    int nz, walls;
+    int mblk;             // finish blocks of the main layers: (nx/SEG) ny nz
+    FastDiv fx, fy, fseg;  // division by nx, ny and nx/SEG
     double dt;
-    BoxMetric bm;  // constants of the recomputed metric
-    int64_t eoff, boff;  // first element / finish block of this item in the launch
+    BoxMetric bm;          // constants of the recomputed metric
+    int eoff, boff;        // first element / finish block of this item in the launch
 };
 
 struct Batch {
@@ -41,16 +45,22 @@ struct Batch {
 };
 static_assert(sizeof(Batch) <= 4096, "the batch table must fit the kernel arguments");
 
+// item of launch-wide block g (items are in ascending eoff / boff order)
+__device__ __forceinline__ int batch_item(const Batch &B, int g, bool fin)
+{
+    int k = 0;
+    while (k + 1 < B.n && g >= (fin ? B.it[k + 1].boff : B.it[k + 1].eoff)) ++k;
+    return k;
+}
+
 template <int N, typename T, int GEO>
 __global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
 {
-    constexpr int NP = (N + 1) * (N + 1) * (N + 1);
+    constexpr int NP = (N + 1) * (N + 1) * (N + 1), BT = block_threads<N>();
     __shared__ T s[8][NP];
-    const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
-    int k = 0;
-    while (k + 1 < B.n && g >= B.it[k + 1].eoff) ++k;
-    const BatchItem &it = B.it[k];
-    const int64_t e = g - it.eoff;
+    const int g = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const BatchItem &it = B.it[batch_item(B, g, false)];
+    const int e = g - it.eoff;
     RhsArgs<T> a;
     a.G = nullptr;
     a.q = it.qs;
@@ -58,16 +68,19 @@ __global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
     a.grav = nullptr;
     a.met = (const T *)it.met;
     a.D = (const T *)B.D;
-    a.nl = it.nl;
+    a.hcol = it.hcol;
+    a.nl = 0;
     a.nu = it.nu;
     a.gamma = B.gamma;
     a.g0 = B.g0;
-    a.nx = it.nx;
-    a.ny = it.ny;
+    a.nx = (int)it.fx.d;
+    a.ny = (int)it.fy.d;
+    a.nz = it.nz;
     a.ni = it.ni;
     a.nj = it.nj;
     a.nk = it.nkw;
-    a.nz = it.nz;
+    a.fx = it.fx;
+    a.fy = it.fy;
     a.bm = it.bm;
 #pragma unroll
     for (int c = 0; c < kEosTerms; ++c) a.eos[c] = B.eos[c];
@@ -87,44 +100,48 @@ __global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
         for (int v = 0; v < 5; ++v) st[l * 5 + v] = o.Jw * o.R[v];
     }
     __syncthreads();
-    T *out = (T *)it.ev + e * NP * 5;
-    for (int t = l; t < NP * 5; t += blockDim.x) out[t] = st[t];
+    T *out = (T *)it.ev + (int64_t)e * (NP * 5);
+#pragma unroll
+    for (int r = 0; r < (NP * 5 + BT - 1) / BT; ++r) {
+        const int t = l + r * BT;
+        if (t < NP * 5) out[t] = st[t];
+    }
 }
 
 template <int N, int SEG, typename T>
 __global__ void k_fin_batch(Batch B)
 {
-    const int64_t g = xcd_remap(blockIdx.x, gridDim.x);
-    int k = 0;
-    while (k + 1 < B.n && g >= B.it[k + 1].boff) ++k;
-    const BatchItem &it = B.it[k];
-    int64_t lb = g - it.boff;
-    const int64_t main_blocks = (int64_t)(it.nx / SEG) * it.ny * it.nz;
+    const int g = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const BatchItem &it = B.it[batch_item(B, g, true)];
+    int lb = g - it.boff;
     int kbase = 0, klayers = N;
-    if (lb >= main_blocks) {  // the top wall layer
+    if (lb >= it.mblk) {  // the top wall layer
         kbase = N;
         klayers = 1;
-        lb -= main_blocks;
+        lb -= it.mblk;
     }
+    const uint32_t t = fdiv((uint32_t)lb, it.fseg);
+    const int sx = lb - (int)(t * it.fseg.d);
+    const uint32_t ez = fdiv(t, it.fy);
+    const int ey = (int)(t - ez * it.fy.d);
     PointArgs p;
     p.off = nullptr;
     p.idx = nullptr;
     p.Minv = it.Minv;
     p.nrm = it.nrm;
-    p.nl = it.nl;
+    p.nl = 0;
     p.nu = it.nu;
     p.nh = it.nh;
     p.walls = it.walls;
     BoxFin b;
-    b.nx = it.nx;
-    b.ny = it.ny;
+    b.nx = (int)it.fx.d;
+    b.ny = (int)it.fy.d;
     b.nz = it.nz;
     b.walls = it.walls;
     b.ni = it.ni;
     b.nj = it.nj;
-    b.nk = 0;
-    box_finish_node<N, SEG, T>(p, b, (const T *)it.ev, lb, threadIdx.x, kbase, klayers, B.stage, it.dt, it.qn, it.qs,
-                               it.qout);
+    box_finish_node<N, SEG, T>(p, b, (const T *)it.ev, sx, ey, kbase == 0 ? (int)ez : it.nz - 1, threadIdx.x, kbase,
+                               klayers, B.stage, it.dt, it.qn, it.qs, it.qout);
 }
 
 template <int N, typename T>
@@ -153,22 +170,29 @@ int32_t run_chunk(const StepItem *items, int n, int stage, int phase, hipStream_
         it.nrm = m.dv.nrm;
         it.met = std::is_same<T, float>::value ? (const void *)m.dv.met32 : (const void *)m.dv.met;
         it.ev = items[k].ev;
-        it.nl = m.nl;
+        it.hcol = m.dv.hcol;
         it.nu = m.nu;
         it.nh = m.nh;
-        it.ni = m.ni;
-        it.nj = m.nj;
-        it.nkw = m.d.periodic[2] ? m.nk : -1;
-        it.nx = m.d.ne[0];
-        it.ny = m.d.ne[1];
+        it.ni = (int)m.ni;
+        it.nj = (int)m.nj;
+        it.nkw = m.d.periodic[2] ? (int)m.nk : -1;
         it.nz = m.d.ne[2];
         it.walls = m.walls ? 1 : 0;
+        it.fx = fast_div((uint32_t)m.d.ne[0]);
+        it.fy = fast_div((uint32_t)m.d.ne[1]);
+        it.fseg = fast_div((uint32_t)(m.d.ne[0] / SEG));
+        const int64_t mblk = (int64_t)(m.d.ne[0] / SEG) * m.d.ne[1] * m.d.ne[2];
+        it.mblk = (int)mblk;
         it.dt = items[k].dt;
         it.bm = box_metric(m);
-        it.eoff = eo;
-        it.boff = bo;
+        it.eoff = (int)eo;
+        it.boff = (int)bo;
         eo += m.ne;
-        bo += (int64_t)(it.nx / SEG) * it.ny * it.nz + (m.walls ? (int64_t)(it.nx / SEG) * it.ny : 0);
+        bo += mblk + (m.walls ? (int64_t)(m.d.ne[0] / SEG) * m.d.ne[1] : 0);
+    }
+    if (eo >= (int64_t(1) << 31) || bo >= (int64_t(1) << 31)) {
+        set_error("batch: more than 2^31 - 1 elements in one launch");
+        return NUMA_EUNSUPPORTED;
     }
     for (int k = n; k < kMaxBatch; ++k) B.it[k] = BatchItem{};
     if (phase == 0) {

@@ -371,6 +371,37 @@ __global__ void k_box_gravity(GeoParams g, double g0, double *out)
     out[2 * g.nu + I] = -g0;
 }
 
+// Terrain of every element column of a box mesh, for the recomputed metric:
+// at local (i, j) of column (ex, ey) the height h of the map (the same
+// expression as box_xyz) and its reference derivatives dh/dxi = sum_m D_im h_mj,
+// dh/deta = sum_m D_jm h_im.  Layout [nx*ny][3][(N+1)^2], column ex + nx*ey.
+__device__ inline double box_terrain(const GeoParams &g, int64_t ci, int64_t cj)
+{
+    const double xx = g.L0 * lattice_frac(ci, g.N, g.nex, g.xi) / g.nex;
+    const double yy = g.L1 * lattice_frac(cj, g.N, g.ney, g.xi) / g.ney;
+    return g.h0 * sin(2.0 * kPi * xx / g.L0) * sin(2.0 * kPi * yy / g.L1);
+}
+
+__global__ void k_box_columns(GeoParams g, double *hcol)
+{
+    const int PP = g.P * g.P;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)g.nex * g.ney * PP) return;
+    const int64_t col = t / PP;
+    const int l = (int)(t - col * PP), i = l % g.P, j = l / g.P;
+    const int64_t ex = col % g.nex, ey = col / g.nex;
+    const int64_t ci = ex * g.N, cj = ey * g.N;
+    double hx = 0.0, hy = 0.0;
+    for (int m = 0; m < g.P; ++m) {
+        hx += g.D[i * g.P + m] * box_terrain(g, ci + m, cj + j);
+        hy += g.D[j * g.P + m] * box_terrain(g, ci + i, cj + m);
+    }
+    double *o = hcol + col * 3 * PP + l;
+    o[0] = box_terrain(g, ci + i, cj + j);
+    o[PP] = hx;
+    o[2 * PP] = hy;
+}
+
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -407,6 +438,9 @@ int32_t launch_geometry(Mesh &m, hipStream_t s)
     hipLaunchKernelGGL(k_unique_coords, dim3(nblocks(m.nu, bs)), dim3(bs), 0, s, g, v.hlat, v.xu);
     hipLaunchKernelGGL(k_reference, dim3(nblocks(m.nu, bs)), dim3(bs), 0, s, g, m.ph, v.hlat, v.xu, v.ref, v.grav);
     hipLaunchKernelGGL(k_normals, dim3(nblocks(m.nh, bs)), dim3(bs), 0, s, g, v.hlat, v.xu, v.nrm);
+    if (v.hcol)
+        hipLaunchKernelGGL(k_box_columns, dim3(nblocks((int64_t)g.nex * g.ney * m.P * m.P, bs)), dim3(bs), 0, s, g,
+                           v.hcol);
     NUMA_HIP(hipGetLastError());
     int hbad = 0;
     NUMA_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));

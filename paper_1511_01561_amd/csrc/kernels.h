@@ -11,10 +11,11 @@ namespace numa {
 namespace dev {
 
 // Per-mesh constants of the recomputed box metric (host-computed, so the
-// kernel divides once per node): x_xi = Lx/(2 nx), y_eta = Ly/(2 ny),
-// z_zeta of the undeformed map H/(2 nz), and the angular steps of the terrain.
+// kernel divides once per node): x_xi = Lx/(2 nx), y_eta = Ly/(2 ny), z_zeta of
+// the undeformed map H/(2 nz), 1/nz and 1/H.  The terrain itself comes from
+// the per-column table (Mesh workspace hcol).
 struct BoxMetric {
-    double xa, ixa, yb, iyb, zz, inz, iH, h0, kx, ky;  // kx = 2 pi/nx, ky = 2 pi/ny
+    double xa, ixa, yb, iyb, zz, inz, iH;
 };
 
 // (1 + x)^gamma - 1 by its binomial series sum_k c_k x^k, c_1 = gamma,
@@ -35,10 +36,9 @@ __device__ __forceinline__ double eos_rel(double x, double gamma, const double *
     return expm1(gamma * log1p(x));
 }
 
-// host: constants of the recomputed metric of a box mesh, series coefficients
+// host: constants of the recomputed metric of a box mesh
 inline BoxMetric box_metric(const Mesh &m)
 {
-    const double kTwoPi = 6.283185307179586476925286766559;
     BoxMetric b;
     b.xa = m.d.extent[0] / (2.0 * m.d.ne[0]);
     b.ixa = 1.0 / b.xa;
@@ -47,9 +47,6 @@ inline BoxMetric box_metric(const Mesh &m)
     b.zz = m.d.extent[2] / (2.0 * m.d.ne[2]);
     b.inz = 1.0 / m.d.ne[2];
     b.iH = 1.0 / m.d.extent[2];
-    b.h0 = m.d.terrain_amp;
-    b.kx = kTwoPi / m.d.ne[0];
-    b.ky = kTwoPi / m.d.ne[1];
     return b;
 }
 
@@ -65,10 +62,12 @@ struct RhsArgs {
     const double *q, *ref, *grav;
     const T *met;
     const T *D;
+    const double *hcol;  // box: terrain h, dh/dxi, dh/deta per element column
     int64_t nl, nu;
     double gamma, g0;
     int nx, ny, nz;      // box: elements along x, y, z
-    int64_t ni, nj, nk;  // box: lattice extents (x, y periodic)
+    int ni, nj, nk;      // box: lattice extents (x, y periodic; nk = -1 unless z is)
+    FastDiv fx, fy;      // box: division by nx and ny
     const double *xi, *w, *Dd;  // FP64 GLL nodes, weights, derivative matrix
     BoxMetric bm;               // box: constants of the recomputed metric
     double eos[kEosTerms];      // coefficients of the binomial series of (1 + x)^gamma - 1
@@ -78,22 +77,23 @@ struct RhsArgs {
 // from the terrain-following map z' = z + h(x, y)(1 - z/H).
 enum { kMetricStored = 0, kMetricBox = 1 };
 
-// position of lattice index c (0..ncell*N) in element units, e_c + (1 + xi_i)/2,
-// e_c clamped to the last element (the node coordinates of the mesh numbering)
-__device__ __forceinline__ double lattice_pos(int64_t c, int N, int ncell, const double *xi)
+// coordinates of box element e = ex + nx (ey + ny ez)
+struct BoxElem {
+    int ex, ey, ez;
+};
+
+__device__ __forceinline__ BoxElem box_elem(uint32_t e, const FastDiv &fx, const FastDiv &fy)
 {
-    int64_t e = c / N;
-    if (e > ncell - 1) e = ncell - 1;
-    return (double)e + (1.0 + xi[c - (int64_t)N * e]) / 2.0;
+    const uint32_t t = fdiv(e, fx), ez = fdiv(t, fy);
+    return BoxElem{(int)(e - t * fx.d), (int)(t - ez * fy.d), (int)ez};
 }
 
-// unique id of local node (i, j, k) of box element e: the element's lattice
+// unique id of local node (i, j, k) of box element b: the element's lattice
 // corner plus the local offset, wrapped in the periodic directions
 template <int N, typename T>
-__device__ __forceinline__ int64_t box_unique(const RhsArgs<T> &a, int64_t e, int i, int j, int k)
+__device__ __forceinline__ int32_t box_unique(const RhsArgs<T> &a, const BoxElem &b, int i, int j, int k)
 {
-    const int64_t ex = e % a.nx, ey = (e / a.nx) % a.ny, ez = e / ((int64_t)a.nx * a.ny);
-    int64_t gi = ex * N + i, gj = ey * N + j, gk = ez * N + k;
+    int gi = b.ex * N + i, gj = b.ey * N + j, gk = b.ez * N + k;
     if (gi == a.ni) gi = 0;
     if (gj == a.nj) gj = 0;
     if (gk == a.nk) gk = 0;
@@ -106,10 +106,8 @@ constexpr int block_threads() { return (((N + 1) * (N + 1) * (N + 1) + 63) / 64)
 // Per-node result of the element RHS.
 template <typename T>
 struct NodeOut {
-    T R[5];     // R_rho', R_u, R_v, R_w, R_theta'
+    T R[5];  // R_rho', R_u, R_v, R_w, R_theta'
     T Jw;
-    int64_t I;  // unique id of the node
-    double q[5];
 };
 
 // Gathers the element tile, differentiates it and evaluates R at node l of
@@ -117,64 +115,52 @@ struct NodeOut {
 // returns false for the padding lanes (l >= (N+1)^3).
 //
 // GEO == kMetricBox (box meshes): the isoparametric metric of the map
-// x = x(xi), y = y(eta), z' = z(zeta) + h(x, y)(1 - z/H) with
-// h = h0 sin(2 pi x/Lx) sin(2 pi y/Ly) is computed from 2(N+1) sines per
-// element instead of being read: x_xi = Lx/(2 nx), y_eta = Ly/(2 ny),
-// z_xi = (1 - z/H) dh/dxi, z_eta = (1 - z/H) dh/deta (D contractions of the
-// nodal h), z_zeta = (1 - h/H) H/(2 nz); J = x_xi y_eta z_zeta and the inverse
-// has xi_x = 1/x_xi, eta_y = 1/y_eta, zeta = (-z_xi/(x_xi z_zeta),
-// -z_eta/(y_eta z_zeta), 1/z_zeta), all other entries zero.
+// x = x(xi), y = y(eta), z' = z(zeta) + h(x, y)(1 - z/H) is computed instead of
+// read.  With h, dh/dxi and dh/deta of the node's column (the per-column
+// terrain table): x_xi = Lx/(2 nx), y_eta = Ly/(2 ny), z_xi = (1 - z/H) dh/dxi,
+// z_eta = (1 - z/H) dh/deta, z_zeta = (1 - h/H) H/(2 nz); J = x_xi y_eta z_zeta
+// and the inverse has xi_x = 1/x_xi, eta_y = 1/y_eta, zeta = (-z_xi/(x_xi
+// z_zeta), -z_eta/(y_eta z_zeta), 1/z_zeta), all other entries zero.
 template <int N, typename T, bool SHELL, int GEO = kMetricStored>
 __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int l, T (*s)[(N + 1) * (N + 1) * (N + 1)],
                                             NodeOut<T> &o)
 {
-    constexpr int P = N + 1, NP = P * P * P, NF = SHELL ? 9 : 8;
-    // GEO == kMetricBox: sin(2 pi x_i/Lx), sin(2 pi y_j/Ly), then their D contractions
-    __shared__ double sn[2 * P], dsn[2 * P];
+    constexpr int P = N + 1, PP = P * P, NP = PP * P;
     const bool act = l < NP;
+    const int i = l % P, j = (l / P) % P, k = l / PP;
     double rp = 0.0, rho = 1.0, u = 0.0, v = 0.0, w = 0.0, tp = 0.0;
-    int64_t I = 0;
-    // metric terms do not depend on the tile: load them before the barrier so
-    // their latency overlaps the state gather and the equation of state
+    // metric terms (or the column terrain) do not depend on the tile: load
+    // them before the barrier so that their latency overlaps the state gather
+    // and the equation of state
     T mx[10];
-    if constexpr (GEO == kMetricStored) {
-        if (act) {
-            const T *mp = a.met + e * 10 * NP + l;
-#pragma unroll
-            for (int c = 0; c < 10; ++c) mx[c] = mp[c * NP];
-        }
-    }
+    double hh = 0.0, hx = 0.0, hy = 0.0;
+    BoxElem be{0, 0, 0};
+    if constexpr (!SHELL) be = box_elem((uint32_t)e, a.fx, a.fy);
+    int32_t I = 0;
     if (act) {
         if constexpr (SHELL) {
             I = a.G[e * NP + l];
         } else {
-            I = box_unique<N, T>(a, e, l % P, (l / P) % P, l / (P * P));
+            I = box_unique<N, T>(a, be, i, j, k);
         }
-        rp = a.q[I];
-        u = a.q[a.nu + I];
-        v = a.q[2 * a.nu + I];
-        w = a.q[3 * a.nu + I];
-        tp = a.q[4 * a.nu + I];
-    }
-    if constexpr (GEO == kMetricBox) {
-        // the terrain sines along the element's x and y lines, then their D
-        // contractions (once per element; the state loads are in flight)
-        if (l < 2 * P) {
-            const int64_t ex = e % a.nx, ey = (e / a.nx) % a.ny;
-            sn[l] = l < P ? sin(a.bm.kx * lattice_pos(ex * N + l, N, a.nx, a.xi))
-                          : sin(a.bm.ky * lattice_pos(ey * N + (l - P), N, a.ny, a.xi));
-        }
-        __syncthreads();
-        if (l < 2 * P) {
-            const int r = l < P ? l : l - P, b0 = l < P ? 0 : P;
-            double d = 0.0;
+        if constexpr (GEO == kMetricStored) {
+            const T *mp = a.met + e * 10 * NP + l;
 #pragma unroll
-            for (int m = 0; m < P; ++m) d += a.Dd[r * P + m] * sn[b0 + m];
-            dsn[l] = d;
+            for (int c = 0; c < 10; ++c) mx[c] = mp[c * NP];
+        } else {
+            const double *hp = a.hcol + (int64_t)(be.ex + a.nx * be.ey) * (3 * PP) + (i + P * j);
+            hh = hp[0];
+            hx = hp[PP];
+            hy = hp[2 * PP];
         }
-    }
-    if (act) {
-        const double rb = a.ref[I], tb = a.ref[a.nu + I], pb = a.ref[2 * a.nu + I];
+        const double *qp = a.q + I;
+        rp = qp[0];
+        u = qp[a.nu];
+        v = qp[2 * a.nu];
+        w = qp[3 * a.nu];
+        tp = qp[4 * a.nu];
+        const double *rf = a.ref + I;
+        const double rb = rf[0], tb = rf[a.nu], pb = rf[2 * a.nu];
         rho = rb + rp;
         // p' = p_bar ((rho theta / rho_bar theta_bar)^gamma - 1) without cancellation
         const double dl = rp * tb + rb * tp + rp * tp;
@@ -195,7 +181,6 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
     }
     __syncthreads();
     if (!act) return false;
-    const int i = l % P, j = (l / P) % P, k = l / (P * P);
     T Di[P], Dj[P], Dk[P];
 #pragma unroll
     for (int m = 0; m < P; ++m) {
@@ -205,12 +190,9 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
     }
     if constexpr (GEO == kMetricBox) {
         const BoxMetric &bm = a.bm;
-        const int64_t ez = e / ((int64_t)a.nx * a.ny);
-        const double omz = 1.0 - lattice_pos(ez * N + k, N, a.nz, a.xi) * bm.inz;  // 1 - z/H
-        const double sx = sn[i], sy = sn[P + j];
-        const double h = bm.h0 * sx * sy;
-        const double za = omz * bm.h0 * sy * dsn[i], zb = omz * bm.h0 * sx * dsn[P + j];
-        const double zc = (1.0 - h * bm.iH) * bm.zz;
+        const double omz = 1.0 - ((double)be.ez + 0.5 * (1.0 + a.xi[k])) * bm.inz;  // 1 - z/H
+        const double za = omz * hx, zb = omz * hy;
+        const double zc = (1.0 - hh * bm.iH) * bm.zz;
         const double izc = 1.0 / zc;
         mx[0] = (T)bm.ixa;
         mx[4] = (T)bm.iyb;
@@ -233,6 +215,7 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
         Uc[1] = uu * mx[3] + vv * mx[4] + ww * mx[5];
         Uc[2] = uu * mx[6] + vv * mx[7] + ww * mx[8];
     }
+    constexpr int NF = SHELL ? 9 : 8;
     T dd[NF][3];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -274,12 +257,6 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
     o.R[4] = -adv(6);
     if constexpr (SHELL) o.R[4] -= adv(8);
     o.Jw = mx[9];
-    o.I = I;
-    o.q[0] = rp;
-    o.q[1] = u;
-    o.q[2] = v;
-    o.q[3] = w;
-    o.q[4] = tp;
     return true;
 }
 
@@ -330,40 +307,39 @@ __device__ inline double rk_combine(int stage, double qn, double y)
 }
 
 // Finish of a fused stage on the box.  A block takes SEG consecutive elements
-// along x of one (ey, ez) and, per element, the lattice nodes whose lower
-// corner it is (local 0 <= i, j, k < N); lanes run along x fastest, so every
-// state read and write covers SEG*N consecutive unique ids.  The copies of a
-// node follow from its lattice position: on an element face along a
-// direction it has two copies (local index 0 of the element above and N of
-// the one below, wrapped when periodic), else one.  A second launch with
-// kbase = N, klayers = 1 covers the top wall layer (a block index of that layer).
+// along x of one (ey, ez) (sx: the segment index along x) and, per element,
+// the lattice nodes whose lower corner it is (local 0 <= i, j, k < N); lanes
+// run along x fastest, so every state read and write covers SEG*N consecutive
+// unique ids.  The copies of a node follow from its lattice position: on an
+// element face along a direction it has two copies (local index 0 of the
+// element above and N of the one below, wrapped when periodic), else one.  A
+// second launch with kbase = N, klayers = 1 covers the top wall layer
+// (ez = nz - 1).  Indices are 32-bit: the mesh keeps n_local, n_unique < 2^31.
 struct BoxFin {
     int nx, ny, nz, walls;
-    int64_t ni, nj, nk;
+    int ni, nj;
 };
 
 template <int N, int SEG, typename T>
-__device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin &b, const T *ev, int64_t blk,
-                                                int lane, int kbase, int klayers, int stage, double dt,
+__device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin &b, const T *ev, int sx, int ey,
+                                                int ez, int lane, int kbase, int klayers, int stage, double dt,
                                                 const double *qn, const double *qs, double *qout)
 {
     constexpr int P = N + 1, NP = P * P * P, W = SEG * N;
     if (lane >= W * N * klayers) return;
-    const int64_t nseg = b.nx / SEG;
-    const int64_t sx = blk % nseg, ey = (blk / nseg) % b.ny, ez = kbase == 0 ? blk / (nseg * b.ny) : b.nz - 1;
     const int a = lane % W, jj = (lane / W) % N, kk = lane / (W * N);
-    const int64_t gi = sx * W + a, gj = ey * N + jj, gk = ez * N + kbase + kk;
-    const int64_t I = gi + b.ni * (gj + b.nj * gk);
+    const int gi = sx * W + a, gj = ey * N + jj, gk = ez * N + kbase + kk;
+    const int32_t I = gi + b.ni * (gj + b.nj * gk);
     // copies along each direction: (element index along the direction, local index)
-    int64_t cx[2], cy[2], cz[2];
+    int cx[2], cy[2], cz[2];
     int lx[2], ly[2], lz[2], nxc, nyc, nzc;
-    const int64_t exa = gi / N;
+    const int exa = sx * SEG + a / N;
     if (a % N == 0) {  // gi is a multiple of N: element face in x
         cx[0] = exa; lx[0] = 0;
         cx[1] = exa == 0 ? b.nx - 1 : exa - 1; lx[1] = N;
         nxc = 2;
     } else {
-        cx[0] = exa; lx[0] = (int)(gi - exa * N);
+        cx[0] = exa; lx[0] = a % N;
         nxc = 1;
     }
     if (jj == 0) {
@@ -390,19 +366,22 @@ __device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin
     for (int z = 0; z < nzc; ++z)
         for (int y = 0; y < nyc; ++y)
             for (int x = 0; x < nxc; ++x) {
-                const int64_t e = cx[x] + b.nx * (cy[y] + b.ny * cz[z]);
-                const int64_t c = e * NP + lx[x] + P * (ly[y] + P * lz[z]);
+                const int32_t e = cx[x] + b.nx * (cy[y] + b.ny * cz[z]);
+                const int32_t c = e * NP + lx[x] + P * (ly[y] + P * lz[z]);
+                const T *src = ev + (int64_t)c * 5;  // node-major [n_local][5]
 #pragma unroll
-                for (int v = 0; v < 5; ++v) r[v] += (double)ev[c * 5 + v];  // node-major [n_local][5]
+                for (int v = 0; v < 5; ++v) r[v] += (double)src[v];
             }
     const double mi = p.Minv[I];
 #pragma unroll
     for (int v = 0; v < 5; ++v) r[v] *= mi;
     noflux(p, I, r[1], r[2], r[3]);
+    const double *qsi = qs + I, *qni = qn + I;
+    double *qoi = qout + I;
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-        double y = qs[v * p.nu + I] + dt * r[v];
-        qout[v * p.nu + I] = rk_combine(stage, stage == 0 ? 0.0 : qn[v * p.nu + I], y);
+        const double y = qsi[v * p.nu] + dt * r[v];
+        qoi[v * p.nu] = rk_combine(stage, stage == 0 ? 0.0 : qni[v * p.nu], y);
     }
 }
 

@@ -28,6 +28,35 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nblocks)
     return x * q + (x < r ? x : r) + slot;
 }
 
+// Division by a run-time invariant divisor d >= 1 with one high multiply
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994, Fig. 4.1): with l = ceil(log2 d),
+// m = floor(2^32 (2^l - d) / d) + 1, s1 = min(l, 1), s2 = max(l - 1, 0),
+// n / d = (t + ((n - t) >> s1)) >> s2 where t = mulhi(m, n), exact for every
+// 32-bit n.  The element and finish kernels decompose their block index this
+// way instead of with 64-bit divisions.
+struct FastDiv {
+    uint32_t d, m, s1, s2;
+};
+
+inline FastDiv fast_div(uint32_t d)
+{
+    FastDiv f{};
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    f.d = d;
+    f.m = (uint32_t)(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+    f.s1 = l < 1 ? l : 1;
+    f.s2 = l > 1 ? l - 1 : 0;
+    return f;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f)
+{
+    const uint32_t t = __umulhi(f.m, n);
+    return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
 // Returns NUMA_EDEVICE (with the message recorded) if a HIP call failed.
 #define NUMA_HIP(call)                                                                        \
     do {                                                                                      \
@@ -53,6 +82,7 @@ struct DeviceView {
     double *grav = nullptr;    // shell: [3][n_unique]
     double *nrm = nullptr;     // [2][3][n_horiz] bottom and top wall normals
     double *xu = nullptr;      // [3][n_unique] unique coordinates
+    double *hcol = nullptr;    // box: [nx*ny][3][(N+1)^2] terrain h, dh/dxi, dh/deta per element column
     int32_t *own = nullptr;    // [n_unique] unique ids in first-occurrence order of the element scan
     int32_t *toff = nullptr;   // [n_unique+1] copy offsets in that order
     int32_t *tidx = nullptr;   // [n_local] copies (e*np + l), ascending per node, in that order

@@ -62,17 +62,20 @@ void launch_t(Mesh &m, const T *met, const T *D, const double *q, TO *out, hipSt
     a.nu = m.nu;
     a.gamma = m.gamma;
     a.g0 = m.ph.g0;
+    a.hcol = m.dv.hcol;
     a.nx = m.d.ne[0];
     a.ny = m.d.ne[1];
     a.nz = m.d.ne[2];
+    a.fx = fast_div((uint32_t)m.d.ne[0]);
+    a.fy = fast_div((uint32_t)m.d.ne[1]);
     if (m.d.kind == NUMA_MESH_BOX) a.bm = box_metric(m);
     eos_coeffs(m.gamma, a.eos);
     a.xi = m.dv.xi64;
     a.w = m.dv.w64;
     a.Dd = m.dv.D64;
-    a.ni = m.ni;
-    a.nj = m.nj;
-    a.nk = m.d.periodic[2] ? m.nk : -1;  // only a periodic z wraps
+    a.ni = (int)m.ni;
+    a.nj = (int)m.nj;
+    a.nk = m.d.periodic[2] ? (int)m.nk : -1;  // only a periodic z wraps
     switch (m.N) {
     case 1: launch_n<1, T, TO>(m, a, out, s); break;
     case 2: launch_n<2, T, TO>(m, a, out, s); break;
