@@ -24,7 +24,7 @@ struct BatchItem {
     const double *ref, *Minv, *nrm;
     const void *met;      // [ne][10][np] of T
     void *ev;             // [nl][5] of T: contributions of this stage, node-major
-    const double *hcol;   // terrain per element column (recomputed metric)
+    const double *hcol;   // column factors of the recomputed metric
     int64_t nu, nh;
     int ni, nj, nkw;      // lattice extents; nkw: extent in z when periodic, else -1
     int nz, walls;

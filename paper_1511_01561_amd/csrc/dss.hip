@@ -41,8 +41,7 @@ __global__ void k_rk_stage(int64_t n, int stage, double dt, const double *qn, co
 {
     int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= n) return;
-    double y = qs[a] + dt * r[a];
-    qout[a] = rk_combine(stage, stage == 0 ? 0.0 : qn[a], y);
+    qout[a] = rk_update(stage, stage == 0 ? 0.0 : qn[a], qs[a], dt, r[a]);
 }
 
 // Second half of a fused stage: DSS (mass-weighted), no-flux projection and
@@ -71,10 +70,8 @@ __global__ void k_stage_finish(PointArgs p, const int32_t *own, const int32_t *t
     for (int v = 0; v < 5; ++v) r[v] *= mi;
     noflux(p, I, r[1], r[2], r[3]);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        double y = qs[v * p.nu + I] + dt * r[v];
-        qout[v * p.nu + I] = rk_combine(stage, stage == 0 ? 0.0 : qn[v * p.nu + I], y);
-    }
+    for (int v = 0; v < 5; ++v)
+        qout[v * p.nu + I] = rk_update(stage, stage == 0 ? 0.0 : qn[v * p.nu + I], qs[v * p.nu + I], dt, r[v]);
 }
 
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }

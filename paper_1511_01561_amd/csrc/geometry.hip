@@ -371,10 +371,18 @@ __global__ void k_box_gravity(GeoParams g, double g0, double *out)
     out[2 * g.nu + I] = -g0;
 }
 
-// Terrain of every element column of a box mesh, for the recomputed metric:
-// at local (i, j) of column (ex, ey) the height h of the map (the same
-// expression as box_xyz) and its reference derivatives dh/dxi = sum_m D_im h_mj,
-// dh/deta = sum_m D_jm h_im.  Layout [nx*ny][3][(N+1)^2], column ex + nx*ey.
+// Column factors of the recomputed box metric.  The map x = x(xi),
+// y = y(eta), z' = z(zeta) + h(x, y)(1 - z/H) has x_xi = Lx/(2 nx),
+// y_eta = Ly/(2 ny), z_zeta = (1 - h/H) H/(2 nz), z_xi = (1 - z/H) dh/dxi and
+// z_eta = (1 - z/H) dh/deta, so at local (i, j) of element column (ex, ey)
+//   c0 = x_xi y_eta z_zeta w_i w_j         (J w_ijk = c0 w_k)
+//   c1 = 1/z_zeta                          (zeta_z)
+//   c2 = -(dh/dxi)/(x_xi z_zeta)           (zeta_x = (1 - z/H) c2)
+//   c3 = -(dh/deta)/(y_eta z_zeta)         (zeta_y = (1 - z/H) c3)
+// with h as in box_xyz, dh/dxi = sum_m D_im h_mj and dh/deta = sum_m D_jm h_im;
+// xi_x = 1/x_xi and eta_y = 1/y_eta, the other entries are zero.  Layout
+// [nx*ny][4][(N+1)^2], column ex + nx*ey: the per-node metric then takes no
+// division and no transcendental.
 __device__ inline double box_terrain(const GeoParams &g, int64_t ci, int64_t cj)
 {
     const double xx = g.L0 * lattice_frac(ci, g.N, g.nex, g.xi) / g.nex;
@@ -396,10 +404,14 @@ __global__ void k_box_columns(GeoParams g, double *hcol)
         hx += g.D[i * g.P + m] * box_terrain(g, ci + m, cj + j);
         hy += g.D[j * g.P + m] * box_terrain(g, ci + i, cj + m);
     }
-    double *o = hcol + col * 3 * PP + l;
-    o[0] = box_terrain(g, ci + i, cj + j);
-    o[PP] = hx;
-    o[2 * PP] = hy;
+    const double h = box_terrain(g, ci + i, cj + j);
+    const double xa = g.L0 / (2.0 * g.nex), yb = g.L1 / (2.0 * g.ney);
+    const double zc = (1.0 - h / g.L2) * (g.L2 / (2.0 * g.nez));
+    double *o = hcol + col * 4 * PP + l;
+    o[0] = xa * yb * zc * (g.w[i] * g.w[j]);
+    o[PP] = 1.0 / zc;
+    o[2 * PP] = -hx / (xa * zc);
+    o[3 * PP] = -hy / (yb * zc);
 }
 
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }

@@ -10,12 +10,12 @@
 namespace numa {
 namespace dev {
 
-// Per-mesh constants of the recomputed box metric (host-computed, so the
-// kernel divides once per node): x_xi = Lx/(2 nx), y_eta = Ly/(2 ny), z_zeta of
-// the undeformed map H/(2 nz), 1/nz and 1/H.  The terrain itself comes from
-// the per-column table (Mesh workspace hcol).
+// Per-mesh constants of the recomputed box metric: xi_x = 2 nx/Lx,
+// eta_y = 2 ny/Ly and 1/nz (the undeformed level z/H of a node is
+// (ez + (1 + xi_k)/2)/nz).  Everything that varies over the terrain comes
+// from the column table (Mesh workspace hcol).
 struct BoxMetric {
-    double xa, ixa, yb, iyb, zz, inz, iH;
+    double ixa, iyb, inz;
 };
 
 // (1 + x)^gamma - 1 by its binomial series sum_k c_k x^k, c_1 = gamma,
@@ -40,13 +40,9 @@ __device__ __forceinline__ double eos_rel(double x, double gamma, const double *
 inline BoxMetric box_metric(const Mesh &m)
 {
     BoxMetric b;
-    b.xa = m.d.extent[0] / (2.0 * m.d.ne[0]);
-    b.ixa = 1.0 / b.xa;
-    b.yb = m.d.extent[1] / (2.0 * m.d.ne[1]);
-    b.iyb = 1.0 / b.yb;
-    b.zz = m.d.extent[2] / (2.0 * m.d.ne[2]);
+    b.ixa = 1.0 / (m.d.extent[0] / (2.0 * m.d.ne[0]));
+    b.iyb = 1.0 / (m.d.extent[1] / (2.0 * m.d.ne[1]));
     b.inz = 1.0 / m.d.ne[2];
-    b.iH = 1.0 / m.d.extent[2];
     return b;
 }
 
@@ -62,7 +58,7 @@ struct RhsArgs {
     const double *q, *ref, *grav;
     const T *met;
     const T *D;
-    const double *hcol;  // box: terrain h, dh/dxi, dh/deta per element column
+    const double *hcol;  // box: column factors of the recomputed metric
     int64_t nl, nu;
     double gamma, g0;
     int nx, ny, nz;      // box: elements along x, y, z
@@ -114,13 +110,12 @@ struct NodeOut {
 // element e.  Must be called by all lanes of the block (it synchronises);
 // returns false for the padding lanes (l >= (N+1)^3).
 //
-// GEO == kMetricBox (box meshes): the isoparametric metric of the map
-// x = x(xi), y = y(eta), z' = z(zeta) + h(x, y)(1 - z/H) is computed instead of
-// read.  With h, dh/dxi and dh/deta of the node's column (the per-column
-// terrain table): x_xi = Lx/(2 nx), y_eta = Ly/(2 ny), z_xi = (1 - z/H) dh/dxi,
-// z_eta = (1 - z/H) dh/deta, z_zeta = (1 - h/H) H/(2 nz); J = x_xi y_eta z_zeta
-// and the inverse has xi_x = 1/x_xi, eta_y = 1/y_eta, zeta = (-z_xi/(x_xi
-// z_zeta), -z_eta/(y_eta z_zeta), 1/z_zeta), all other entries zero.
+// GEO == kMetricBox (box meshes): the isoparametric metric of the
+// terrain-following map x = x(xi), y = y(eta), z' = z(zeta) + h(x, y)(1 - z/H)
+// is computed instead of read: with the node's column factors c0..c3 (see
+// k_box_columns) and its undeformed level z/H, xi_x = 2 nx/Lx,
+// eta_y = 2 ny/Ly, zeta = ((1 - z/H) c2, (1 - z/H) c3, c1), J w = c0 w_k, all
+// other entries zero.
 template <int N, typename T, bool SHELL, int GEO = kMetricStored>
 __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int l, T (*s)[(N + 1) * (N + 1) * (N + 1)],
                                             NodeOut<T> &o)
@@ -133,7 +128,7 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
     // them before the barrier so that their latency overlaps the state gather
     // and the equation of state
     T mx[10];
-    double hh = 0.0, hx = 0.0, hy = 0.0;
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0, zk = 0.0;
     BoxElem be{0, 0, 0};
     if constexpr (!SHELL) be = box_elem((uint32_t)e, a.fx, a.fy);
     int32_t I = 0;
@@ -148,10 +143,12 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
 #pragma unroll
             for (int c = 0; c < 10; ++c) mx[c] = mp[c * NP];
         } else {
-            const double *hp = a.hcol + (int64_t)(be.ex + a.nx * be.ey) * (3 * PP) + (i + P * j);
-            hh = hp[0];
-            hx = hp[PP];
-            hy = hp[2 * PP];
+            const double *cp = a.hcol + (int64_t)(be.ex + a.nx * be.ey) * (4 * PP) + (i + P * j);
+            c0 = cp[0] * a.w[k];
+            c1 = cp[PP];
+            c2 = cp[2 * PP];
+            c3 = cp[3 * PP];
+            zk = a.xi[k];
         }
         const double *qp = a.q + I;
         rp = qp[0];
@@ -189,17 +186,13 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
         Dk[m] = a.D[k * P + m];
     }
     if constexpr (GEO == kMetricBox) {
-        const BoxMetric &bm = a.bm;
-        const double omz = 1.0 - ((double)be.ez + 0.5 * (1.0 + a.xi[k])) * bm.inz;  // 1 - z/H
-        const double za = omz * hx, zb = omz * hy;
-        const double zc = (1.0 - hh * bm.iH) * bm.zz;
-        const double izc = 1.0 / zc;
-        mx[0] = (T)bm.ixa;
-        mx[4] = (T)bm.iyb;
-        mx[6] = (T)(-za * bm.ixa * izc);
-        mx[7] = (T)(-zb * bm.iyb * izc);
-        mx[8] = (T)izc;
-        mx[9] = (T)(bm.xa * bm.yb * zc * (a.w[i] * a.w[j] * a.w[k]));
+        const double omz = 1.0 - ((double)be.ez + 0.5 * (1.0 + zk)) * a.bm.inz;  // 1 - z/H
+        mx[0] = (T)a.bm.ixa;
+        mx[4] = (T)a.bm.iyb;
+        mx[6] = (T)(omz * c2);
+        mx[7] = (T)(omz * c3);
+        mx[8] = (T)c1;
+        mx[9] = (T)c0;
     }
     // reference derivatives of every field, then the chain rule through the
     // metric: for the advected fields directly in contravariant form,
@@ -298,12 +291,16 @@ __device__ inline void noflux(const PointArgs &p, int64_t I, double &r1, double 
     r3 -= dn * n2;
 }
 
-// SSP-RK3 stage combination (Shu-Osher form)
-__device__ inline double rk_combine(int stage, double qn, double y)
+// SSP-RK3 stage update (Shu-Osher form): y = q_s + dt R, then
+// q_out = a q^n + b y with (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3).  The
+// contractions are written out (fma) so that every kernel that updates a
+// state rounds it the same way.
+__device__ inline double rk_update(int stage, double qn, double qs, double dt, double r)
 {
+    const double y = fma(dt, r, qs);
     if (stage == 0) return y;
-    if (stage == 1) return 0.75 * qn + 0.25 * y;
-    return (1.0 / 3.0) * qn + (2.0 / 3.0) * y;
+    if (stage == 1) return fma(0.25, y, 0.75 * qn);
+    return fma(2.0 / 3.0, y, (1.0 / 3.0) * qn);
 }
 
 // Finish of a fused stage on the box.  A block takes SEG consecutive elements
@@ -362,27 +359,48 @@ __device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin
     } else {
         cz[0] = ez; lz[0] = kl; nzc = 1;  // kl == N only for the top wall layer
     }
-    double r[5] = {0, 0, 0, 0, 0};
-    for (int z = 0; z < nzc; ++z)
-        for (int y = 0; y < nyc; ++y)
-            for (int x = 0; x < nxc; ++x) {
-                const int32_t e = cx[x] + b.nx * (cy[y] + b.ny * cz[z]);
-                const int32_t c = e * NP + lx[x] + P * (ly[y] + P * lz[z]);
-                const T *src = ev + (int64_t)c * 5;  // node-major [n_local][5]
-#pragma unroll
-                for (int v = 0; v < 5; ++v) r[v] += (double)src[v];
-            }
+    // the loads that do not depend on the sum are issued first
+    const double *qsi = qs + I, *qni = qn + I;
+    double *qoi = qout + I;
     const double mi = p.Minv[I];
+    double qsv[5], qnv[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        qsv[v] = qsi[v * p.nu];
+        qnv[v] = stage == 0 ? 0.0 : qni[v * p.nu];
+    }
+    // copies of one z layer: the up to four (y, x) copies are loaded together
+    // (absent ones re-read the first copy and count zero), so a node waits
+    // for one round trip per z layer instead of one per copy
+    if (nxc == 1) { cx[1] = cx[0]; lx[1] = lx[0]; }
+    if (nyc == 1) { cy[1] = cy[0]; ly[1] = ly[0]; }
+    double r[5] = {0, 0, 0, 0, 0};
+    for (int z = 0; z < nzc; ++z) {
+        T c[4][5];
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const int32_t e = cx[x] + b.nx * (cy[y] + b.ny * cz[z]);
+                const int32_t cc = e * NP + lx[x] + P * (ly[y] + P * lz[z]);
+                const T *src = ev + (int64_t)cc * 5;  // node-major [n_local][5]
+#pragma unroll
+                for (int v = 0; v < 5; ++v) c[2 * y + x][v] = src[v];
+            }
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const bool has = y < nyc && x < nxc;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) r[v] += has ? (double)c[2 * y + x][v] : 0.0;
+            }
+    }
 #pragma unroll
     for (int v = 0; v < 5; ++v) r[v] *= mi;
     noflux(p, I, r[1], r[2], r[3]);
-    const double *qsi = qs + I, *qni = qn + I;
-    double *qoi = qout + I;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        const double y = qsi[v * p.nu] + dt * r[v];
-        qoi[v * p.nu] = rk_combine(stage, stage == 0 ? 0.0 : qni[v * p.nu], y);
-    }
+    for (int v = 0; v < 5; ++v) qoi[v * p.nu] = rk_update(stage, qnv[v], qsv[v], dt, r[v]);
 }
 
 // x-segment length of a box finish block: whole 128-byte lines of FP64 state

@@ -278,7 +278,7 @@ uint64_t layout_workspace(Mesh &m, int32_t prec_mask, char *base)
     if (m.d.kind == NUMA_MESH_SHELL) v.grav = (double *)take(24ull * m.nu);
     v.nrm = (double *)take(48ull * m.nh);
     v.xu = (double *)take(24ull * m.nu);
-    if (m.d.kind == NUMA_MESH_BOX) v.hcol = (double *)take(24ull * m.d.ne[0] * m.d.ne[1] * m.P * m.P);
+    if (m.d.kind == NUMA_MESH_BOX) v.hcol = (double *)take(32ull * m.d.ne[0] * m.d.ne[1] * m.P * m.P);
     v.own = (int32_t *)take(4ull * m.nu);
     v.toff = (int32_t *)take(4ull * (m.nu + 1));
     v.tidx = (int32_t *)take(4ull * m.nl);

@@ -82,7 +82,7 @@ struct DeviceView {
     double *grav = nullptr;    // shell: [3][n_unique]
     double *nrm = nullptr;     // [2][3][n_horiz] bottom and top wall normals
     double *xu = nullptr;      // [3][n_unique] unique coordinates
-    double *hcol = nullptr;    // box: [nx*ny][3][(N+1)^2] terrain h, dh/dxi, dh/deta per element column
+    double *hcol = nullptr;    // box: [nx*ny][4][(N+1)^2] column factors of the recomputed metric
     int32_t *own = nullptr;    // [n_unique] unique ids in first-occurrence order of the element scan
     int32_t *toff = nullptr;   // [n_unique+1] copy offsets in that order
     int32_t *tidx = nullptr;   // [n_local] copies (e*np + l), ascending per node, in that order
