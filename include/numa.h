@@ -137,15 +137,18 @@ int32_t numa_mesh_attach_workspace(numa_mesh_t m, void *dev_ptr, uint64_t bytes,
  * computes element-local coordinates, the metric terms and J w by derivative
  * contractions of the coordinates (isoparametric), the mass matrix
  * M_I = sum_e w_ijk J^e (Eq. (discstrongform)) and its inverse, the reference
- * state, gravity and wall normals, into the workspace.  Asynchronous. */
+ * state, gravity, wall normals and (box) the column factors of the
+ * recomputed metric, into the workspace.  Asynchronous. */
 int32_t numa_geometry(numa_mesh_t m, const numa_phys *ph, void *stream);
 
 /* Metric terms of the element kernels (numa_rhs, numa_step, numa_step_batch).
  * NUMA_METRIC_STORED (default) reads the 9 inverse-metric entries and J w
  * computed by numa_geometry at every element-local node.  NUMA_METRIC_RECOMPUTE
  * (box meshes) recomputes the same isoparametric metric of the
- * terrain-following map in the kernel every stage from 2(N+1) sines per
- * element, so the metric costs no memory traffic (the paper's next step,
+ * terrain-following map in the kernel every stage from four factors per
+ * element column and local (i, j) (J w without w_k, 1/z_zeta and the two
+ * terrain slopes over x_xi z_zeta, y_eta z_zeta; numa_geometry computes them),
+ * so the per-node metric costs no memory traffic (the paper's next step,
  * Sec. "Next Steps": recompute the metric terms in each stage).  Host only;
  * returns NUMA_EUNSUPPORTED on a shell. */
 int32_t numa_mesh_set_metric(numa_mesh_t m, int32_t mode);

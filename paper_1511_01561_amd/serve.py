@@ -54,13 +54,15 @@ class Slot:
 
 class GpuExecutor:
     """libnuma on one GPU: geometry per mesh shape (shared, read-only), and per
-    request a state and private scratch in device memory."""
+    request a state and private scratch in device memory.  Box meshes run with
+    the metric recomputed every stage unless metric says otherwise."""
 
-    def __init__(self, prec=0, device="cuda:0", use_graphs=True):
+    def __init__(self, prec=0, device="cuda:0", use_graphs=True, metric=None):
         import torch
         from . import numa
         self.torch, self.numa = torch, numa
         self.prec = prec
+        self.metric = numa.METRIC_RECOMPUTE if metric is None else metric
         self.device = device
         self.use_graphs = use_graphs
         self.stream = torch.cuda.Stream(device=device)  # default priority
@@ -73,6 +75,8 @@ class GpuExecutor:
             with self.torch.cuda.stream(self.stream):
                 g = self.numa.Mesh(req.workload["mesh"], req.workload["phys"], prec_mask=1 | (2 if self.prec else 0),
                                    device=self.device, stream=self.stream)
+                if req.workload["mesh"]["kind"] == self.numa.MESH_BOX:
+                    g.set_metric(self.metric)
             self._geoms[req.key] = g
         return g
 
