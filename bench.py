@@ -320,7 +320,7 @@ def main():
         mixed["dtype"] = "f32 contractions / f64 state"
     # roofline of the dominant kernel of the headline path
     el, fin = head["element_kernel"], head["finish_kernel"]
-    dom_name, dom = (("k_elem_batch<4,double,recomputed metric>", el) if el["avg_launch_us"] >= fin["avg_launch_us"]
+    dom_name, dom = (("k_elem_col<4,double> (recomputed metric)", el) if el["avg_launch_us"] >= fin["avg_launch_us"]
                      else ("k_fin_batch<4,4,double>", fin))
     traffic = load_traffic("stage", workload) if dom is el else None
     roofline = dict(kernel=dom_name, bound="hbm", achieved=dom["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",

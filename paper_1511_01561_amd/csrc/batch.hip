@@ -28,11 +28,13 @@ struct BatchItem {
     int64_t nu, nh;
     int ni, nj, nkw;      // lattice extents; nkw: extent in z when periodic, else -1
     int nz, walls;
+    int ne;               // elements
     int mblk;             // finish blocks of the main layers: (nx/SEG) ny nz
     FastDiv fx, fy, fseg;  // division by nx, ny and nx/SEG
     double dt;
     BoxMetric bm;          // constants of the recomputed metric
-    int eoff, boff;        // first element / finish block of this item in the launch
+    int eoff, boff;        // first element / finish block of this item in the launch (eoff: a
+                           // multiple of the elements per element workgroup)
 };
 
 struct Batch {
@@ -53,14 +55,10 @@ __device__ __forceinline__ int batch_item(const Batch &B, int g, bool fin)
     return k;
 }
 
-template <int N, typename T, int GEO>
-__global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
+// element-kernel arguments of one batch item
+template <typename T>
+__device__ __forceinline__ RhsArgs<T> elem_args(const Batch &B, const BatchItem &it)
 {
-    constexpr int NP = (N + 1) * (N + 1) * (N + 1), BT = block_threads<N>();
-    __shared__ T s[8][NP];
-    const int g = (int)xcd_remap(blockIdx.x, gridDim.x);
-    const BatchItem &it = B.it[batch_item(B, g, false)];
-    const int e = g - it.eoff;
     RhsArgs<T> a;
     a.G = nullptr;
     a.q = it.qs;
@@ -87,12 +85,38 @@ __global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
     a.xi = B.xi;
     a.w = B.w;
     a.Dd = B.Dd;
+    return a;
+}
+
+// node-major [n_local][5] output of element e (a copy's five values in one
+// run for the finish), staged through LDS (st, 5 (N+1)^3 values) so that the
+// block writes them as one contiguous, coalesced run; the caller has
+// synchronised after writing st
+template <int N, typename T>
+__device__ __forceinline__ void store_contributions(const BatchItem &it, int e, int l, const T *st)
+{
+    constexpr int NP = (N + 1) * (N + 1) * (N + 1), BT = block_threads<N>();
+    T *out = (T *)it.ev + (int64_t)e * (NP * 5);
+#pragma unroll
+    for (int r = 0; r < (NP * 5 + BT - 1) / BT; ++r) {
+        const int t = l + r * BT;
+        if (t < NP * 5) out[t] = st[t];
+    }
+}
+
+// One workgroup per element (the launch-wide element index, XCD-remapped).
+template <int N, typename T, int GEO>
+__global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
+{
+    constexpr int NP = (N + 1) * (N + 1) * (N + 1);
+    __shared__ T s[8][NP];
+    const int g = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const BatchItem &it = B.it[batch_item(B, g, false)];
+    const int e = g - it.eoff;
+    const RhsArgs<T> a = elem_args<T>(B, it);
     NodeOut<T> o;
     const int l = threadIdx.x;
     const bool act = element_rhs<N, T, false, GEO>(a, e, l, s, o);
-    // node-major [n_local][5] output (a copy's five values in one run for the
-    // finish), staged through the tile so that the block writes its 5 (N+1)^3
-    // values as one contiguous, coalesced run
     __syncthreads();  // every lane has finished reading the tile
     T *st = &s[0][0];
     if (act) {
@@ -100,12 +124,157 @@ __global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
         for (int v = 0; v < 5; ++v) st[l * 5 + v] = o.Jw * o.R[v];
     }
     __syncthreads();
-    T *out = (T *)it.ev + (int64_t)e * (NP * 5);
+    store_contributions<N, T>(it, e, l, st);
+}
+
+// Column variant for the recomputed box metric: a workgroup takes EB
+// consecutive elements and a lane one (i, j) column of one of them, i.e. the
+// N+1 nodes (i, j, 0..N).  The lane gathers its column (all loads in flight
+// together), evaluates the equation of state and keeps the column's fields in
+// registers: the zeta derivatives are contractions with D_km, which is the
+// same for every lane, so they need no LDS.  Only the xi and eta derivatives
+// read the element tile.  The arithmetic per node is that of element_rhs.
+// Elements per workgroup: as many columns as fill two wavefronts (one
+// element at N = 7 and 8), which keeps the tile (8 fields of (N+1)^3 nodes
+// per element) within 47 KB.
+template <int N, typename T>
+constexpr int col_eb()
+{
+    constexpr int PP = (N + 1) * (N + 1);
+    return N >= 7 ? 1 : (128 / PP > 0 ? 128 / PP : 1);
+}
+template <int N, typename T>
+constexpr int col_threads() { return ((col_eb<N, T>() * (N + 1) * (N + 1) + 63) / 64) * 64; }
+
+template <int N, typename T>
+__global__ __launch_bounds__((col_threads<N, T>())) void k_elem_col(Batch B)
+{
+    constexpr int P = N + 1, PP = P * P, NP = PP * P, EB = col_eb<N, T>(), BT = col_threads<N, T>();
+    __shared__ T s[EB][8][NP];
+    const int g0 = (int)xcd_remap(blockIdx.x, gridDim.x) * EB;
+    const BatchItem &it = B.it[batch_item(B, g0, false)];
+    const RhsArgs<T> a = elem_args<T>(B, it);
+    const int e0 = g0 - it.eoff;  // first element of the workgroup in the item
+    const int t = threadIdx.x, q = t / PP, c = t % PP, i = c % P, j = c / P;
+    const bool act = q < EB && e0 + q < it.ne;
+    // per node of the column: 1/rho and rho'/rho (formed in FP64), zeta
+    // derivatives of the 8 tile fields
+    T irho[P], buoy[P], dz[8][P];
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+    int ez = 0;
+    if (act) {
+        const BoxElem be = box_elem((uint32_t)(e0 + q), a.fx, a.fy);
+        ez = be.ez;
+        const double *cp = a.hcol + (int64_t)(be.ex + a.nx * be.ey) * (4 * PP) + c;
+        c0 = cp[0];
+        c1 = cp[PP];
+        c2 = cp[2 * PP];
+        c3 = cp[3 * PP];
+        int gi = be.ex * N + i, gj = be.ey * N + j;
+        if (gi == a.ni) gi = 0;
+        if (gj == a.nj) gj = 0;
+        const int base = gi + a.ni * gj, layer = a.ni * a.nj;
+        T col[8][P];
 #pragma unroll
-    for (int r = 0; r < (NP * 5 + BT - 1) / BT; ++r) {
-        const int t = l + r * BT;
-        if (t < NP * 5) out[t] = st[t];
+        for (int k = 0; k < P; ++k) {
+            int gk = be.ez * N + k;
+            if (gk == a.nk) gk = 0;
+            const int32_t I = base + layer * gk;
+            const double *qp = a.q + I, *rf = a.ref + I;
+            const double rp = qp[0], u = qp[a.nu], v = qp[2 * a.nu], w = qp[3 * a.nu], tp = qp[4 * a.nu];
+            const double rb = rf[0], tb = rf[a.nu], pb = rf[2 * a.nu];
+            const double rho = rb + rp;
+            // p' = p_bar ((rho theta / rho_bar theta_bar)^gamma - 1) without cancellation
+            const double dl = rp * tb + rb * tp + rp * tp;
+            const double pp = pb * eos_rel(dl / (rb * tb), a.gamma, a.eos);
+            const double ir = 1.0 / rho;
+            irho[k] = (T)ir;
+            buoy[k] = (T)(rp * ir);
+            col[0][k] = (T)(rho * u);
+            col[1][k] = (T)(rho * v);
+            col[2][k] = (T)(rho * w);
+            col[3][k] = (T)u;
+            col[4][k] = (T)v;
+            col[5][k] = (T)w;
+            col[6][k] = (T)tp;
+            col[7][k] = (T)pp;
+#pragma unroll
+            for (int f = 0; f < 8; ++f) s[q][f][c + PP * k] = col[f][k];
+        }
+        const T *D = a.D;
+#pragma unroll
+        for (int f = 0; f < 8; ++f)
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                T d = 0;
+#pragma unroll
+                for (int m = 0; m < P; ++m) d += D[k * P + m] * col[f][m];
+                dz[f][k] = d;
+            }
     }
+    __syncthreads();  // tiles complete
+    T res[P][5];
+    if (act) {
+        T Di[P], Dj[P];
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+            Di[m] = a.D[i * P + m];
+            Dj[m] = a.D[j * P + m];
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            T mx[10];
+            box_node_metric<T>(a.bm, ez, B.xi[k], c0 * B.w[k], c1, c2, c3, mx);
+            T dd[8][3];
+#pragma unroll
+            for (int f = 0; f < 8; ++f) {
+                T da = 0, db = 0;
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
+                    da += Di[m] * s[q][f][m + P * (j + P * k)];
+                    db += Dj[m] * s[q][f][i + P * (m + P * k)];
+                }
+                dd[f][0] = da;
+                dd[f][1] = db;
+                dd[f][2] = dz[f][k];
+            }
+            const int l = c + PP * k;
+            // node_combine with 1/rho and rho'/rho already formed
+            const T uu = s[q][3][l], vv = s[q][4][l], ww = s[q][5][l];
+            T Uc[3];
+            Uc[0] = uu * mx[0];
+            Uc[1] = vv * mx[4];
+            Uc[2] = uu * mx[6] + vv * mx[7] + ww * mx[8];
+            auto cart = [&](int f, int cc) -> T {
+                if (cc == 0) return dd[f][0] * mx[0] + dd[f][2] * mx[6];
+                if (cc == 1) return dd[f][1] * mx[4] + dd[f][2] * mx[7];
+                return dd[f][2] * mx[8];
+            };
+            auto adv = [&](int f) -> T { return Uc[0] * dd[f][0] + Uc[1] * dd[f][1] + Uc[2] * dd[f][2]; };
+            const T gz = (T)(-a.g0);
+            T R[5];
+            R[0] = -(cart(0, 0) + cart(1, 1) + cart(2, 2));
+            R[1] = -adv(3) - cart(7, 0) * irho[k];
+            R[2] = -adv(4) - cart(7, 1) * irho[k];
+            R[3] = -adv(5) - cart(7, 2) * irho[k] + buoy[k] * gz;
+            R[4] = -adv(6);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) res[k][v] = mx[9] * R[v];
+        }
+    }
+    __syncthreads();  // tiles read
+    T *st = &s[0][0][0];
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) st[(q * NP + c + PP * k) * 5 + v] = res[k][v];
+    }
+    __syncthreads();
+    // the workgroup's elements are consecutive: one contiguous run
+    const int ne = it.ne - e0 < EB ? it.ne - e0 : EB;
+    T *out = (T *)it.ev + (int64_t)e0 * (NP * 5);
+    for (int u = t; u < ne * NP * 5; u += BT) out[u] = st[u];
 }
 
 template <int N, int SEG, typename T>
@@ -158,6 +327,12 @@ int32_t run_chunk(const StepItem *items, int n, int stage, int phase, hipStream_
     B.w = items[0].mesh->dv.w64;
     B.Dd = items[0].mesh->dv.D64;
     eos_coeffs(B.gamma, B.eos);
+    // the recomputed metric runs the column kernel, EB elements per workgroup
+    // (FP64 above N = 4 its registers outgrow it: one node per lane there)
+    constexpr bool col_ok = sizeof(T) == 4 || N <= 4;
+    const bool recompute = items[0].mesh->metric_mode == NUMA_METRIC_RECOMPUTE;
+    const bool col = recompute && col_ok;
+    const int eb = col ? col_eb<N, T>() : 1;
     int64_t eo = 0, bo = 0;
     for (int k = 0; k < n; ++k) {
         const Mesh &m = *items[k].mesh;
@@ -185,9 +360,10 @@ int32_t run_chunk(const StepItem *items, int n, int stage, int phase, hipStream_
         it.mblk = (int)mblk;
         it.dt = items[k].dt;
         it.bm = box_metric(m);
+        it.ne = (int)m.ne;
         it.eoff = (int)eo;
         it.boff = (int)bo;
-        eo += m.ne;
+        eo += (m.ne + eb - 1) / eb * eb;
         bo += mblk + (m.walls ? (int64_t)(m.d.ne[0] / SEG) * m.d.ne[1] : 0);
     }
     if (eo >= (int64_t(1) << 31) || bo >= (int64_t(1) << 31)) {
@@ -196,11 +372,14 @@ int32_t run_chunk(const StepItem *items, int n, int stage, int phase, hipStream_
     }
     for (int k = n; k < kMaxBatch; ++k) B.it[k] = BatchItem{};
     if (phase == 0) {
-        if (items[0].mesh->metric_mode == NUMA_METRIC_RECOMPUTE)
-            hipLaunchKernelGGL((k_elem_batch<N, T, kMetricBox>), dim3((unsigned)eo), dim3(block_threads<N>()), 0, s, B);
-        else
+        if (!recompute) {
             hipLaunchKernelGGL((k_elem_batch<N, T, kMetricStored>), dim3((unsigned)eo), dim3(block_threads<N>()), 0, s,
                                B);
+        } else if constexpr (col_ok) {
+            hipLaunchKernelGGL((k_elem_col<N, T>), dim3((unsigned)(eo / eb)), dim3(col_threads<N, T>()), 0, s, B);
+        } else {
+            hipLaunchKernelGGL((k_elem_batch<N, T, kMetricBox>), dim3((unsigned)eo), dim3(block_threads<N>()), 0, s, B);
+        }
     } else {
         const int threads = ((SEG * N * N * N + 63) / 64) * 64;
         hipLaunchKernelGGL((k_fin_batch<N, SEG, T>), dim3((unsigned)bo), dim3(threads), 0, s, B);

@@ -106,9 +106,22 @@ struct NodeOut {
     T Jw;
 };
 
-// Gathers the element tile, differentiates it and evaluates R at node l of
-// element e.  Must be called by all lanes of the block (it synchronises);
-// returns false for the padding lanes (l >= (N+1)^3).
+// Operands of node l that are loaded before its element's tile is built:
+// state, reference, and the metric (stored) or the column factors (recomputed).
+template <typename T>
+struct NodeIn {
+    double rp, u, v, w, tp, rb, tb, pb;
+    double c0, c1, c2, c3, zk;  // box, recomputed metric: column factors (c0 with w_k), xi_k
+    T mx[10];                   // stored metric: inverse metric (9) and J w
+    int32_t I;                  // unique id
+    int ez;                     // box: element layer
+};
+
+// The three phases of the element right-hand side at node l of element e:
+// node_gather issues the loads, node_stage evaluates the equation of state
+// and writes the node's fields into the element tile, node_derive (after a
+// barrier) differentiates the tile and evaluates R.  element_rhs runs them in
+// order.
 //
 // GEO == kMetricBox (box meshes): the isoparametric metric of the
 // terrain-following map x = x(xi), y = y(eta), z' = z(zeta) + h(x, y)(1 - z/H)
@@ -116,87 +129,108 @@ struct NodeOut {
 // k_box_columns) and its undeformed level z/H, xi_x = 2 nx/Lx,
 // eta_y = 2 ny/Ly, zeta = ((1 - z/H) c2, (1 - z/H) c3, c1), J w = c0 w_k, all
 // other entries zero.
-template <int N, typename T, bool SHELL, int GEO = kMetricStored>
-__device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int l, T (*s)[(N + 1) * (N + 1) * (N + 1)],
-                                            NodeOut<T> &o)
+template <int N, typename T, bool SHELL, int GEO>
+__device__ __forceinline__ void node_gather(const RhsArgs<T> &a, int64_t e, int l, NodeIn<T> &in)
 {
     constexpr int P = N + 1, PP = P * P, NP = PP * P;
-    const bool act = l < NP;
+    if (l >= NP) return;
     const int i = l % P, j = (l / P) % P, k = l / PP;
-    double rp = 0.0, rho = 1.0, u = 0.0, v = 0.0, w = 0.0, tp = 0.0;
-    // metric terms (or the column terrain) do not depend on the tile: load
-    // them before the barrier so that their latency overlaps the state gather
-    // and the equation of state
-    T mx[10];
-    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0, zk = 0.0;
-    BoxElem be{0, 0, 0};
-    if constexpr (!SHELL) be = box_elem((uint32_t)e, a.fx, a.fy);
-    int32_t I = 0;
-    if (act) {
-        if constexpr (SHELL) {
-            I = a.G[e * NP + l];
-        } else {
-            I = box_unique<N, T>(a, be, i, j, k);
-        }
-        if constexpr (GEO == kMetricStored) {
-            const T *mp = a.met + e * 10 * NP + l;
-#pragma unroll
-            for (int c = 0; c < 10; ++c) mx[c] = mp[c * NP];
-        } else {
+    if constexpr (SHELL) {
+        in.I = a.G[e * NP + l];
+    } else {
+        const BoxElem be = box_elem((uint32_t)e, a.fx, a.fy);
+        in.I = box_unique<N, T>(a, be, i, j, k);
+        in.ez = be.ez;
+        if constexpr (GEO == kMetricBox) {
             const double *cp = a.hcol + (int64_t)(be.ex + a.nx * be.ey) * (4 * PP) + (i + P * j);
-            c0 = cp[0] * a.w[k];
-            c1 = cp[PP];
-            c2 = cp[2 * PP];
-            c3 = cp[3 * PP];
-            zk = a.xi[k];
-        }
-        const double *qp = a.q + I;
-        rp = qp[0];
-        u = qp[a.nu];
-        v = qp[2 * a.nu];
-        w = qp[3 * a.nu];
-        tp = qp[4 * a.nu];
-        const double *rf = a.ref + I;
-        const double rb = rf[0], tb = rf[a.nu], pb = rf[2 * a.nu];
-        rho = rb + rp;
-        // p' = p_bar ((rho theta / rho_bar theta_bar)^gamma - 1) without cancellation
-        const double dl = rp * tb + rb * tp + rp * tp;
-        const double pp = pb * eos_rel(dl / (rb * tb), a.gamma, a.eos);
-        s[0][l] = (T)(rho * u);
-        s[1][l] = (T)(rho * v);
-        s[2][l] = (T)(rho * w);
-        s[3][l] = (T)u;
-        s[4][l] = (T)v;
-        s[5][l] = (T)w;
-        s[6][l] = (T)tp;
-        s[7][l] = (T)pp;
-        if constexpr (SHELL) {
-            // the background theta is differentiated relative to the element's first node
-            const double t0 = a.ref[a.nu + a.G[e * NP]];
-            s[8][l] = (T)(tb - t0);
+            in.c0 = cp[0] * a.w[k];
+            in.c1 = cp[PP];
+            in.c2 = cp[2 * PP];
+            in.c3 = cp[3 * PP];
+            in.zk = a.xi[k];
         }
     }
-    __syncthreads();
-    if (!act) return false;
-    T Di[P], Dj[P], Dk[P];
+    if constexpr (GEO == kMetricStored) {
+        const T *mp = a.met + e * 10 * NP + l;
+#pragma unroll
+        for (int c = 0; c < 10; ++c) in.mx[c] = mp[c * NP];
+    }
+    const double *qp = a.q + in.I;
+    in.rp = qp[0];
+    in.u = qp[a.nu];
+    in.v = qp[2 * a.nu];
+    in.w = qp[3 * a.nu];
+    in.tp = qp[4 * a.nu];
+    const double *rf = a.ref + in.I;
+    in.rb = rf[0];
+    in.tb = rf[a.nu];
+    in.pb = rf[2 * a.nu];
+}
+
+template <int N, typename T, bool SHELL>
+__device__ __forceinline__ void node_stage(const RhsArgs<T> &a, int64_t e, int l, const NodeIn<T> &in,
+                                           T (*s)[(N + 1) * (N + 1) * (N + 1)])
+{
+    constexpr int NP = (N + 1) * (N + 1) * (N + 1);
+    if (l >= NP) return;
+    const double rho = in.rb + in.rp;
+    // p' = p_bar ((rho theta / rho_bar theta_bar)^gamma - 1) without cancellation
+    const double dl = in.rp * in.tb + in.rb * in.tp + in.rp * in.tp;
+    const double pp = in.pb * eos_rel(dl / (in.rb * in.tb), a.gamma, a.eos);
+    s[0][l] = (T)(rho * in.u);
+    s[1][l] = (T)(rho * in.v);
+    s[2][l] = (T)(rho * in.w);
+    s[3][l] = (T)in.u;
+    s[4][l] = (T)in.v;
+    s[5][l] = (T)in.w;
+    s[6][l] = (T)in.tp;
+    s[7][l] = (T)pp;
+    if constexpr (SHELL) {
+        // the background theta is differentiated relative to the element's first node
+        const double t0 = a.ref[a.nu + a.G[e * NP]];
+        s[8][l] = (T)(in.tb - t0);
+    }
+}
+
+// rows i, j, k of D for node l (l < (N+1)^3)
+template <int N, typename T>
+__device__ __forceinline__ void d_rows(const T *D, int l, T *Di, T *Dj, T *Dk)
+{
+    constexpr int P = N + 1, PP = P * P;
+    const int i = l % P, j = (l / P) % P, k = l / PP;
 #pragma unroll
     for (int m = 0; m < P; ++m) {
-        Di[m] = a.D[i * P + m];
-        Dj[m] = a.D[j * P + m];
-        Dk[m] = a.D[k * P + m];
+        Di[m] = D[i * P + m];
+        Dj[m] = D[j * P + m];
+        Dk[m] = D[k * P + m];
     }
-    if constexpr (GEO == kMetricBox) {
-        const double omz = 1.0 - ((double)be.ez + 0.5 * (1.0 + zk)) * a.bm.inz;  // 1 - z/H
-        mx[0] = (T)a.bm.ixa;
-        mx[4] = (T)a.bm.iyb;
-        mx[6] = (T)(omz * c2);
-        mx[7] = (T)(omz * c3);
-        mx[8] = (T)c1;
-        mx[9] = (T)c0;
-    }
-    // reference derivatives of every field, then the chain rule through the
-    // metric: for the advected fields directly in contravariant form,
-    // u . grad f = sum_d U_d df/dxi_d with U_d = u . grad(xi_d)
+}
+
+// metric of a box node with the recomputed metric: column factors c0..c3,
+// element layer ez and xi_k
+template <typename T>
+__device__ __forceinline__ void box_node_metric(const BoxMetric &bm, int ez, double zk, double c0, double c1, double c2,
+                                                double c3, T *mx)
+{
+    const double omz = 1.0 - ((double)ez + 0.5 * (1.0 + zk)) * bm.inz;  // 1 - z/H
+    mx[0] = (T)bm.ixa;
+    mx[4] = (T)bm.iyb;
+    mx[6] = (T)(omz * c2);
+    mx[7] = (T)(omz * c3);
+    mx[8] = (T)c1;
+    mx[9] = (T)c0;
+}
+
+// R at one node from the reference derivatives dd[f][d] of the tile fields
+// (d = xi, eta, zeta) and the metric mx: the chain rule, for the advected
+// fields directly in contravariant form, u . grad f = sum_d U_d df/dxi_d with
+// U_d = u . grad(xi_d).  With GEO == kMetricBox only the entries of the
+// box metric are read (xi_x, eta_y, zeta_x, zeta_y, zeta_z), and the
+// contractions the chain rule does not use are never formed.
+template <typename T, bool SHELL, int GEO>
+__device__ __forceinline__ void node_combine(const RhsArgs<T> &a, const T (*dd)[3], const T *mx, double u, double v,
+                                             double w, double rp, double rb, int32_t I, NodeOut<T> &o)
+{
     const T uu = (T)u, vv = (T)v, ww = (T)w;
     T Uc[3];
     if constexpr (GEO == kMetricBox) {
@@ -207,21 +241,6 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
         Uc[0] = uu * mx[0] + vv * mx[1] + ww * mx[2];
         Uc[1] = uu * mx[3] + vv * mx[4] + ww * mx[5];
         Uc[2] = uu * mx[6] + vv * mx[7] + ww * mx[8];
-    }
-    constexpr int NF = SHELL ? 9 : 8;
-    T dd[NF][3];
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-        T da = 0, db = 0, dc = 0;
-#pragma unroll
-        for (int m = 0; m < P; ++m) {
-            da += Di[m] * s[f][m + P * (j + P * k)];
-            db += Dj[m] * s[f][i + P * (m + P * k)];
-            dc += Dk[m] * s[f][i + P * (j + P * m)];
-        }
-        dd[f][0] = da;
-        dd[f][1] = db;
-        dd[f][2] = dc;
     }
     // Cartesian derivative d/dx_c of field f (row c of the inverse metric)
     auto cart = [&](int f, int c) -> T {
@@ -234,7 +253,7 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
         }
     };
     auto adv = [&](int f) -> T { return Uc[0] * dd[f][0] + Uc[1] * dd[f][1] + Uc[2] * dd[f][2]; };
-    const double irho64 = 1.0 / rho;
+    const double irho64 = 1.0 / (rb + rp);
     const T irho = (T)irho64;
     const T buoy = (T)(rp * irho64);
     T gx = 0, gy = 0, gz = (T)(-a.g0);
@@ -250,6 +269,58 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
     o.R[4] = -adv(6);
     if constexpr (SHELL) o.R[4] -= adv(8);
     o.Jw = mx[9];
+}
+
+template <int N, typename T, bool SHELL, int GEO>
+__device__ __forceinline__ void node_derive(const RhsArgs<T> &a, int l, const NodeIn<T> &in, const T *Di,
+                                            const T *Dj, const T *Dk, T (*s)[(N + 1) * (N + 1) * (N + 1)],
+                                            NodeOut<T> &o)
+{
+    constexpr int P = N + 1, PP = P * P;
+    const int i = l % P, j = (l / P) % P, k = l / PP;
+    T mx[10];
+    if constexpr (GEO == kMetricBox) {
+        box_node_metric<T>(a.bm, in.ez, in.zk, in.c0, in.c1, in.c2, in.c3, mx);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 10; ++c) mx[c] = in.mx[c];
+    }
+    // reference derivatives of every field (the unused ones are dropped by
+    // the compiler), then R
+    constexpr int NF = SHELL ? 9 : 8;
+    T dd[NF][3];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        T da = 0, db = 0, dc = 0;
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+            da += Di[m] * s[f][m + P * (j + P * k)];
+            db += Dj[m] * s[f][i + P * (m + P * k)];
+            dc += Dk[m] * s[f][i + P * (j + P * m)];
+        }
+        dd[f][0] = da;
+        dd[f][1] = db;
+        dd[f][2] = dc;
+    }
+    node_combine<T, SHELL, GEO>(a, dd, mx, in.u, in.v, in.w, in.rp, in.rb, in.I, o);
+}
+
+// Gathers the element tile, differentiates it and evaluates R at node l of
+// element e.  Must be called by all lanes of the block (it synchronises);
+// returns false for the padding lanes (l >= (N+1)^3).
+template <int N, typename T, bool SHELL, int GEO = kMetricStored>
+__device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int l, T (*s)[(N + 1) * (N + 1) * (N + 1)],
+                                            NodeOut<T> &o)
+{
+    constexpr int P = N + 1, NP = P * P * P;
+    NodeIn<T> in;
+    node_gather<N, T, SHELL, GEO>(a, e, l, in);
+    node_stage<N, T, SHELL>(a, e, l, in, s);
+    __syncthreads();
+    if (l >= NP) return false;
+    T Di[P], Dj[P], Dk[P];
+    d_rows<N, T>(a.D, l, Di, Dj, Dk);
+    node_derive<N, T, SHELL, GEO>(a, l, in, Di, Dj, Dk, s, o);
     return true;
 }
 

@@ -101,3 +101,47 @@ def test_shell_refuses_recomputed_metric(torch_cuda):
     g = numa.Mesh(wl["mesh"], wl["phys"], prec_mask=1)
     with pytest.raises(numa.NumaError):
         g.set_metric(numa.METRIC_RECOMPUTE)
+
+
+@pytest.mark.parametrize("N,ne,perz", [(1, (4, 3, 3), 0), (2, (8, 3, 2), 0), (3, (4, 3, 3), 1), (4, (4, 3, 3), 0),
+                                       (5, (4, 5, 1), 0), (6, (4, 3, 2), 1), (7, (2, 3, 2), 0), (8, (2, 2, 2), 0)])
+def test_step_parity_all_orders_recomputed_metric(torch_cuda, oracle_mod, N, ne, perz):
+    """Every order through the recomputed-metric stage kernels (several
+    elements per workgroup, element counts that leave the last workgroup of
+    the mesh partly empty), FP64 against the oracle and the mixed path within
+    the mixed tolerance of it."""
+    from paper_1511_01561_amd import numa
+    p = recompute_pair(terrain_box(N, ne, perz), oracle_mod)
+    q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, N))
+    qo = p.o.step(q0, 0.05, 2)
+    qg = p.dev(q0)
+    p.g.step(qg, 0.05, 2)
+    assert_groups(p.host(qg), qo, TOL64, "recomputed step N=%d ne=%s" % (N, ne))
+    qm = p.dev(q0)
+    p.g.step(qm, 0.05, 2, prec=numa.PREC_MIXED)
+    e = group_err(p.host(qm) - q0, qo - q0)
+    print("recomputed mixed 2-step increment", {k: "%.1e" % v for k, v in e.items()})
+    assert max(e.values()) < 1e-4
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("N", [3, 4, 6])
+def test_recomputed_batch_equals_alone_ragged(torch_cuda, prec, N):
+    """Items whose element counts are not multiples of the elements per
+    workgroup, batched: bitwise the same as each alone, both precisions."""
+    from paper_1511_01561_amd import numa
+    torch = torch_cuda
+    objs = []
+    for k, ne in enumerate(((4, 3, 3), (8, 5, 1), (4, 3, 1))):
+        wl = inputs.box_workload(*ne, N, ne[0] * 6250.0, ne[1] * 6250.0, ne[2] * 1250.0, terrain=500.0,
+                                 bubble_centre=(ne[0] * 3000.0, ne[1] * 3000.0, ne[2] * 600.0))
+        g = numa.Mesh(wl["mesh"], wl["phys"], prec_mask=3)
+        g.set_metric(numa.METRIC_RECOMPUTE)
+        q = g.init_state(wl["ic"], inputs.device_noise(g.n_unique, 30 + k))
+        objs.append((g, q, numa.alloc_scratch(g, prec)))
+    alone = [q.clone() for _, q, _ in objs]
+    numa.step_batch([(g, q, s, 0.05) for g, q, s in objs], 2, prec)
+    for (g, _, _), a in zip(objs, alone):
+        g.step(a, 0.05, 2, prec=prec)
+    torch.cuda.synchronize()
+    assert all(torch.equal(q, a) for (_, q, _), a in zip(objs, alone))
