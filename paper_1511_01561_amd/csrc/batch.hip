@@ -277,6 +277,134 @@ __global__ __launch_bounds__((col_threads<N, T>())) void k_elem_col(Batch B)
     for (int u = t; u < ne * NP * 5; u += BT) out[u] = st[u];
 }
 
+// Streaming variant of the column kernel: after the tile is built the lane
+// walks the 8 fields once, reads its own column of each field (the zeta
+// contraction), the xi and eta lines of each of its nodes, and adds the
+// field's terms to the R of its N+1 nodes, so that only R, the advecting
+// contravariant velocity and 1/rho, rho'/rho of the column stay in registers
+// (the terms are added in the order element_rhs sums them).
+template <int N, typename T>
+__global__ __launch_bounds__((col_threads<N, T>())) void k_elem_stream(Batch B)
+{
+    constexpr int P = N + 1, PP = P * P, NP = PP * P, EB = col_eb<N, T>(), BT = col_threads<N, T>();
+    __shared__ T s[EB][8][NP];
+    const int g0 = (int)xcd_remap(blockIdx.x, gridDim.x) * EB;
+    const BatchItem &it = B.it[batch_item(B, g0, false)];
+    const RhsArgs<T> a = elem_args<T>(B, it);
+    const int e0 = g0 - it.eoff;
+    const int t = threadIdx.x, q = t / PP, c = t % PP, i = c % P, j = c / P;
+    const bool act = q < EB && e0 + q < it.ne;
+    T irho[P], buoy[P], Uc[P][3];
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+    int ez = 0;
+    if (act) {
+        const BoxElem be = box_elem((uint32_t)(e0 + q), a.fx, a.fy);
+        ez = be.ez;
+        const double *cp = a.hcol + (int64_t)(be.ex + a.nx * be.ey) * (4 * PP) + c;
+        c0 = cp[0];
+        c1 = cp[PP];
+        c2 = cp[2 * PP];
+        c3 = cp[3 * PP];
+        int gi = be.ex * N + i, gj = be.ey * N + j;
+        if (gi == a.ni) gi = 0;
+        if (gj == a.nj) gj = 0;
+        const int base = gi + a.ni * gj, layer = a.ni * a.nj;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            int gk = be.ez * N + k;
+            if (gk == a.nk) gk = 0;
+            const int32_t I = base + layer * gk;
+            const double *qp = a.q + I, *rf = a.ref + I;
+            const double rp = qp[0], u = qp[a.nu], v = qp[2 * a.nu], w = qp[3 * a.nu], tp = qp[4 * a.nu];
+            const double rb = rf[0], tb = rf[a.nu], pb = rf[2 * a.nu];
+            const double rho = rb + rp;
+            // p' = p_bar ((rho theta / rho_bar theta_bar)^gamma - 1) without cancellation
+            const double dl = rp * tb + rb * tp + rp * tp;
+            const double pp = pb * eos_rel(dl / (rb * tb), a.gamma, a.eos);
+            const double ir = 1.0 / rho;
+            irho[k] = (T)ir;
+            buoy[k] = (T)(rp * ir);
+            T mx[10];
+            box_node_metric<T>(a.bm, ez, B.xi[k], c0, c1, c2, c3, mx);
+            const T uu = (T)u, vv = (T)v, ww = (T)w;
+            Uc[k][0] = uu * mx[0];
+            Uc[k][1] = vv * mx[4];
+            Uc[k][2] = uu * mx[6] + vv * mx[7] + ww * mx[8];
+            const int l = c + PP * k;
+            s[q][0][l] = (T)(rho * u);
+            s[q][1][l] = (T)(rho * v);
+            s[q][2][l] = (T)(rho * w);
+            s[q][3][l] = uu;
+            s[q][4][l] = vv;
+            s[q][5][l] = ww;
+            s[q][6][l] = (T)tp;
+            s[q][7][l] = (T)pp;
+        }
+    }
+    __syncthreads();  // tiles complete
+    T R[P][5];
+    if (act) {
+        T Di[P], Dj[P];
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+            Di[m] = a.D[i * P + m];
+            Dj[m] = a.D[j * P + m];
+        }
+        const T *D = a.D;
+        const T mx0 = (T)a.bm.ixa, mx4 = (T)a.bm.iyb, mx8 = (T)c1;
+#pragma unroll
+        for (int f = 0; f < 8; ++f) {
+            T cf[P];
+#pragma unroll
+            for (int m = 0; m < P; ++m) cf[m] = s[q][f][c + PP * m];
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const double omz = 1.0 - ((double)ez + 0.5 * (1.0 + B.xi[k])) * a.bm.inz;  // 1 - z/H
+                const T mx6 = (T)(omz * c2), mx7 = (T)(omz * c3);
+                T dc = 0, da = 0, db = 0;
+#pragma unroll
+                for (int m = 0; m < P; ++m) dc += D[k * P + m] * cf[m];
+                if (f != 1 && f != 2) {
+#pragma unroll
+                    for (int m = 0; m < P; ++m) da += Di[m] * s[q][f][m + P * (j + P * k)];
+                }
+                if (f != 0 && f != 2) {
+#pragma unroll
+                    for (int m = 0; m < P; ++m) db += Dj[m] * s[q][f][i + P * (m + P * k)];
+                }
+                if (f == 0) R[k][0] = da * mx0 + dc * mx6;                // d(rho u)/dx
+                if (f == 1) R[k][0] = R[k][0] + (db * mx4 + dc * mx7);    // + d(rho v)/dy
+                if (f == 2) R[k][0] = -(R[k][0] + dc * mx8);              // + d(rho w)/dz
+                if (f >= 3 && f <= 6) R[k][f - 2] = -(Uc[k][0] * da + Uc[k][1] * db + Uc[k][2] * dc);
+                if (f == 7) {
+                    R[k][1] = R[k][1] - (da * mx0 + dc * mx6) * irho[k];
+                    R[k][2] = R[k][2] - (db * mx4 + dc * mx7) * irho[k];
+                    R[k][3] = R[k][3] - (dc * mx8) * irho[k] + buoy[k] * (T)(-a.g0);
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const T jw = (T)(c0 * B.w[k]);
+#pragma unroll
+            for (int v = 0; v < 5; ++v) R[k][v] = jw * R[k][v];
+        }
+    }
+    __syncthreads();  // tiles read
+    T *st = &s[0][0][0];
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) st[(q * NP + c + PP * k) * 5 + v] = R[k][v];
+    }
+    __syncthreads();
+    // the workgroup's elements are consecutive: one contiguous run
+    const int ne = it.ne - e0 < EB ? it.ne - e0 : EB;
+    T *out = (T *)it.ev + (int64_t)e0 * (NP * 5);
+    for (int u = t; u < ne * NP * 5; u += BT) out[u] = st[u];
+}
+
 template <int N, int SEG, typename T>
 __global__ void k_fin_batch(Batch B)
 {
@@ -327,9 +455,11 @@ int32_t run_chunk(const StepItem *items, int n, int stage, int phase, hipStream_
     B.w = items[0].mesh->dv.w64;
     B.Dd = items[0].mesh->dv.D64;
     eos_coeffs(B.gamma, B.eos);
-    // the recomputed metric runs the column kernel, EB elements per workgroup
-    // (FP64 above N = 4 its registers outgrow it: one node per lane there)
-    constexpr bool col_ok = sizeof(T) == 4 || N <= 4;
+    // the recomputed metric runs a column kernel, EB elements per workgroup:
+    // registers for every field's column up to N = 4, the streaming variant
+    // above (FP64 at N = 7, 8 outgrows both: one node per lane there)
+    constexpr int kind = N <= 4 ? 0 : (sizeof(T) == 4 || N <= 6 ? 1 : 2);
+    constexpr bool col_ok = kind != 2;
     const bool recompute = items[0].mesh->metric_mode == NUMA_METRIC_RECOMPUTE;
     const bool col = recompute && col_ok;
     const int eb = col ? col_eb<N, T>() : 1;
@@ -375,8 +505,10 @@ int32_t run_chunk(const StepItem *items, int n, int stage, int phase, hipStream_
         if (!recompute) {
             hipLaunchKernelGGL((k_elem_batch<N, T, kMetricStored>), dim3((unsigned)eo), dim3(block_threads<N>()), 0, s,
                                B);
-        } else if constexpr (col_ok) {
+        } else if constexpr (kind == 0) {
             hipLaunchKernelGGL((k_elem_col<N, T>), dim3((unsigned)(eo / eb)), dim3(col_threads<N, T>()), 0, s, B);
+        } else if constexpr (kind == 1) {
+            hipLaunchKernelGGL((k_elem_stream<N, T>), dim3((unsigned)(eo / eb)), dim3(col_threads<N, T>()), 0, s, B);
         } else {
             hipLaunchKernelGGL((k_elem_batch<N, T, kMetricBox>), dim3((unsigned)eo), dim3(block_threads<N>()), 0, s, B);
         }
