@@ -145,3 +145,22 @@ def test_recomputed_batch_equals_alone_ragged(torch_cuda, prec, N):
         g.step(a, 0.05, 2, prec=prec)
     torch.cuda.synchronize()
     assert all(torch.equal(q, a) for (_, q, _), a in zip(objs, alone))
+
+
+def test_full_size_largest_order(torch_cuda, oracle_mod):
+    """The largest configuration of the order sweep, 64x64x16 at N = 8
+    (33.8 M unique nodes), in the launch configuration the benchmark times:
+    one FP64 step against the oracle, and the mixed step within the mixed
+    tolerance of it."""
+    from paper_1511_01561_amd import numa
+    p = recompute_pair(inputs.gpu_box(8), oracle_mod)
+    q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 0))
+    qo = p.o.step(q0, 0.05, 1)
+    qg = p.dev(q0)
+    p.g.step(qg, 0.05, 1)
+    assert_groups(p.host(qg), qo, TOL64, "N=8 full-size step")
+    qm = p.dev(q0)
+    p.g.step(qm, 0.05, 1, prec=numa.PREC_MIXED)
+    e = group_err(p.host(qm) - q0, qo - q0)
+    print("N=8 full-size mixed increment", {k: "%.1e" % v for k, v in e.items()})
+    assert max(e.values()) < 1e-4

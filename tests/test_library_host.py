@@ -119,3 +119,11 @@ def test_gll_rejects_bad_order(L):
     buf = np.zeros(100)
     assert L.numa_gll(0, buf.ctypes.data, buf.ctypes.data, buf.ctypes.data) == -1
     assert L.numa_gll(9, buf.ctypes.data, buf.ctypes.data, buf.ctypes.data) == -1
+
+
+def test_mesh_beyond_32bit_indices_rejected(L):
+    """n_local >= 2^31 (the index width of the gather map and the E-vector
+    copies) is refused before anything is allocated."""
+    rc, h = _create(dict(kind=0, N=1, ne=(1300, 1300, 1300), periodic=(1, 1, 0), extent=(1, 1, 1), h0=0.0))
+    assert rc == -4 and not h.value
+    assert b"32-bit" in L.numa_last_error()
