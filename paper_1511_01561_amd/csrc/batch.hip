@@ -32,6 +32,7 @@ struct BatchItem {
     int mblk;             // finish blocks of the main layers: (nx/SEG) ny nz
     FastDiv fx, fy, fseg;  // division by nx, ny and nx/SEG
     double dt;
+    double theta0;         // the box reference is isentropic: theta_bar = theta0 everywhere
     BoxMetric bm;          // constants of the recomputed metric
     int eoff, boff;        // first element / finish block of this item in the launch (eoff: a
                            // multiple of the elements per element workgroup)
@@ -182,7 +183,7 @@ __global__ __launch_bounds__((col_threads<N, T>())) void k_elem_col(Batch B)
             const int32_t I = base + layer * gk;
             const double *qp = a.q + I, *rf = a.ref + I;
             const double rp = qp[0], u = qp[a.nu], v = qp[2 * a.nu], w = qp[3 * a.nu], tp = qp[4 * a.nu];
-            const double rb = rf[0], tb = rf[a.nu], pb = rf[2 * a.nu];
+            const double rb = rf[0], tb = it.theta0, pb = rf[2 * a.nu];
             const double rho = rb + rp;
             // p' = p_bar ((rho theta / rho_bar theta_bar)^gamma - 1) without cancellation
             const double dl = rp * tb + rb * tp + rp * tp;
@@ -316,7 +317,7 @@ __global__ __launch_bounds__((col_threads<N, T>())) void k_elem_stream(Batch B)
             const int32_t I = base + layer * gk;
             const double *qp = a.q + I, *rf = a.ref + I;
             const double rp = qp[0], u = qp[a.nu], v = qp[2 * a.nu], w = qp[3 * a.nu], tp = qp[4 * a.nu];
-            const double rb = rf[0], tb = rf[a.nu], pb = rf[2 * a.nu];
+            const double rb = rf[0], tb = it.theta0, pb = rf[2 * a.nu];
             const double rho = rb + rp;
             // p' = p_bar ((rho theta / rho_bar theta_bar)^gamma - 1) without cancellation
             const double dl = rp * tb + rb * tp + rp * tp;
@@ -489,6 +490,7 @@ int32_t run_chunk(const StepItem *items, int n, int stage, int phase, hipStream_
         const int64_t mblk = (int64_t)(m.d.ne[0] / SEG) * m.d.ne[1] * m.d.ne[2];
         it.mblk = (int)mblk;
         it.dt = items[k].dt;
+        it.theta0 = m.ph.T0;
         it.bm = box_metric(m);
         it.ne = (int)m.ne;
         it.eoff = (int)eo;
