@@ -178,18 +178,17 @@ def sweep(orders, shell_steps, long_steps, oracle_check=True):
         rec = {"unique_nodes": g.n_unique, "local_nodes": g.n_local,
                "fp64_ms_per_step": 1e3 * t64, "mixed_ms_per_step": 1e3 * tmx, "speedup": t64 / tmx,
                "fp64_updates_per_s": 3 * g.n_unique / t64, "mixed_updates_per_s": 3 * g.n_unique / tmx}
-        if mm["kind"] == inputs.MESH_BOX:
-            # the same steps with the metric recomputed per stage
-            g.set_metric(numa.METRIC_RECOMPUTE)
-            r64, rmx = timed(g, q0, numa.PREC_FP64, dt), timed(g, q0, numa.PREC_MIXED, dt)
-            a, b = q0.clone(), q0.clone()
-            g.step(a, dt, 1, prec=numa.PREC_FP64)
-            g.set_metric(numa.METRIC_STORED)
-            g.step(b, dt, 1, prec=numa.PREC_FP64)
-            rec["recompute"] = {"fp64_ms_per_step": 1e3 * r64, "mixed_ms_per_step": 1e3 * rmx,
-                                "speedup": r64 / rmx, "fp64_updates_per_s": 3 * g.n_unique / r64,
-                                "mixed_updates_per_s": 3 * g.n_unique / rmx,
-                                "vs_stored_state_1": group_err(a.cpu().numpy(), b.cpu().numpy())}
+        # the same steps with the metric recomputed per stage
+        g.set_metric(numa.METRIC_RECOMPUTE)
+        r64, rmx = timed(g, q0, numa.PREC_FP64, dt), timed(g, q0, numa.PREC_MIXED, dt)
+        a, b = q0.clone(), q0.clone()
+        g.step(a, dt, 1, prec=numa.PREC_FP64)
+        g.set_metric(numa.METRIC_STORED)
+        g.step(b, dt, 1, prec=numa.PREC_FP64)
+        rec["recompute"] = {"fp64_ms_per_step": 1e3 * r64, "mixed_ms_per_step": 1e3 * rmx,
+                            "speedup": r64 / rmx, "fp64_updates_per_s": 3 * g.n_unique / r64,
+                            "mixed_updates_per_s": 3 * g.n_unique / rmx,
+                            "vs_stored_state_1": group_err(a.cpu().numpy(), b.cpu().numpy())}
         h0 = q0.cpu().numpy()
         for n in (1, nlong):
             a, b = q0.clone(), q0.clone()

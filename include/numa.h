@@ -144,13 +144,17 @@ int32_t numa_geometry(numa_mesh_t m, const numa_phys *ph, void *stream);
 /* Metric terms of the element kernels (numa_rhs, numa_step, numa_step_batch).
  * NUMA_METRIC_STORED (default) reads the 9 inverse-metric entries and J w
  * computed by numa_geometry at every element-local node.  NUMA_METRIC_RECOMPUTE
- * (box meshes) recomputes the same isoparametric metric of the
- * terrain-following map in the kernel every stage from four factors per
- * element column and local (i, j) (J w without w_k, 1/z_zeta and the two
- * terrain slopes over x_xi z_zeta, y_eta z_zeta; numa_geometry computes them),
- * so the per-node metric costs no memory traffic (the paper's next step,
- * Sec. "Next Steps": recompute the metric terms in each stage).  Host only;
- * returns NUMA_EUNSUPPORTED on a shell. */
+ * recomputes the same isoparametric metric in the kernel every stage from
+ * factors that numa_geometry computes once, so the per-node metric costs no
+ * memory traffic (the paper's next step, Sec. "Next Steps": recompute the
+ * metric terms in each stage).  Box: four factors per element column and
+ * local (i, j) of the terrain-following map (J w without w_k, 1/z_zeta and the
+ * two terrain slopes over x_xi z_zeta, y_eta z_zeta).  Shell: per element
+ * column and local (i, j) the three contravariant directions of the
+ * equiangular map scaled by the triple product T, T w_i w_j and the radial
+ * direction; per radial node 1/r, 1/h_zeta, r^2 h_zeta w_k and the gravity
+ * g0 (a/r)^2 (the gather map and the gravity array are not read either).
+ * Host only. */
 int32_t numa_mesh_set_metric(numa_mesh_t m, int32_t mode);
 
 /* Copy an internal field (NUMA_FIELD_*) to a caller device buffer. */

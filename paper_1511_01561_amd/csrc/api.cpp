@@ -187,10 +187,6 @@ int32_t numa_mesh_set_metric(numa_mesh_t m, int32_t mode)
         set_error("numa_mesh_set_metric: unknown mode %d", mode);
         return NUMA_EINVAL;
     }
-    if (mode == NUMA_METRIC_RECOMPUTE && m->d.kind != NUMA_MESH_BOX) {
-        set_error("numa_mesh_set_metric: the recomputed metric is available for box meshes only");
-        return NUMA_EUNSUPPORTED;
-    }
     m->metric_mode = mode;
     return NUMA_OK;
 }

@@ -80,6 +80,11 @@ __device__ __forceinline__ RhsArgs<T> elem_args(const Batch &B, const BatchItem 
     a.nk = it.nkw;
     a.fx = it.fx;
     a.fy = it.fy;
+    a.scol = nullptr;
+    a.slay = nullptr;
+    a.shid = nullptr;
+    a.nh = it.nh;
+    a.feh = FastDiv{1, 1, 0, 0};
     a.bm = it.bm;
 #pragma unroll
     for (int c = 0; c < kEosTerms; ++c) a.eos[c] = B.eos[c];

@@ -414,6 +414,69 @@ __global__ void k_box_columns(GeoParams g, double *hcol)
     o[3 * PP] = -hy / (yb * zc);
 }
 
+// Column and layer factors of the recomputed shell metric.  The map
+// x = (a + h(zeta)) d(xi, eta) with the isoparametric contractions of k_metric
+// gives the columns A = [r d_xi, r d_eta, h_zeta d] (r = a + h, d_xi =
+// sum_m D_im d_mj, d_eta = sum_m D_jm d_im, h_zeta = sum_m D_km h_m), so with
+// T = d_xi . (d_eta x d):
+//   grad xi = (d_eta x d)/(r T), grad eta = (d x d_xi)/(r T),
+//   grad zeta = (d_xi x d_eta)/(h_zeta T), J w = T w_i w_j r^2 h_zeta w_k.
+// Per element column (horizontal element eh, local (i, j)), layout
+// [6 ne^2][13][(N+1)^2]: (d_eta x d)/T (3), (d x d_xi)/T (3), (d_xi x d_eta)/T
+// (3), T w_i w_j, d (3, for gravity).  Per radial node (layer ez, local k),
+// layout [nz (N+1)][4]: 1/r, 1/h_zeta, r^2 h_zeta w_k, g0 (a/r)^2.  The
+// horizontal unique id of each column is its bottom node's id.
+__global__ void k_shell_columns(GeoParams g, const int32_t *G, double *scol, int32_t *shid)
+{
+    const int PP = g.P * g.P;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 6 * (int64_t)g.nex * g.nex * PP) return;
+    const int64_t eh = t / PP;
+    const int c = (int)(t - eh * PP), i = c % g.P, j = c / g.P;
+    double d[3], h, dx[3] = {0, 0, 0}, dy[3] = {0, 0, 0};
+    for (int m = 0; m < g.P; ++m) {
+        double dm[3];
+        shell_local(g, eh, m + g.P * j, dm, h);
+        for (int a = 0; a < 3; ++a) dx[a] += g.D[i * g.P + m] * dm[a];
+        shell_local(g, eh, i + g.P * m, dm, h);
+        for (int a = 0; a < 3; ++a) dy[a] += g.D[j * g.P + m] * dm[a];
+    }
+    shell_local(g, eh, c, d, h);
+    const double u1[3] = {dy[1] * d[2] - dy[2] * d[1], dy[2] * d[0] - dy[0] * d[2], dy[0] * d[1] - dy[1] * d[0]};
+    const double u2[3] = {d[1] * dx[2] - d[2] * dx[1], d[2] * dx[0] - d[0] * dx[2], d[0] * dx[1] - d[1] * dx[0]};
+    const double u3[3] = {dx[1] * dy[2] - dx[2] * dy[1], dx[2] * dy[0] - dx[0] * dy[2], dx[0] * dy[1] - dx[1] * dy[0]};
+    const double T = dx[0] * u1[0] + dx[1] * u1[1] + dx[2] * u1[2];
+    double *o = scol + eh * 13 * PP + c;
+    for (int a = 0; a < 3; ++a) {
+        o[a * PP] = u1[a] / T;
+        o[(3 + a) * PP] = u2[a] / T;
+        o[(6 + a) * PP] = u3[a] / T;
+        o[(10 + a) * PP] = d[a];
+    }
+    o[9 * PP] = T * (g.w[i] * g.w[j]);
+    shid[t] = G[eh * g.np + c];  // element eh of the bottom layer, local node (i, j, 0)
+}
+
+__global__ void k_shell_layers(GeoParams g, double g0, double *slay)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)g.nez * g.P) return;
+    const int64_t ez = t / g.P;
+    const int k = (int)(t - ez * g.P);
+    double d[3], h, hz = 0.0;
+    const int64_t e0 = ez * 6 * (int64_t)g.nex * g.nex;  // any element of layer ez
+    for (int m = 0; m < g.P; ++m) {
+        shell_local(g, e0, g.P * g.P * m, d, h);
+        hz += g.D[k * g.P + m] * h;
+    }
+    shell_local(g, e0, g.P * g.P * k, d, h);
+    const double r = g.L0 + h, ar = g.L0 / r;
+    slay[4 * t] = 1.0 / r;
+    slay[4 * t + 1] = 1.0 / hz;
+    slay[4 * t + 2] = r * r * hz * g.w[k];
+    slay[4 * t + 3] = g0 * ar * ar;
+}
+
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
@@ -453,6 +516,12 @@ int32_t launch_geometry(Mesh &m, hipStream_t s)
     if (v.hcol)
         hipLaunchKernelGGL(k_box_columns, dim3(nblocks((int64_t)g.nex * g.ney * m.P * m.P, bs)), dim3(bs), 0, s, g,
                            v.hcol);
+    if (v.scol) {
+        hipLaunchKernelGGL(k_shell_columns, dim3(nblocks(6 * (int64_t)g.nex * g.nex * m.P * m.P, bs)), dim3(bs), 0, s,
+                           g, v.G, v.scol, v.shid);
+        hipLaunchKernelGGL(k_shell_layers, dim3(nblocks((int64_t)g.nez * m.P, bs)), dim3(bs), 0, s, g, m.ph.g0,
+                           v.slay);
+    }
     NUMA_HIP(hipGetLastError());
     int hbad = 0;
     NUMA_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -64,6 +64,10 @@ struct RhsArgs {
     int nx, ny, nz;      // box: elements along x, y, z
     int ni, nj, nk;      // box: lattice extents (x, y periodic; nk = -1 unless z is)
     FastDiv fx, fy;      // box: division by nx and ny
+    const double *scol, *slay;  // shell, recomputed metric: column and layer factors
+    const int32_t *shid;        // shell, recomputed metric: horizontal unique id of each column
+    int64_t nh;                 // shell: horizontal nodes
+    FastDiv feh;                // shell: division by the elements of one layer (6 ne^2)
     const double *xi, *w, *Dd;  // FP64 GLL nodes, weights, derivative matrix
     BoxMetric bm;               // box: constants of the recomputed metric
     double eos[kEosTerms];      // coefficients of the binomial series of (1 + x)^gamma - 1
@@ -71,7 +75,7 @@ struct RhsArgs {
 
 // Metric of a box element: stored per node (the general path), or recomputed
 // from the terrain-following map z' = z + h(x, y)(1 - z/H).
-enum { kMetricStored = 0, kMetricBox = 1 };
+enum { kMetricStored = 0, kMetricBox = 1, kMetricShell = 2 };
 
 // coordinates of box element e = ex + nx (ey + ny ez)
 struct BoxElem {
@@ -112,8 +116,10 @@ template <typename T>
 struct NodeIn {
     double rp, u, v, w, tp, rb, tb, pb;
     double c0, c1, c2, c3, zk;  // box, recomputed metric: column factors (c0 with w_k), xi_k
-    T mx[10];                   // stored metric: inverse metric (9) and J w
+    T mx[10];                   // stored metric and shell: inverse metric (9) and J w
+    T gv[3];                    // shell, recomputed metric: gravity
     int32_t I;                  // unique id
+    int32_t I0;                 // shell, recomputed metric: unique id of the element's first node
     int ez;                     // box: element layer
 };
 
@@ -135,7 +141,26 @@ __device__ __forceinline__ void node_gather(const RhsArgs<T> &a, int64_t e, int 
     constexpr int P = N + 1, PP = P * P, NP = PP * P;
     if (l >= NP) return;
     const int i = l % P, j = (l / P) % P, k = l / PP;
-    if constexpr (SHELL) {
+    if constexpr (SHELL && GEO == kMetricShell) {
+        // the column's horizontal id plus the radial layer; metric and gravity
+        // from the column and layer factors (k_shell_columns, k_shell_layers)
+        const uint32_t ez = fdiv((uint32_t)e, a.feh);
+        const int64_t eh = e - (int64_t)ez * a.feh.d;
+        const int c = i + P * j;
+        const int32_t *hp = a.shid + eh * PP;
+        in.I = hp[c] + (int32_t)(a.nh * ((int64_t)ez * N + k));
+        in.I0 = hp[0] + (int32_t)(a.nh * ((int64_t)ez * N));
+        const double *cp = a.scol + eh * 13 * PP + c, *lp = a.slay + 4 * ((int64_t)ez * P + k);
+        const double ir = lp[0], ihz = lp[1], jwk = lp[2], ga = lp[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            in.mx[d] = (T)(cp[d * PP] * ir);
+            in.mx[3 + d] = (T)(cp[(3 + d) * PP] * ir);
+            in.mx[6 + d] = (T)(cp[(6 + d) * PP] * ihz);
+            in.gv[d] = (T)(-ga * cp[(10 + d) * PP]);
+        }
+        in.mx[9] = (T)(cp[9 * PP] * jwk);
+    } else if constexpr (SHELL) {
         in.I = a.G[e * NP + l];
     } else {
         const BoxElem be = box_elem((uint32_t)e, a.fx, a.fy);
@@ -167,7 +192,7 @@ __device__ __forceinline__ void node_gather(const RhsArgs<T> &a, int64_t e, int 
     in.pb = rf[2 * a.nu];
 }
 
-template <int N, typename T, bool SHELL>
+template <int N, typename T, bool SHELL, int GEO = kMetricStored>
 __device__ __forceinline__ void node_stage(const RhsArgs<T> &a, int64_t e, int l, const NodeIn<T> &in,
                                            T (*s)[(N + 1) * (N + 1) * (N + 1)])
 {
@@ -187,7 +212,7 @@ __device__ __forceinline__ void node_stage(const RhsArgs<T> &a, int64_t e, int l
     s[7][l] = (T)pp;
     if constexpr (SHELL) {
         // the background theta is differentiated relative to the element's first node
-        const double t0 = a.ref[a.nu + a.G[e * NP]];
+        const double t0 = a.ref[a.nu + (GEO == kMetricShell ? in.I0 : a.G[e * NP])];
         s[8][l] = (T)(in.tb - t0);
     }
 }
@@ -229,7 +254,7 @@ __device__ __forceinline__ void box_node_metric(const BoxMetric &bm, int ez, dou
 // contractions the chain rule does not use are never formed.
 template <typename T, bool SHELL, int GEO>
 __device__ __forceinline__ void node_combine(const RhsArgs<T> &a, const T (*dd)[3], const T *mx, double u, double v,
-                                             double w, double rp, double rb, int32_t I, NodeOut<T> &o)
+                                             double w, double rp, double rb, const T *gv, NodeOut<T> &o)
 {
     const T uu = (T)u, vv = (T)v, ww = (T)w;
     T Uc[3];
@@ -258,9 +283,9 @@ __device__ __forceinline__ void node_combine(const RhsArgs<T> &a, const T (*dd)[
     const T buoy = (T)(rp * irho64);
     T gx = 0, gy = 0, gz = (T)(-a.g0);
     if constexpr (SHELL) {
-        gx = (T)a.grav[I];
-        gy = (T)a.grav[a.nu + I];
-        gz = (T)a.grav[2 * a.nu + I];
+        gx = gv[0];
+        gy = gv[1];
+        gz = gv[2];
     }
     o.R[0] = -(cart(0, 0) + cart(1, 1) + cart(2, 2));
     o.R[1] = -adv(3) - cart(7, 0) * irho + buoy * gx;
@@ -281,7 +306,7 @@ __device__ __forceinline__ void node_derive(const RhsArgs<T> &a, int l, const No
     T mx[10];
     if constexpr (GEO == kMetricBox) {
         box_node_metric<T>(a.bm, in.ez, in.zk, in.c0, in.c1, in.c2, in.c3, mx);
-    } else {
+    } else {  // stored, or the shell's recomputed metric (formed by node_gather)
 #pragma unroll
         for (int c = 0; c < 10; ++c) mx[c] = in.mx[c];
     }
@@ -302,7 +327,17 @@ __device__ __forceinline__ void node_derive(const RhsArgs<T> &a, int l, const No
         dd[f][1] = db;
         dd[f][2] = dc;
     }
-    node_combine<T, SHELL, GEO>(a, dd, mx, in.u, in.v, in.w, in.rp, in.rb, in.I, o);
+    T gv[3] = {0, 0, 0};
+    if constexpr (SHELL && GEO == kMetricShell) {
+        gv[0] = in.gv[0];
+        gv[1] = in.gv[1];
+        gv[2] = in.gv[2];
+    } else if constexpr (SHELL) {
+        gv[0] = (T)a.grav[in.I];
+        gv[1] = (T)a.grav[a.nu + in.I];
+        gv[2] = (T)a.grav[2 * a.nu + in.I];
+    }
+    node_combine<T, SHELL, GEO>(a, dd, mx, in.u, in.v, in.w, in.rp, in.rb, gv, o);
 }
 
 // Gathers the element tile, differentiates it and evaluates R at node l of
@@ -315,7 +350,7 @@ __device__ __forceinline__ bool element_rhs(const RhsArgs<T> &a, int64_t e, int 
     constexpr int P = N + 1, NP = P * P * P;
     NodeIn<T> in;
     node_gather<N, T, SHELL, GEO>(a, e, l, in);
-    node_stage<N, T, SHELL>(a, e, l, in, s);
+    node_stage<N, T, SHELL, GEO>(a, e, l, in, s);
     __syncthreads();
     if (l >= NP) return false;
     T Di[P], Dj[P], Dk[P];

@@ -279,6 +279,12 @@ uint64_t layout_workspace(Mesh &m, int32_t prec_mask, char *base)
     v.nrm = (double *)take(48ull * m.nh);
     v.xu = (double *)take(24ull * m.nu);
     if (m.d.kind == NUMA_MESH_BOX) v.hcol = (double *)take(32ull * m.d.ne[0] * m.d.ne[1] * m.P * m.P);
+    if (m.d.kind == NUMA_MESH_SHELL) {
+        const uint64_t ncol = 6ull * m.d.ne[0] * m.d.ne[0] * m.P * m.P;
+        v.scol = (double *)take(8ull * 13 * ncol);
+        v.slay = (double *)take(8ull * 4 * m.d.ne[2] * m.P);
+        v.shid = (int32_t *)take(4ull * ncol);
+    }
     v.own = (int32_t *)take(4ull * m.nu);
     v.toff = (int32_t *)take(4ull * (m.nu + 1));
     v.tidx = (int32_t *)take(4ull * m.nl);

@@ -83,6 +83,9 @@ struct DeviceView {
     double *nrm = nullptr;     // [2][3][n_horiz] bottom and top wall normals
     double *xu = nullptr;      // [3][n_unique] unique coordinates
     double *hcol = nullptr;    // box: [nx*ny][4][(N+1)^2] column factors of the recomputed metric
+    double *scol = nullptr;    // shell: [6 ne^2][13][(N+1)^2] column factors of the recomputed metric
+    double *slay = nullptr;    // shell: [nz (N+1)][4] layer factors of the recomputed metric
+    int32_t *shid = nullptr;   // shell: [6 ne^2][(N+1)^2] horizontal unique id of each element column
     int32_t *own = nullptr;    // [n_unique] unique ids in first-occurrence order of the element scan
     int32_t *toff = nullptr;   // [n_unique+1] copy offsets in that order
     int32_t *tidx = nullptr;   // [n_local] copies (e*np + l), ascending per node, in that order

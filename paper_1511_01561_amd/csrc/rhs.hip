@@ -40,7 +40,9 @@ template <int N, typename T, typename TO>
 void launch_n(Mesh &m, const RhsArgs<T> &a, TO *out, hipStream_t s)
 {
     dim3 grid((unsigned)m.ne), block(block_threads<N>());
-    if (m.d.kind == NUMA_MESH_SHELL)
+    if (m.d.kind == NUMA_MESH_SHELL && m.metric_mode == NUMA_METRIC_RECOMPUTE)
+        hipLaunchKernelGGL((k_rhs<N, T, TO, true, kMetricShell>), grid, block, 0, s, a, out);
+    else if (m.d.kind == NUMA_MESH_SHELL)
         hipLaunchKernelGGL((k_rhs<N, T, TO, true, kMetricStored>), grid, block, 0, s, a, out);
     else if (m.metric_mode == NUMA_METRIC_RECOMPUTE)
         hipLaunchKernelGGL((k_rhs<N, T, TO, false, kMetricBox>), grid, block, 0, s, a, out);
@@ -68,6 +70,11 @@ void launch_t(Mesh &m, const T *met, const T *D, const double *q, TO *out, hipSt
     a.nz = m.d.ne[2];
     a.fx = fast_div((uint32_t)m.d.ne[0]);
     a.fy = fast_div((uint32_t)m.d.ne[1]);
+    a.scol = m.dv.scol;
+    a.slay = m.dv.slay;
+    a.shid = m.dv.shid;
+    a.nh = m.nh;
+    a.feh = fast_div((uint32_t)(m.d.kind == NUMA_MESH_SHELL ? 6 * m.d.ne[0] * m.d.ne[0] : 1));
     if (m.d.kind == NUMA_MESH_BOX) a.bm = box_metric(m);
     eos_coeffs(m.gamma, a.eos);
     a.xi = m.dv.xi64;
