@@ -74,7 +74,104 @@ __global__ void k_stage_finish(PointArgs p, const int32_t *own, const int32_t *t
         qout[v * p.nu + I] = rk_update(stage, stage == 0 ? 0.0 : qn[v * p.nu + I], qs[v * p.nu + I], dt, r[v]);
 }
 
+// Finish of a fused stage on the shell: one lane per unique node in unique
+// order I = h + n_h gk, so state reads and writes run along the horizontal
+// numbering.  The copies of a node factor: its horizontal copies in the
+// bottom layer (hoff/hidx, 1 to 4, ascending) times its radial copies (local
+// k = 0 of layer gk/N and k = N of the layer below on a layer boundary, else
+// one).  The contributions are node-major [n_local][5]; the up to four
+// horizontal copies of one radial copy are loaded together.
+struct ShellFin {
+    const int32_t *hoff, *hidx;
+    FastDiv fnh;      // division by n_horiz
+    int nz;           // element layers
+    int64_t layer;    // elements of one layer times (N+1)^3
+};
+
+template <int N, typename T>
+__global__ void k_shell_finish(PointArgs p, ShellFin sf, const T *ev, int stage, double dt, const double *qn,
+                               const double *qs, double *qout)
+{
+    constexpr int P = N + 1, PP = P * P;
+    const int64_t t = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (t >= p.nu) return;
+    const int32_t I = (int32_t)t;
+    const uint32_t gk = fdiv((uint32_t)I, sf.fnh);
+    const int32_t h = I - (int32_t)(gk * sf.fnh.d);
+    const double *qsi = qs + I, *qni = qn + I;
+    const double mi = p.Minv[I];
+    double qsv[5], qnv[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        qsv[v] = qsi[v * p.nu];
+        qnv[v] = stage == 0 ? 0.0 : qni[v * p.nu];
+    }
+    // radial copies: (layer, local k)
+    int ez[2], kz[2], nzc = 1;
+    const int top = sf.nz * N;
+    if (gk == (uint32_t)top) {
+        ez[0] = sf.nz - 1;
+        kz[0] = N;
+    } else {
+        ez[0] = (int)(gk / N);
+        kz[0] = (int)(gk - (uint32_t)ez[0] * N);
+        if (kz[0] == 0 && ez[0] > 0) {
+            ez[1] = ez[0] - 1;
+            kz[1] = N;
+            nzc = 2;
+        }
+    }
+    const int32_t hb = sf.hoff[h], hn = sf.hoff[h + 1] - hb;
+    int32_t hc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) hc[q] = sf.hidx[hb + (q < hn ? q : hn - 1)];
+    double r[5] = {0, 0, 0, 0, 0};
+    for (int z = 0; z < nzc; ++z) {
+        const int64_t base = ez[z] * sf.layer + PP * kz[z];
+        T c[4][5];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const T *src = ev + (base + hc[q]) * 5;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) c[q][v] = src[v];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) r[v] += q < hn ? (double)c[q][v] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) r[v] *= mi;
+    noflux(p, I, r[1], r[2], r[3]);
+    double *qoi = qout + I;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) qoi[v * p.nu] = rk_update(stage, qnv[v], qsv[v], dt, r[v]);
+}
+
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <typename T>
+void launch_shell_finish_t(Mesh &m, const T *ev, int32_t stage, double dt, const double *qn, const double *qs,
+                           double *qout, hipStream_t s)
+{
+    ShellFin sf;
+    sf.hoff = m.dv.hoff;
+    sf.hidx = m.dv.hidx;
+    sf.fnh = fast_div((uint32_t)m.nh);
+    sf.nz = m.d.ne[2];
+    sf.layer = 6 * (int64_t)m.d.ne[0] * m.d.ne[0] * m.np;
+    const dim3 grid(nblocks(m.nu, 256)), block(256);
+    switch (m.N) {
+    case 1: hipLaunchKernelGGL((k_shell_finish<1, T>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    case 2: hipLaunchKernelGGL((k_shell_finish<2, T>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    case 3: hipLaunchKernelGGL((k_shell_finish<3, T>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    case 4: hipLaunchKernelGGL((k_shell_finish<4, T>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    case 5: hipLaunchKernelGGL((k_shell_finish<5, T>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    case 6: hipLaunchKernelGGL((k_shell_finish<6, T>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    case 7: hipLaunchKernelGGL((k_shell_finish<7, T>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    default: hipLaunchKernelGGL((k_shell_finish<8, T>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    }
+}
 
 }  // namespace
 
@@ -97,6 +194,14 @@ int32_t launch_rk_stage(Mesh &m, int32_t stage, double dt, const double *qn, con
 int32_t launch_stage_finish(Mesh &m, int32_t prec, int32_t stage, double dt, const double *qn, const double *qs,
                             double *qout, hipStream_t s)
 {
+    if (m.d.kind == NUMA_MESH_SHELL) {  // node-major contributions (launch_stage_elements)
+        if (prec == NUMA_PREC_MIXED)
+            launch_shell_finish_t<float>(m, m.dv.ev32, stage, dt, qn, qs, qout, s);
+        else
+            launch_shell_finish_t<double>(m, m.dv.ev64, stage, dt, qn, qs, qout, s);
+        NUMA_HIP(hipGetLastError());
+        return NUMA_OK;
+    }
     if (prec == NUMA_PREC_MIXED)
         hipLaunchKernelGGL(k_stage_finish<float>, dim3(nblocks(m.nu, 256)), dim3(256), 0, s, point_args(m), m.dv.own,
                            m.dv.toff, m.dv.tidx, m.dv.ev32, stage, dt, qn, qs, qout);

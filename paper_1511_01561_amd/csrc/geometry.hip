@@ -490,6 +490,10 @@ int32_t launch_geometry(Mesh &m, hipStream_t s)
         NUMA_HIP(hipMemcpyAsync(v.off, m.off.data(), 4 * (m.nu + 1), hipMemcpyHostToDevice, s));
         NUMA_HIP(hipMemcpyAsync(v.idx, m.idx.data(), 4 * m.nl, hipMemcpyHostToDevice, s));
         if (v.hlat) NUMA_HIP(hipMemcpyAsync(v.hlat, m.hlat.data(), 12 * m.nh, hipMemcpyHostToDevice, s));
+        if (v.hoff) {
+            NUMA_HIP(hipMemcpyAsync(v.hoff, m.hoff.data(), 4 * m.hoff.size(), hipMemcpyHostToDevice, s));
+            NUMA_HIP(hipMemcpyAsync(v.hidx, m.hidx.data(), 4 * m.hidx.size(), hipMemcpyHostToDevice, s));
+        }
         NUMA_HIP(hipMemcpyAsync(v.own, m.own.data(), 4 * m.nu, hipMemcpyHostToDevice, s));
         NUMA_HIP(hipMemcpyAsync(v.toff, m.toff.data(), 4 * (m.nu + 1), hipMemcpyHostToDevice, s));
         NUMA_HIP(hipMemcpyAsync(v.tidx, m.tidx.data(), 4 * m.nl, hipMemcpyHostToDevice, s));

@@ -219,6 +219,19 @@ int32_t build_mesh(Mesh &m)
                         }
                     }
     }
+    if (d.kind == NUMA_MESH_SHELL) {
+        // copies of each horizontal node in the bottom layer, ascending e*np + l
+        // (the radial copies follow from the layer): the shell finish's lists
+        const int64_t neh = 6 * (int64_t)d.ne[0] * d.ne[0], PP = (int64_t)P * P;
+        m.hoff.assign(m.nh + 1, 0);
+        for (int64_t eh = 0; eh < neh; ++eh)
+            for (int64_t c = 0; c < PP; ++c) m.hoff[m.G[eh * np + c] + 1]++;
+        for (int64_t h = 0; h < m.nh; ++h) m.hoff[h + 1] += m.hoff[h];
+        m.hidx.resize(neh * PP);
+        std::vector<int32_t> hc(m.hoff.begin(), m.hoff.end() - 1);
+        for (int64_t eh = 0; eh < neh; ++eh)
+            for (int64_t c = 0; c < PP; ++c) m.hidx[hc[m.G[eh * np + c]]++] = (int32_t)(eh * np + c);
+    }
     // inverse map by counting sort: copies of each unique node in ascending e*np + l
     m.off.assign(m.nu + 1, 0);
     for (int64_t c = 0; c < m.nl; ++c) m.off[m.G[c] + 1]++;
@@ -284,6 +297,8 @@ uint64_t layout_workspace(Mesh &m, int32_t prec_mask, char *base)
         v.scol = (double *)take(8ull * 13 * ncol);
         v.slay = (double *)take(8ull * 4 * m.d.ne[2] * m.P);
         v.shid = (int32_t *)take(4ull * ncol);
+        v.hoff = (int32_t *)take(4ull * (m.nh + 1));
+        v.hidx = (int32_t *)take(4ull * ncol);
     }
     v.own = (int32_t *)take(4ull * m.nu);
     v.toff = (int32_t *)take(4ull * (m.nu + 1));

@@ -86,6 +86,8 @@ struct DeviceView {
     double *scol = nullptr;    // shell: [6 ne^2][13][(N+1)^2] column factors of the recomputed metric
     double *slay = nullptr;    // shell: [nz (N+1)][4] layer factors of the recomputed metric
     int32_t *shid = nullptr;   // shell: [6 ne^2][(N+1)^2] horizontal unique id of each element column
+    int32_t *hoff = nullptr;   // shell: [n_horiz+1] offsets of the horizontal copy lists
+    int32_t *hidx = nullptr;   // shell: [6 ne^2 (N+1)^2] copies e*np + l (bottom layer, k = 0), ascending
     int32_t *own = nullptr;    // [n_unique] unique ids in first-occurrence order of the element scan
     int32_t *toff = nullptr;   // [n_unique+1] copy offsets in that order
     int32_t *tidx = nullptr;   // [n_local] copies (e*np + l), ascending per node, in that order
@@ -108,6 +110,7 @@ struct Mesh {
     std::vector<int32_t> G, off, idx, hlat;
     std::vector<float> D32;
     std::vector<int32_t> own, toff, tidx;
+    std::vector<int32_t> hoff, hidx;  // shell: copies of each horizontal node in the bottom layer (e*np + l)
     // optional event timing of the stage kernels (numa_profile)
     bool profiling = false;
     std::vector<hipEvent_t> ev_pool;

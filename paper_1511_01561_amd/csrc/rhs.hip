@@ -22,24 +22,54 @@ namespace {
 
 using namespace dev;
 
-template <int N, typename T, typename TO, bool SHELL, int GEO>
+// NM: node-major output [n_local][5] (the element's 5 (N+1)^3 values staged
+// through the tile and written as one contiguous run), for the shell's fused
+// stage; otherwise element-major [5][n_local].
+template <int N, typename T, typename TO, bool SHELL, int GEO, bool NM = false>
 __global__ __launch_bounds__(block_threads<N>()) void k_rhs(RhsArgs<T> a, TO *out)
 {
-    constexpr int NP = (N + 1) * (N + 1) * (N + 1), NF = SHELL ? 9 : 8;
+    constexpr int NP = (N + 1) * (N + 1) * (N + 1), NF = SHELL ? 9 : 8, BT = block_threads<N>();
     __shared__ T s[NF][NP];
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
     const int l = threadIdx.x;
     NodeOut<T> o;
-    if (!element_rhs<N, T, SHELL, GEO>(a, e, l, s, o)) return;
-    TO *p = out + e * NP + l;
+    const bool act = element_rhs<N, T, SHELL, GEO>(a, e, l, s, o);
+    if constexpr (NM) {
+        static_assert(sizeof(TO) == sizeof(T), "node-major output is staged in the tile");
+        __syncthreads();  // every lane has finished reading the tile
+        TO *st = (TO *)&s[0][0];
+        if (act) {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) p[v * a.nl] = (TO)(o.Jw * o.R[v]);
+            for (int v = 0; v < 5; ++v) st[l * 5 + v] = (TO)(o.Jw * o.R[v]);
+        }
+        __syncthreads();
+        TO *dst = out + e * (NP * 5);
+#pragma unroll
+        for (int r = 0; r < (NP * 5 + BT - 1) / BT; ++r) {
+            const int t = l + r * BT;
+            if (t < NP * 5) dst[t] = st[t];
+        }
+    } else {
+        if (!act) return;
+        TO *p = out + e * NP + l;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) p[v * a.nl] = (TO)(o.Jw * o.R[v]);
+    }
 }
 
 template <int N, typename T, typename TO>
-void launch_n(Mesh &m, const RhsArgs<T> &a, TO *out, hipStream_t s)
+void launch_n(Mesh &m, const RhsArgs<T> &a, TO *out, bool node_major, hipStream_t s)
 {
     dim3 grid((unsigned)m.ne), block(block_threads<N>());
+    if constexpr (sizeof(TO) == sizeof(T)) {
+        if (node_major && m.d.kind == NUMA_MESH_SHELL) {
+            if (m.metric_mode == NUMA_METRIC_RECOMPUTE)
+                hipLaunchKernelGGL((k_rhs<N, T, TO, true, kMetricShell, true>), grid, block, 0, s, a, out);
+            else
+                hipLaunchKernelGGL((k_rhs<N, T, TO, true, kMetricStored, true>), grid, block, 0, s, a, out);
+            return;
+        }
+    }
     if (m.d.kind == NUMA_MESH_SHELL && m.metric_mode == NUMA_METRIC_RECOMPUTE)
         hipLaunchKernelGGL((k_rhs<N, T, TO, true, kMetricShell>), grid, block, 0, s, a, out);
     else if (m.d.kind == NUMA_MESH_SHELL)
@@ -51,7 +81,7 @@ void launch_n(Mesh &m, const RhsArgs<T> &a, TO *out, hipStream_t s)
 }
 
 template <typename T, typename TO>
-void launch_t(Mesh &m, const T *met, const T *D, const double *q, TO *out, hipStream_t s)
+void launch_t(Mesh &m, const T *met, const T *D, const double *q, TO *out, bool node_major, hipStream_t s)
 {
     RhsArgs<T> a;
     a.G = m.dv.G;
@@ -84,14 +114,14 @@ void launch_t(Mesh &m, const T *met, const T *D, const double *q, TO *out, hipSt
     a.nj = (int)m.nj;
     a.nk = m.d.periodic[2] ? (int)m.nk : -1;  // only a periodic z wraps
     switch (m.N) {
-    case 1: launch_n<1, T, TO>(m, a, out, s); break;
-    case 2: launch_n<2, T, TO>(m, a, out, s); break;
-    case 3: launch_n<3, T, TO>(m, a, out, s); break;
-    case 4: launch_n<4, T, TO>(m, a, out, s); break;
-    case 5: launch_n<5, T, TO>(m, a, out, s); break;
-    case 6: launch_n<6, T, TO>(m, a, out, s); break;
-    case 7: launch_n<7, T, TO>(m, a, out, s); break;
-    default: launch_n<8, T, TO>(m, a, out, s); break;
+    case 1: launch_n<1, T, TO>(m, a, out, node_major, s); break;
+    case 2: launch_n<2, T, TO>(m, a, out, node_major, s); break;
+    case 3: launch_n<3, T, TO>(m, a, out, node_major, s); break;
+    case 4: launch_n<4, T, TO>(m, a, out, node_major, s); break;
+    case 5: launch_n<5, T, TO>(m, a, out, node_major, s); break;
+    case 6: launch_n<6, T, TO>(m, a, out, node_major, s); break;
+    case 7: launch_n<7, T, TO>(m, a, out, node_major, s); break;
+    default: launch_n<8, T, TO>(m, a, out, node_major, s); break;
     }
 }
 
@@ -100,9 +130,9 @@ void launch_t(Mesh &m, const T *met, const T *D, const double *q, TO *out, hipSt
 int32_t launch_rhs(Mesh &m, int32_t prec, const double *q, double *evec, hipStream_t s)
 {
     if (prec == NUMA_PREC_MIXED)
-        launch_t<float, double>(m, m.dv.met32, m.dv.D32, q, evec, s);
+        launch_t<float, double>(m, m.dv.met32, m.dv.D32, q, evec, false, s);
     else
-        launch_t<double, double>(m, m.dv.met, m.dv.D64, q, evec, s);
+        launch_t<double, double>(m, m.dv.met, m.dv.D64, q, evec, false, s);
     NUMA_HIP(hipGetLastError());
     return NUMA_OK;
 }
@@ -112,10 +142,12 @@ int32_t launch_rhs(Mesh &m, int32_t prec, const double *q, double *evec, hipStre
 int32_t launch_stage_elements(Mesh &m, int32_t prec, int32_t, double, const double *, const double *qs, double *,
                               hipStream_t s)
 {
+    // the shell's finish reads node-major contributions, the generic one element-major
+    const bool nm = m.d.kind == NUMA_MESH_SHELL;
     if (prec == NUMA_PREC_MIXED)
-        launch_t<float, float>(m, m.dv.met32, m.dv.D32, qs, m.dv.ev32, s);
+        launch_t<float, float>(m, m.dv.met32, m.dv.D32, qs, m.dv.ev32, nm, s);
     else
-        launch_t<double, double>(m, m.dv.met, m.dv.D64, qs, m.dv.ev64, s);
+        launch_t<double, double>(m, m.dv.met, m.dv.D64, qs, m.dv.ev64, nm, s);
     NUMA_HIP(hipGetLastError());
     return NUMA_OK;
 }

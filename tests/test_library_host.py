@@ -127,3 +127,44 @@ def test_mesh_beyond_32bit_indices_rejected(L):
     rc, h = _create(dict(kind=0, N=1, ne=(1300, 1300, 1300), periodic=(1, 1, 0), extent=(1, 1, 1), h0=0.0))
     assert rc == -4 and not h.value
     assert b"32-bit" in L.numa_last_error()
+
+
+@pytest.mark.parametrize("N,ne,nz", [(1, 2, 2), (3, 2, 3), (4, 3, 2)])
+def test_shell_copies_factor_horizontal_times_radial(L, N, ne, nz):
+    """The shell's fused finish builds the copies of unique node h + n_h gk as
+    (the copies of horizontal node h in the bottom layer) x (the radial
+    copies: local k = 0 of layer gk/N and k = N of the layer below on a layer
+    boundary, else the one layer).  Check that against the gather map."""
+    rc, h = _create(dict(kind=1, N=N, ne=(ne, ne, nz), periodic=(0, 0, 0), extent=(6.371e6, 0.0, 3e4)))
+    assert rc == 0
+    try:
+        vals = [ct.c_int64() for _ in range(5)]
+        assert L.numa_mesh_info(h, *[ct.byref(v) for v in vals]) == 0
+        n_elem, n_local, n_unique, nh, nk = (v.value for v in vals)
+        G = np.zeros(n_local, dtype=np.int32)
+        assert L.numa_mesh_gather_map(h, G.ctypes.data) == 0
+    finally:
+        L.numa_mesh_destroy(h)
+    P = N + 1
+    np_, pp = P ** 3, P * P
+    neh = 6 * ne * ne
+    assert nh == 6 * (ne * N) ** 2 + 2 and nk == nz * N + 1
+    # horizontal copy lists from the bottom layer, ascending e*np + l
+    hcopies = [[] for _ in range(nh)]
+    for eh in range(neh):
+        for c in range(pp):
+            hcopies[G[eh * np_ + c]].append(eh * np_ + c)
+    expected = [[] for _ in range(n_unique)]
+    for c, I in enumerate(G):
+        expected[I].append(c)
+    top = nz * N
+    for I in range(n_unique):
+        hh, gk = I % nh, I // nh
+        if gk == top:
+            rad = [(nz - 1, N)]
+        else:
+            ez, kz = gk // N, gk % N
+            rad = [(ez, kz)] + ([(ez - 1, N)] if kz == 0 and ez > 0 else [])
+        got = sorted(ez * neh * np_ + pp * kz + hc for ez, kz in rad for hc in hcopies[hh])
+        assert got == sorted(expected[I]), I
+        assert 1 <= len(hcopies[hh]) <= 4
