@@ -168,3 +168,17 @@ def test_shell_copies_factor_horizontal_times_radial(L, N, ne, nz):
         got = sorted(ez * neh * np_ + pp * kz + hc for ez, kz in rad for hc in hcopies[hh])
         assert got == sorted(expected[I]), I
         assert 1 <= len(hcopies[hh]) <= 4
+
+
+def test_missing_library_fails_loudly():
+    """Without the built HIP library the binding raises; nothing falls back
+    to a CPU path."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1511_01561_amd import numa\n"
+            "numa.LIB_PATH = '/nonexistent/libnuma.so'\n"
+            "try:\n    numa.lib()\nexcept numa.NumaError as e:\n    print('raised', e)\n"
+            % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert "raised" in out.stdout and "no CPU fallback" in out.stdout, out.stdout + out.stderr
