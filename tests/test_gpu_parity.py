@@ -369,3 +369,31 @@ def test_step_parity_orders_and_meshes(torch_cuda, oracle_mod, N, ne, perz):
     e = group_err(p.host(qm) - q0, qo - q0)
     print("mixed 2-step increment", {k: "%.1e" % v for k, v in e.items()})
     assert max(e.values()) < 1e-4
+
+
+# ---------------------------------------------------------------- edge cases
+@pytest.mark.parametrize("which", ["box4", "nx6", "shell"])
+def test_zero_steps_leave_the_state_untouched(torch_cuda, oracle_mod, which):
+    """nsteps = 0 through the batched box path, the generic path (nx = 6 at
+    N = 4) and the shell path: the state is bitwise unchanged."""
+    from paper_1511_01561_amd import numa
+    torch = torch_cuda
+    if which == "box4":
+        wl = inputs.small_box()
+    elif which == "nx6":
+        wl = inputs.box_workload(6, 4, 2, 4, 1.2e4, 9e3, 6e3, terrain=300.0, bubble_centre=(6e3, 4.5e3, 2.5e3),
+                                 bubble_radius=2.5e3)
+    else:
+        wl = small_shell(3)
+    g = numa.Mesh(wl["mesh"], wl["phys"], prec_mask=3)
+    noise = inputs.device_noise(g.n_unique, 3) if wl["ic"]["noise_amp"] else None
+    q = g.init_state(wl["ic"], noise)
+    q0 = q.clone()
+    for prec in (0, 1):
+        g.step(q, 0.05, 0, prec=prec)
+    torch.cuda.synchronize()
+    assert torch.equal(q, q0)
+    if wl["mesh"]["kind"] == 0 and wl["mesh"]["ne"][0] % 4 == 0:
+        numa.step_batch([(g, q, numa.alloc_scratch(g, 0), 0.05)], 0, 0)
+        torch.cuda.synchronize()
+        assert torch.equal(q, q0)

@@ -182,3 +182,11 @@ def test_missing_library_fails_loudly():
             % os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert "raised" in out.stdout and "no CPU fallback" in out.stdout, out.stdout + out.stderr
+
+
+def test_empty_batch_rejected(L):
+    """A batch without items is an argument error, refused before any device work."""
+    assert L.numa_step_batch(None, 0, 0, 1, None) == -1
+    assert b"no items" in L.numa_last_error()
+    h = ct.c_void_p()
+    assert L.numa_batch_capture(None, 0, 0, 1, None, ct.byref(h)) == -1
