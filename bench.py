@@ -169,7 +169,7 @@ def sweep(orders, shell_steps, long_steps, oracle_check=True):
         torch.cuda.synchronize()
         return (time.perf_counter() - t) / steps
 
-    def run(wl, dt, nlong, name):
+    def run(wl, dt, nlong, name, long_oracle=False):
         mm = wl["mesh"]
         g = numa.Mesh(mm, wl["phys"], prec_mask=3)
         nz = torch.as_tensor(inputs.noise(g.n_unique, 0), device="cuda:0") if wl["ic"]["noise_amp"] else None
@@ -197,6 +197,16 @@ def sweep(orders, shell_steps, long_steps, oracle_check=True):
             A, B = a.cpu().numpy(), b.cpu().numpy()
             rec["mixed_vs_fp64_state_%d" % n] = group_err(B, A)
             rec["mixed_vs_fp64_increment_%d" % n] = group_err(B - h0, A - h0)
+            if n == nlong and oracle_check and long_oracle:
+                # the whole run on the oracle (the 64x64x16 N = 4 box and the shell only)
+                import oracle
+                om = oracle.OracleMesh(mm["kind"], mm["N"], mm["ne"], mm["periodic"], mm["extent"], mm["h0"],
+                                       wl["phys"])
+                t0 = time.perf_counter()
+                qo = om.step(h0, dt, n)
+                _log("%s: oracle %d steps %.1f s" % (name, n, time.perf_counter() - t0))
+                rec["fp64_vs_oracle_state_%d" % n] = group_err(A, qo)
+                del om
             if n == 1 and oracle_check:
                 import oracle
                 om = oracle.OracleMesh(mm["kind"], mm["N"], mm["ne"], mm["periodic"], mm["extent"], mm["h0"],
@@ -217,9 +227,10 @@ def sweep(orders, shell_steps, long_steps, oracle_check=True):
         return rec
 
     for N in orders:
-        res["box"]["N%d" % N] = run(inputs.gpu_box(N), 0.05, long_steps, "box64x64x16 N=%d" % N)
+        res["box"]["N%d" % N] = run(inputs.gpu_box(N), 0.05, long_steps, "box64x64x16 N=%d" % N, long_oracle=N == 4)
     if shell_steps:
-        res["shell"] = run(inputs.shell_workload(32, 10, 4, seed=0), 0.5, shell_steps, "shell6x32x32x10 N=4")
+        res["shell"] = run(inputs.shell_workload(32, 10, 4, seed=0), 0.5, shell_steps, "shell6x32x32x10 N=4",
+                           long_oracle=True)
     return res
 
 
