@@ -41,14 +41,17 @@ def source_hash(paths):
 
 def element_bytes(nu, nl, prec, metric):
     """Algorithmic HBM bytes of one launch of the element kernel of a fused
-    stage on the box: the unique state (5 x 8 B) and reference (3 x 8 B) read
-    once; per element-local node the contribution written once (5 x 8 B, or
-    5 x 4 B mixed) and, with the stored metric, the 9 inverse-metric entries
-    and J w (10 x 8 B, or 10 x 4 B mixed).  Unique ids follow from the lattice
-    and a recomputed metric costs no traffic."""
+    stage on the box: the unique state (5 x 8 B) and reference read once
+    (rho_bar, theta_bar, p_bar: 3 x 8 B; the recomputed-metric kernels take the
+    isentropic theta_bar = theta0 as a constant: 2 x 8 B); per element-local
+    node the contribution written once (5 x 8 B, or 5 x 4 B mixed) and, with
+    the stored metric, the 9 inverse-metric entries and J w (10 x 8 B, or
+    10 x 4 B mixed).  Unique ids follow from the lattice and a recomputed
+    metric costs no traffic."""
     contrib = 20 if prec == "mixed" else 40
     met = 0 if metric == "recompute" else (40 if prec == "mixed" else 80)
-    return nu * (40 + 24) + nl * (met + contrib)
+    ref = 16 if metric == "recompute" else 24
+    return nu * (40 + ref) + nl * (met + contrib)
 
 
 def finish_bytes(nu, nl, n_wall, prec):
