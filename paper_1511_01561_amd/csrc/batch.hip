@@ -110,6 +110,30 @@ __device__ __forceinline__ void store_contributions(const BatchItem &it, int e, 
     }
 }
 
+// Copy n values staged in LDS (st, 16-byte aligned) to out with 16-byte
+// stores: the leading values until out is 16-byte aligned one by one, then
+// 16-byte vectors (two FP64 or four FP32 values per lane), then the tail.
+template <typename T>
+__device__ __forceinline__ void store_run(T *out, const T *st, int n, int t, int nthreads)
+{
+    using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+    constexpr int W = 16 / sizeof(T);
+    int lead = (int)(((16 - ((uintptr_t)out & 15)) & 15) / sizeof(T));
+    if (lead > n) lead = n;
+    if (t < lead) out[t] = st[t];
+    const int nv = (n - lead) / W;
+    const T *sv = st + lead;
+    V *ov = reinterpret_cast<V *>(out + lead);
+    for (int u = t; u < nv; u += nthreads) {
+        V val;
+        T *vp = reinterpret_cast<T *>(&val);
+#pragma unroll
+        for (int c = 0; c < W; ++c) vp[c] = sv[u * W + c];
+        ov[u] = val;
+    }
+    for (int u = lead + nv * W + t; u < n; u += nthreads) out[u] = st[u];
+}
+
 // One workgroup per element (the launch-wide element index, XCD-remapped).
 template <int N, typename T, int GEO>
 __global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
@@ -280,7 +304,7 @@ __global__ __launch_bounds__((col_threads<N, T>())) void k_elem_col(Batch B)
     // the workgroup's elements are consecutive: one contiguous run
     const int ne = it.ne - e0 < EB ? it.ne - e0 : EB;
     T *out = (T *)it.ev + (int64_t)e0 * (NP * 5);
-    for (int u = t; u < ne * NP * 5; u += BT) out[u] = st[u];
+    store_run<T>(out, st, ne * NP * 5, t, BT);
 }
 
 // Streaming variant of the column kernel: after the tile is built the lane
@@ -408,7 +432,7 @@ __global__ __launch_bounds__((col_threads<N, T>())) void k_elem_stream(Batch B)
     // the workgroup's elements are consecutive: one contiguous run
     const int ne = it.ne - e0 < EB ? it.ne - e0 : EB;
     T *out = (T *)it.ev + (int64_t)e0 * (NP * 5);
-    for (int u = t; u < ne * NP * 5; u += BT) out[u] = st[u];
+    store_run<T>(out, st, ne * NP * 5, t, BT);
 }
 
 template <int N, int SEG, typename T>
