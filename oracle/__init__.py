@@ -69,6 +69,9 @@ def lib():
         L.or_dss.argtypes = [P, ct.c_int, P, ct.c_int, P]
         L.or_rk_stage.argtypes = [P, ct.c_int, ct.c_double, P, P, P, P]
         L.or_step.argtypes = [P, ct.c_double, ct.c_int, P]
+        L.or_filter_sigma.argtypes = [ct.c_int, ct.c_double, ct.c_int, P]
+        L.or_filter_matrix.argtypes = [ct.c_int, ct.c_double, ct.c_int, P]
+        L.or_filter.argtypes = [P, ct.c_double, ct.c_int, P]
         _lib = L
     return _lib
 
@@ -206,11 +209,35 @@ class OracleMesh:
         lib().or_rk_stage(self._h, stage, dt, _p(qn), _p(qs), _p(r), _p(out))
         return out
 
+    def filter(self, q: np.ndarray, order: float, cutoff: int) -> np.ndarray:
+        """Filtered state: element filter, J w weighting, DSS / M, no-flux."""
+        q = np.array(q, dtype=np.float64, copy=True).reshape(5, self.n_unique)
+        rc = lib().or_filter(self._h, float(order), int(cutoff), _p(q))
+        if rc != 0:
+            raise ValueError("oracle filter (%d)" % rc)
+        return q
+
     def step(self, q: np.ndarray, dt: float, nsteps: int) -> np.ndarray:
         q = np.array(q, dtype=np.float64, copy=True).reshape(5, self.n_unique)
         if lib().or_step(self._h, dt, nsteps, _p(q)) != 0:
             raise MemoryError("oracle step")
         return q
+
+
+def filter_sigma(N: int, order: float, cutoff: int) -> np.ndarray:
+    """Boyd-Vandeven modal factors sigma_0..sigma_N (erfc-log form)."""
+    s = np.zeros(N + 1)
+    if lib().or_filter_sigma(N, float(order), int(cutoff), _p(s)) != 0:
+        raise ValueError("filter parameters")
+    return s
+
+
+def filter_matrix(N: int, order: float, cutoff: int) -> np.ndarray:
+    """1D nodal filter matrix V diag(sigma) V^-1, F[i, m]."""
+    F = np.zeros((N + 1, N + 1))
+    if lib().or_filter_matrix(N, float(order), int(cutoff), _p(F)) != 0:
+        raise ValueError("filter parameters")
+    return F
 
 
 def num_threads() -> int:

@@ -850,6 +850,133 @@ int or_step(const or_ctx *C, double dt, int nsteps, double *q)
     return 0;
 }
 
+/*
+ * Boyd-Vandeven filter (Sec. "Filter"; Code example 1: "compute filter",
+ * then "DSS and multiply with inverse mass matrix").  The paper names the
+ * filter -- a spectral transformation of the element's nodal values that
+ * damps the highest modes, i.e. one filter-matrix product per element -- but
+ * gives neither its order nor its cutoff.  Reading: the erfc-log form of the
+ * Boyd-Vandeven filter with order p and cutoff s as inputs; the modal factor of
+ * Legendre mode k is
+ *   sigma_k = 1                                   for k <= s,
+ *   sigma_k = erfc(2 sqrt(p) chi(t) (t - 1/2)) / 2  with t = (k - s)/(N - s),
+ *   chi(t)  = sqrt(-log(1 - 4 (t - 1/2)^2) / (4 (t - 1/2)^2)),  chi(1/2) = 1,
+ * so sigma_s = 1 (t = 0, the limit), sigma = 1/2 at t = 1/2 and sigma_N = 0
+ * (t = 1).  s >= N leaves the element unchanged.
+ */
+int or_filter_sigma(int N, double order, int cutoff, double *sigma)
+{
+    if (N < 1 || N >= OR_MAXP || !(order > 0.0) || cutoff < 0) return -1;
+    for (int k = 0; k <= N; k++) {
+        if (k < cutoff || cutoff >= N) {
+            sigma[k] = 1.0;
+            continue;
+        }
+        double t = (double)(k - cutoff) / (double)(N - cutoff);
+        double d = t - 0.5;
+        double chi;
+        if (t <= 0.0 || t >= 1.0) {   /* the limits of the erfc-log form */
+            sigma[k] = t <= 0.0 ? 1.0 : 0.0;
+            continue;
+        }
+        if (d == 0.0) chi = 1.0;
+        else chi = sqrt(-log(1.0 - 4.0 * d * d) / (4.0 * d * d));
+        sigma[k] = 0.5 * erfc(2.0 * sqrt(order) * chi * d);
+    }
+    return 0;
+}
+
+/* The 1D filter matrix F = V diag(sigma) V^-1 with the Legendre Vandermonde
+ * matrix V_ik = P_k(xi_i) at the GLL nodes, V^-1 by Gauss-Jordan elimination
+ * with partial pivoting.  F[i*P + m], P = N + 1. */
+int or_filter_matrix(int N, double order, int cutoff, double *F)
+{
+    int P = N + 1;
+    double xi[OR_MAXP], w[OR_MAXP], D[OR_MAXP * OR_MAXP], sigma[OR_MAXP];
+    double V[OR_MAXP][OR_MAXP], A[OR_MAXP][2 * OR_MAXP];
+    if (or_gll(N, xi, w, D) || or_filter_sigma(N, order, cutoff, sigma)) return -1;
+    for (int i = 0; i < P; i++)
+        for (int k = 0; k < P; k++) {
+            double Pk, dPk, Pk1;
+            legendre(k, xi[i], &Pk, &dPk, &Pk1);
+            V[i][k] = Pk;
+        }
+    /* [V | I] -> [I | V^-1] */
+    for (int i = 0; i < P; i++)
+        for (int k = 0; k < 2 * P; k++) A[i][k] = k < P ? V[i][k] : (k - P == i ? 1.0 : 0.0);
+    for (int c = 0; c < P; c++) {
+        int piv = c;
+        for (int r = c + 1; r < P; r++)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        if (A[piv][c] == 0.0) return -1;
+        if (piv != c)
+            for (int k = 0; k < 2 * P; k++) {
+                double t = A[c][k];
+                A[c][k] = A[piv][k];
+                A[piv][k] = t;
+            }
+        double inv = 1.0 / A[c][c];
+        for (int k = 0; k < 2 * P; k++) A[c][k] *= inv;
+        for (int r = 0; r < P; r++) {
+            if (r == c) continue;
+            double f = A[r][c];
+            for (int k = 0; k < 2 * P; k++) A[r][k] -= f * A[c][k];
+        }
+    }
+    for (int i = 0; i < P; i++)
+        for (int m = 0; m < P; m++) {
+            double s = 0.0;
+            for (int k = 0; k < P; k++) s += V[i][k] * sigma[k] * A[k][P + m];
+            F[i * P + m] = s;
+        }
+    return 0;
+}
+
+/*
+ * The filter step on the state q ([5][nu], in place): every element's nodal
+ * values of each variable are multiplied by the element filter matrix, the
+ * Kronecker product F (x) F (x) F of size (N+1)^3 (local node l = i + P(j + P k),
+ * so its entry (l, l') is F_ii' F_jj' F_kk'), weighted by J w, summed at the
+ * unique nodes and divided by M (or_dss); the velocity is projected at the
+ * no-flux walls as after every DSS (reading).  Reading: the filter acts on the
+ * perturbation state (rho', u, v, w, theta'), which leaves the hydrostatic
+ * reference state untouched.
+ */
+int or_filter(const or_ctx *C, double order, int cutoff, double *q)
+{
+    int P = C->P, np = C->np;
+    double F[OR_MAXP * OR_MAXP];
+    if (or_filter_matrix(C->N, order, cutoff, F)) return -1;
+    int64_t nl = C->nl, nu = C->nu;
+    double *cbuf = (double *)malloc(sizeof(double) * 5 * nl);
+    double *K = (double *)malloc(sizeof(double) * np * np);
+    if (!cbuf || !K) { free(cbuf); free(K); return -2; }
+    for (int l = 0; l < np; l++) {
+        int i = l % P, j = (l / P) % P, k = l / (P * P);
+        for (int l2 = 0; l2 < np; l2++) {
+            int i2 = l2 % P, j2 = (l2 / P) % P, k2 = l2 / (P * P);
+            K[l * np + l2] = F[i * P + i2] * F[j * P + j2] * F[k * P + k2];
+        }
+    }
+#pragma omp parallel for
+    for (int64_t e = 0; e < C->ne; e++) {
+        double a[OR_MAXP * OR_MAXP * OR_MAXP];
+        for (int v = 0; v < 5; v++) {
+            for (int l = 0; l < np; l++) a[l] = q[v * nu + C->G[e * np + l]];
+            for (int l = 0; l < np; l++) {
+                double s = 0.0;
+                for (int l2 = 0; l2 < np; l2++) s += K[l * np + l2] * a[l2];
+                int64_t c = e * np + l;
+                cbuf[v * nl + c] = C->met[9 * nl + c] * s;
+            }
+        }
+    }
+    or_dss(C, 5, cbuf, 3, q);
+    free(cbuf);
+    free(K);
+    return 0;
+}
+
 int or_num_threads(void)
 {
 #ifdef _OPENMP

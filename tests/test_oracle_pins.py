@@ -540,3 +540,152 @@ def test_initial_state_balanced_pressure(small):
     r = np.sqrt((x - 5e3) ** 2 + (y - 5e3) ** 2 + (z - 2e3) ** 2)
     bell = np.where(r < 2e3, 0.25 * (1 + np.cos(np.pi * r / 2e3)), 0.0)
     np.testing.assert_allclose(q[4], bell, rtol=1e-14, atol=1e-16)
+
+
+# --------------------------------------------------------------------------
+# Boyd-Vandeven filter (Sec. "Filter"; Code example 1: filter, then DSS and
+# inverse mass).  Order and cutoff are inputs (the paper gives neither).
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("N,order,cutoff", [(4, 12.0, 1), (6, 8.0, 2), (8, 16.0, 4), (8, 4.0, 0), (7, 36.0, 3)])
+def test_filter_sigma_shape(oracle_mod, N, order, cutoff):
+    s = oracle_mod.filter_sigma(N, order, cutoff)
+    np.testing.assert_array_equal(s[:cutoff + 1], 1.0)      # modes up to the cutoff untouched
+    assert s[N] == 0.0                                       # top mode removed
+    assert np.all(np.diff(s) <= 0) and np.all(s >= 0)        # monotone damping
+    # the erfc-log form is odd about t = 1/2: sigma(t) + sigma(1 - t) = 1
+    k = np.arange(cutoff, N + 1)
+    np.testing.assert_allclose(s[k] + s[k[::-1]], 1.0, rtol=0, atol=1e-15)
+    if (N - cutoff) % 2 == 0:
+        assert abs(s[(N + cutoff) // 2] - 0.5) < 1e-16
+
+
+def test_filter_sigma_sharpens_with_order(oracle_mod):
+    # larger order -> closer to the sharp cut at t = 1/2
+    lo = oracle_mod.filter_sigma(8, 2.0, 0)
+    hi = oracle_mod.filter_sigma(8, 200.0, 0)
+    assert np.all(hi[:4] >= lo[:4]) and np.all(hi[5:] <= lo[5:])
+    assert hi[3] > 0.999 and hi[5] < 1e-3
+    assert lo[3] < 0.9 and lo[5] > 0.1
+
+
+@pytest.mark.parametrize("N,order,cutoff", [(2, 12.0, 0), (4, 12.0, 1), (8, 16.0, 4), (5, 6.0, 2)])
+def test_filter_matrix_is_modal_damping(oracle_mod, N, order, cutoff):
+    """F applied to P_k at the GLL nodes gives sigma_k P_k (numpy's Legendre series)."""
+    xi, _, _ = oracle_mod.gll(N)
+    F = oracle_mod.filter_matrix(N, order, cutoff)
+    s = oracle_mod.filter_sigma(N, order, cutoff)
+    for k in range(N + 1):
+        c = np.zeros(k + 1)
+        c[k] = 1.0
+        pk = npleg.legval(xi, c)
+        np.testing.assert_allclose(F @ pk, s[k] * pk, rtol=0, atol=2e-14)
+
+
+def test_filter_matrix_low_order_closed_forms(oracle_mod):
+    # N = 1, cutoff 0: the constant mode only, i.e. the two-node mean
+    np.testing.assert_allclose(oracle_mod.filter_matrix(1, 12.0, 0), np.full((2, 2), 0.5), rtol=0, atol=1e-16)
+    # N = 2, cutoff 0: sigma = (1, 1/2, 0) on nodes (-1, 0, 1), P_2 = (3x^2 - 1)/2;
+    # a = c0 + c1 x + c2 P2(x): c0 = (a0 + 4 a1 + a2)/6, c1 = (a2 - a0)/2, c2 = (a0 - 2 a1 + a2)/3
+    C = np.array([[1 / 6, 4 / 6, 1 / 6], [-0.5, 0.0, 0.5], [1 / 3, -2 / 3, 1 / 3]])
+    V = np.array([[1.0, -1.0, 1.0], [1.0, 0.0, -0.5], [1.0, 1.0, 1.0]])
+    F2 = V @ np.diag([1.0, 0.5, 0.0]) @ C
+    np.testing.assert_allclose(oracle_mod.filter_matrix(2, 12.0, 0), F2, rtol=0, atol=1e-15)
+    # cutoff at N: the identity
+    np.testing.assert_allclose(oracle_mod.filter_matrix(6, 12.0, 6), np.eye(7), rtol=0, atol=1e-14)
+
+
+def _filter_box(oracle_mod, N=4, nz=2, h0=0.0):
+    return _box(oracle_mod, 2, 2, nz, N, h0=h0, ext=(2e3, 3e3, 1e3))
+
+
+def test_filter_single_vertical_mode(oracle_mod):
+    """A state that is P_k(zeta) in every element of a one-layer box comes back
+    as sigma_k P_k: the whole path (element matrix, J w, DSS / M) is exact."""
+    N, order, cutoff = 6, 10.0, 2
+    m = _filter_box(oracle_mod, N, nz=1)
+    z = m.get("xu")[2]
+    zeta = 2.0 * z / 1e3 - 1.0
+    s = oracle_mod.filter_sigma(N, order, cutoff)
+    for k in range(N + 1):
+        c = np.zeros(k + 1)
+        c[k] = 1.0
+        pk = npleg.legval(zeta, c)
+        q = np.zeros((5, m.n_unique))
+        q[0] = pk
+        q[4] = 2.0 * pk
+        out = m.filter(q, order, cutoff)
+        np.testing.assert_allclose(out[0], s[k] * pk, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(out[4], 2.0 * s[k] * pk, rtol=0, atol=2e-13)
+        assert np.all(out[1:4] == 0.0)
+
+
+def test_filter_horizontal_brute_force(oracle_mod):
+    """x- and y-dependent state, expected value by per-element Legendre fits
+    (numpy) and the plain average of the two copies on element faces."""
+    N, order, cutoff = 4, 12.0, 1
+    Lx, Ly = 2e3, 3e3
+    m = _filter_box(oracle_mod, N, nz=1)
+    x, y, _ = m.get("xu")
+    f = (x - Lx / 2) ** 4 / Lx ** 4 + 0.5 * (y - Ly / 2) ** 3 * (y - Ly / 2) / Ly ** 4   # periodic, continuous
+    q = np.zeros((5, m.n_unique))
+    q[0] = f
+    out = m.filter(q, order, cutoff)
+    s = oracle_mod.filter_sigma(N, order, cutoff)
+    xi, _, _ = oracle_mod.gll(N)
+
+    def damp1d(g, lo, L):        # filtered 1D profile of one element at its GLL nodes
+        xs = lo + (xi + 1) * L / 4
+        coef = npleg.legfit(xi, g(xs), N)
+        return xs, npleg.legval(xi, coef * s)
+
+    gx = lambda t: (t - Lx / 2) ** 4 / Lx ** 4
+    gy = lambda t: 0.5 * (t - Ly / 2) ** 4 / Ly ** 4
+    # f is a sum of an x- and a y-profile; sigma_0 = 1 keeps constants, so each
+    # filtered element is the sum of the filtered profiles; on faces the two
+    # element copies have equal J w and average.
+    def nodal(g, L):
+        vals = {}
+        for e in range(2):
+            xs, v = damp1d(g, e * L / 2, L)
+            for a, b in zip(xs, v):
+                key = round((a % L) / L * 4 * N) % (4 * N)
+                vals.setdefault(key, []).append(b)
+        return {k: np.mean(v) for k, v in vals.items()}
+    ex, ey = nodal(gx, Lx), nodal(gy, Ly)
+    kx = np.round((x % Lx) / Lx * 4 * N).astype(int) % (4 * N)
+    ky = np.round((y % Ly) / Ly * 4 * N).astype(int) % (4 * N)
+    want = np.array([ex[a] for a in kx]) + np.array([ey[b] for b in ky])
+    np.testing.assert_allclose(out[0], want, rtol=0, atol=1e-14)
+    assert np.abs(out[0] - f).max() > 1e-4          # the top modes were there and were damped
+
+
+def test_filter_preserves_low_degree_and_is_identity_at_full_cutoff(oracle_mod):
+    N = 5
+    m = _filter_box(oracle_mod, N, nz=2, h0=0.0)
+    x, y, z = m.get("xu")
+    lowdeg = 1.0 + 1e-3 * z + 1e-7 * z * z     # degree 2 in z, constant in x, y
+    q = np.zeros((5, m.n_unique))
+    q[0] = lowdeg
+    q[4] = 3.0 - 2e-3 * z
+    out = m.filter(q, 10.0, 2)
+    np.testing.assert_allclose(out, q, rtol=0, atol=1e-13)
+    rng = np.random.default_rng(7)
+    r = np.zeros((5, m.n_unique))
+    r[0], r[4] = rng.standard_normal((2, m.n_unique))
+    np.testing.assert_allclose(m.filter(r, 10.0, N), r, rtol=0, atol=1e-13)
+
+
+def test_filter_conserves_mass_and_respects_walls(oracle_mod):
+    """Affine elements: the GLL-weighted element integral keeps only the mean
+    mode, which sigma_0 = 1 leaves, so sum M q is unchanged for rho' and theta';
+    the velocity has no normal component at the walls afterwards."""
+    m = _filter_box(oracle_mod, 4, nz=2)
+    rng = np.random.default_rng(8)
+    q = rng.standard_normal((5, m.n_unique))
+    out = m.filter(q, 8.0, 1)
+    M = m.get("mass")
+    for v in (0, 4):
+        assert abs((M * out[v]).sum() - (M * q[v]).sum()) < 1e-12 * (M * np.abs(q[v])).sum()
+    assert np.abs(out - q).max() > 0.1
+    nrm, isb = m.get("normals"), m.get("isbnd").astype(bool)
+    assert np.abs((out[1:4] * nrm).sum(0)[isb]).max() < 1e-14
