@@ -181,6 +181,27 @@ int32_t numa_rhs(numa_mesh_t m, int32_t prec, const double *q, double *c_elem, v
 int32_t numa_dss(numa_mesh_t m, int32_t nvar, const double *c_elem, double *out, int32_t flags,
                  void *stream);
 
+/* Boyd-Vandeven filter (Sec. "Filter"; Code example 1: filter after the
+ * stages, then DSS with the inverse mass matrix), in place on the state
+ * q [5][n_unique] (device).  Each element's nodal values of every variable are
+ * multiplied by F (x) F (x) F, F = V diag(sigma) V^-1 the 1D nodal filter
+ * (V_ik = P_k(xi_i), Legendre polynomials at the GLL nodes), weighted by J w,
+ * summed at the unique nodes, divided by M and projected at the walls: the
+ * DSS of numa_dss with NUMA_DSS_MASS | NUMA_DSS_NOFLUX.  The paper names the
+ * filter but not its parameters; here sigma_k = 1 for k <= cutoff and, with
+ * t = (k - cutoff) / (N - cutoff), d = t - 1/2, the erfc-log form
+ * sigma_k = erfc(2 sqrt(filter_order) d sqrt(-log(1 - 4 d^2) / (4 d^2))) / 2
+ * (1/2 at t = 1/2, 0 for the top mode N); cutoff >= N leaves every element
+ * unchanged.  filter_order must be finite and > 0, cutoff >= 0 (NUMA_EINVAL
+ * otherwise).  The state is the perturbation state (rho', u, v, w, theta'), so
+ * the hydrostatic reference is not filtered.  Uses the mesh's contribution
+ * scratch, like numa_step: calls on one mesh on different streams race. */
+int32_t numa_filter(numa_mesh_t m, double filter_order, int32_t cutoff, double *q, void *stream);
+
+/* The 1D filter matrix of numa_filter for GLL order `order` (1..8):
+ * F[i * (order + 1) + m], host memory, (order + 1)^2 doubles.  Host only. */
+int32_t numa_filter_matrix(int32_t order, double filter_order, int32_t cutoff, double *F);
+
 /* SSP-RK3 stage s in 0..2 (Shu-Osher form), pointwise over [5][n_unique]:
  * qout = a_s qn + b_s (qs + dt r), (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3).
  * qout may alias qs or qn; qn is not read for s = 0. */

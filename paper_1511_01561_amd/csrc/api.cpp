@@ -1,6 +1,7 @@
 // C-ABI entry points of libnuma (declared in include/numa.h): argument
 // checking, error reporting, workspace binding and the stage sequencing of
 // numa_step.  All arithmetic of the path runs in the HIP kernels.
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -279,6 +280,44 @@ int32_t numa_dss(numa_mesh_t m, int32_t nvar, const double *c_elem, double *out,
         return NUMA_EINVAL;
     }
     return numa::launch_dss(*m, nvar, c_elem, out, flags, as_stream(stream));
+}
+
+static bool filter_params_ok(const char *fn, double filter_order, int32_t cutoff)
+{
+    if (!(filter_order > 0.0) || !std::isfinite(filter_order) || cutoff < 0) {
+        set_error("%s: filter order must be finite and > 0 and the cutoff >= 0 (got %g, %d)", fn, filter_order,
+                  cutoff);
+        return false;
+    }
+    return true;
+}
+
+int32_t numa_filter_matrix(int32_t order, double filter_order, int32_t cutoff, double *F)
+{
+    double xi[numa::kMaxP], w[numa::kMaxP], D[numa::kMaxP * numa::kMaxP];
+    if (!F) {
+        set_error("numa_filter_matrix: null output");
+        return NUMA_EINVAL;
+    }
+    if (!numa::gll(order, xi, w, D)) {
+        set_error("numa_filter_matrix: order %d outside 1..8", order);
+        return NUMA_EINVAL;
+    }
+    if (!filter_params_ok("numa_filter_matrix", filter_order, cutoff)) return NUMA_EINVAL;
+    numa::filter_matrix(order, xi, w, filter_order, cutoff, F);
+    return NUMA_OK;
+}
+
+int32_t numa_filter(numa_mesh_t m, double filter_order, int32_t cutoff, double *q, void *stream)
+{
+    int32_t rc = need_ready(m, "numa_filter");
+    if (rc) return rc;
+    if (!q) {
+        set_error("numa_filter: null state");
+        return NUMA_EINVAL;
+    }
+    if (!filter_params_ok("numa_filter", filter_order, cutoff)) return NUMA_EINVAL;
+    return numa::launch_filter(*m, filter_order, cutoff, q, as_stream(stream));
 }
 
 int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn, const double *qs, const double *r,

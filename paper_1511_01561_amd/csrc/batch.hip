@@ -6,8 +6,6 @@
 // and per-node arithmetic is the single-mesh code (kernels.h), so an item's
 // result does not depend on what it is batched with.  A single box mesh
 // (numa_step) runs through the same kernels with one item.
-#include <type_traits>
-
 #include "kernels.h"
 
 namespace numa {
@@ -108,30 +106,6 @@ __device__ __forceinline__ void store_contributions(const BatchItem &it, int e, 
         const int t = l + r * BT;
         if (t < NP * 5) out[t] = st[t];
     }
-}
-
-// Copy n values staged in LDS (st, 16-byte aligned) to out with 16-byte
-// stores: the leading values until out is 16-byte aligned one by one, then
-// 16-byte vectors (two FP64 or four FP32 values per lane), then the tail.
-template <typename T>
-__device__ __forceinline__ void store_run(T *out, const T *st, int n, int t, int nthreads)
-{
-    using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
-    constexpr int W = 16 / sizeof(T);
-    int lead = (int)(((16 - ((uintptr_t)out & 15)) & 15) / sizeof(T));
-    if (lead > n) lead = n;
-    if (t < lead) out[t] = st[t];
-    const int nv = (n - lead) / W;
-    const T *sv = st + lead;
-    V *ov = reinterpret_cast<V *>(out + lead);
-    for (int u = t; u < nv; u += nthreads) {
-        V val;
-        T *vp = reinterpret_cast<T *>(&val);
-#pragma unroll
-        for (int c = 0; c < W; ++c) vp[c] = sv[u * W + c];
-        ov[u] = val;
-    }
-    for (int u = lead + nv * W + t; u < n; u += nthreads) out[u] = st[u];
 }
 
 // One workgroup per element (the launch-wide element index, XCD-remapped).
@@ -435,7 +409,7 @@ __global__ __launch_bounds__((col_threads<N, T>())) void k_elem_stream(Batch B)
     store_run<T>(out, st, ne * NP * 5, t, BT);
 }
 
-template <int N, int SEG, typename T>
+template <int N, int SEG, typename T, bool PLAIN = false>
 __global__ void k_fin_batch(Batch B)
 {
     const int g = (int)xcd_remap(blockIdx.x, gridDim.x);
@@ -467,8 +441,8 @@ __global__ void k_fin_batch(Batch B)
     b.walls = it.walls;
     b.ni = it.ni;
     b.nj = it.nj;
-    box_finish_node<N, SEG, T>(p, b, (const T *)it.ev, sx, ey, kbase == 0 ? (int)ez : it.nz - 1, threadIdx.x, kbase,
-                               klayers, B.stage, it.dt, it.qn, it.qs, it.qout);
+    box_finish_node<N, SEG, T, PLAIN>(p, b, (const T *)it.ev, sx, ey, kbase == 0 ? (int)ez : it.nz - 1, threadIdx.x,
+                                      kbase, klayers, B.stage, it.dt, it.qn, it.qs, it.qout);
 }
 
 template <int N, typename T>
@@ -551,6 +525,39 @@ int32_t run_chunk(const StepItem *items, int n, int stage, int phase, hipStream_
     return NUMA_OK;
 }
 
+// DSS of node-major FP64 contributions ev ([n_local][5]) into q with M^-1
+// and the wall projection, by the box finish kernel (one item)
+template <int N>
+int32_t run_plain_finish(const Mesh &m, const double *ev, double *q, hipStream_t s)
+{
+    constexpr int SEG = seg_for<N>();
+    Batch B{};
+    B.n = 1;
+    B.stage = 0;
+    BatchItem &it = B.it[0];
+    it.qout = q;
+    it.Minv = m.dv.Minv;
+    it.nrm = m.dv.nrm;
+    it.ev = (void *)ev;
+    it.nu = m.nu;
+    it.nh = m.nh;
+    it.ni = (int)m.ni;
+    it.nj = (int)m.nj;
+    it.nz = m.d.ne[2];
+    it.walls = m.walls ? 1 : 0;
+    it.fx = fast_div((uint32_t)m.d.ne[0]);
+    it.fy = fast_div((uint32_t)m.d.ne[1]);
+    it.fseg = fast_div((uint32_t)(m.d.ne[0] / SEG));
+    const int64_t mblk = (int64_t)(m.d.ne[0] / SEG) * m.d.ne[1] * m.d.ne[2];
+    it.mblk = (int)mblk;
+    it.ne = (int)m.ne;
+    const int64_t bo = mblk + (m.walls ? (int64_t)(m.d.ne[0] / SEG) * m.d.ne[1] : 0);
+    const int threads = ((SEG * N * N * N + 63) / 64) * 64;
+    hipLaunchKernelGGL((k_fin_batch<N, SEG, double, true>), dim3((unsigned)bo), dim3(threads), 0, s, B);
+    NUMA_HIP(hipGetLastError());
+    return NUMA_OK;
+}
+
 template <typename T>
 int32_t run_stage_t(const StepItem *items, int n, int stage, int phase, hipStream_t s)
 {
@@ -589,6 +596,20 @@ bool box_batchable(const Mesh &m)
     default: seg = seg_for<8>(); break;
     }
     return m.d.ne[0] % seg == 0;
+}
+
+int32_t launch_box_plain_finish(const Mesh &m, const double *ev, double *q, hipStream_t s)
+{
+    switch (m.N) {
+    case 1: return run_plain_finish<1>(m, ev, q, s);
+    case 2: return run_plain_finish<2>(m, ev, q, s);
+    case 3: return run_plain_finish<3>(m, ev, q, s);
+    case 4: return run_plain_finish<4>(m, ev, q, s);
+    case 5: return run_plain_finish<5>(m, ev, q, s);
+    case 6: return run_plain_finish<6>(m, ev, q, s);
+    case 7: return run_plain_finish<7>(m, ev, q, s);
+    default: return run_plain_finish<8>(m, ev, q, s);
+    }
 }
 
 int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int32_t stage, int phase, hipStream_t s)

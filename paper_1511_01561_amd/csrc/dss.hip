@@ -80,7 +80,8 @@ __global__ void k_stage_finish(PointArgs p, const int32_t *own, const int32_t *t
 // bottom layer (hoff/hidx, 1 to 4, ascending) times its radial copies (local
 // k = 0 of layer gk/N and k = N of the layer below on a layer boundary, else
 // one).  The contributions are node-major [n_local][5]; the up to four
-// horizontal copies of one radial copy are loaded together.
+// horizontal copies of one radial copy are loaded together.  PLAIN: the
+// output is the summed, mass-weighted, projected value (the filter's DSS).
 struct ShellFin {
     const int32_t *hoff, *hidx;
     FastDiv fnh;      // division by n_horiz
@@ -88,7 +89,7 @@ struct ShellFin {
     int64_t layer;    // elements of one layer times (N+1)^3
 };
 
-template <int N, typename T>
+template <int N, typename T, bool PLAIN = false>
 __global__ void k_shell_finish(PointArgs p, ShellFin sf, const T *ev, int stage, double dt, const double *qn,
                                const double *qs, double *qout)
 {
@@ -100,12 +101,13 @@ __global__ void k_shell_finish(PointArgs p, ShellFin sf, const T *ev, int stage,
     const int32_t h = I - (int32_t)(gk * sf.fnh.d);
     const double *qsi = qs + I, *qni = qn + I;
     const double mi = p.Minv[I];
-    double qsv[5], qnv[5];
+    double qsv[5] = {0, 0, 0, 0, 0}, qnv[5] = {0, 0, 0, 0, 0};
+    if (!PLAIN)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        qsv[v] = qsi[v * p.nu];
-        qnv[v] = stage == 0 ? 0.0 : qni[v * p.nu];
-    }
+        for (int v = 0; v < 5; ++v) {
+            qsv[v] = qsi[v * p.nu];
+            qnv[v] = stage == 0 ? 0.0 : qni[v * p.nu];
+        }
     // radial copies: (layer, local k)
     int ez[2], kz[2], nzc = 1;
     const int top = sf.nz * N;
@@ -145,12 +147,12 @@ __global__ void k_shell_finish(PointArgs p, ShellFin sf, const T *ev, int stage,
     noflux(p, I, r[1], r[2], r[3]);
     double *qoi = qout + I;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) qoi[v * p.nu] = rk_update(stage, qnv[v], qsv[v], dt, r[v]);
+    for (int v = 0; v < 5; ++v) qoi[v * p.nu] = PLAIN ? r[v] : rk_update(stage, qnv[v], qsv[v], dt, r[v]);
 }
 
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-template <typename T>
+template <typename T, bool PLAIN = false>
 void launch_shell_finish_t(Mesh &m, const T *ev, int32_t stage, double dt, const double *qn, const double *qs,
                            double *qout, hipStream_t s)
 {
@@ -162,14 +164,14 @@ void launch_shell_finish_t(Mesh &m, const T *ev, int32_t stage, double dt, const
     sf.layer = 6 * (int64_t)m.d.ne[0] * m.d.ne[0] * m.np;
     const dim3 grid(nblocks(m.nu, 256)), block(256);
     switch (m.N) {
-    case 1: hipLaunchKernelGGL((k_shell_finish<1, T>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
-    case 2: hipLaunchKernelGGL((k_shell_finish<2, T>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
-    case 3: hipLaunchKernelGGL((k_shell_finish<3, T>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
-    case 4: hipLaunchKernelGGL((k_shell_finish<4, T>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
-    case 5: hipLaunchKernelGGL((k_shell_finish<5, T>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
-    case 6: hipLaunchKernelGGL((k_shell_finish<6, T>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
-    case 7: hipLaunchKernelGGL((k_shell_finish<7, T>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
-    default: hipLaunchKernelGGL((k_shell_finish<8, T>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    case 1: hipLaunchKernelGGL((k_shell_finish<1, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    case 2: hipLaunchKernelGGL((k_shell_finish<2, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    case 3: hipLaunchKernelGGL((k_shell_finish<3, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    case 4: hipLaunchKernelGGL((k_shell_finish<4, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    case 5: hipLaunchKernelGGL((k_shell_finish<5, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    case 6: hipLaunchKernelGGL((k_shell_finish<6, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    case 7: hipLaunchKernelGGL((k_shell_finish<7, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    default: hipLaunchKernelGGL((k_shell_finish<8, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
     }
 }
 
@@ -187,6 +189,13 @@ int32_t launch_rk_stage(Mesh &m, int32_t stage, double dt, const double *qn, con
 {
     int64_t n = 5 * m.nu;
     hipLaunchKernelGGL(k_rk_stage, dim3(nblocks(n, 256)), dim3(256), 0, s, n, stage, dt, qn, qs, r, qout);
+    NUMA_HIP(hipGetLastError());
+    return NUMA_OK;
+}
+
+int32_t launch_shell_plain_finish(Mesh &m, const double *ev, double *q, hipStream_t s)
+{
+    launch_shell_finish_t<double, true>(m, ev, 0, 0.0, nullptr, nullptr, q, s);
     NUMA_HIP(hipGetLastError());
     return NUMA_OK;
 }

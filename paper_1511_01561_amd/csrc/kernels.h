@@ -4,6 +4,7 @@
 #pragma once
 
 #include <cmath>
+#include <type_traits>
 
 #include "numa_internal.h"
 
@@ -418,12 +419,14 @@ __device__ inline double rk_update(int stage, double qn, double qs, double dt, d
 // element above and N of the one below, wrapped when periodic), else one.  A
 // second launch with kbase = N, klayers = 1 covers the top wall layer
 // (ez = nz - 1).  Indices are 32-bit: the mesh keeps n_local, n_unique < 2^31.
+// PLAIN: the output is the summed, mass-weighted and projected value itself
+// (the filter's DSS); qs and qn are not read.
 struct BoxFin {
     int nx, ny, nz, walls;
     int ni, nj;
 };
 
-template <int N, int SEG, typename T>
+template <int N, int SEG, typename T, bool PLAIN = false>
 __device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin &b, const T *ev, int sx, int ey,
                                                 int ez, int lane, int kbase, int klayers, int stage, double dt,
                                                 const double *qn, const double *qs, double *qout)
@@ -469,12 +472,13 @@ __device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin
     const double *qsi = qs + I, *qni = qn + I;
     double *qoi = qout + I;
     const double mi = p.Minv[I];
-    double qsv[5], qnv[5];
+    double qsv[5] = {0, 0, 0, 0, 0}, qnv[5] = {0, 0, 0, 0, 0};
+    if (!PLAIN)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-        qsv[v] = qsi[v * p.nu];
-        qnv[v] = stage == 0 ? 0.0 : qni[v * p.nu];
-    }
+        for (int v = 0; v < 5; ++v) {
+            qsv[v] = qsi[v * p.nu];
+            qnv[v] = stage == 0 ? 0.0 : qni[v * p.nu];
+        }
     // copies of one z layer: the up to four (y, x) copies are loaded together
     // (absent ones re-read the first copy and count zero), so a node waits
     // for one round trip per z layer instead of one per copy
@@ -506,7 +510,30 @@ __device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin
     for (int v = 0; v < 5; ++v) r[v] *= mi;
     noflux(p, I, r[1], r[2], r[3]);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) qoi[v * p.nu] = rk_update(stage, qnv[v], qsv[v], dt, r[v]);
+    for (int v = 0; v < 5; ++v) qoi[v * p.nu] = PLAIN ? r[v] : rk_update(stage, qnv[v], qsv[v], dt, r[v]);
+}
+
+// Copy n values staged in LDS (st) to out with 16-byte stores: the leading values until out is 16-byte aligned one by one, then
+// 16-byte vectors (two FP64 or four FP32 values per lane), then the tail.
+template <typename T>
+__device__ __forceinline__ void store_run(T *out, const T *st, int n, int t, int nthreads)
+{
+    using V = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+    constexpr int W = 16 / sizeof(T);
+    int lead = (int)(((16 - ((uintptr_t)out & 15)) & 15) / sizeof(T));
+    if (lead > n) lead = n;
+    if (t < lead) out[t] = st[t];
+    const int nv = (n - lead) / W;
+    const T *sv = st + lead;
+    V *ov = reinterpret_cast<V *>(out + lead);
+    for (int u = t; u < nv; u += nthreads) {
+        V val;
+        T *vp = reinterpret_cast<T *>(&val);
+#pragma unroll
+        for (int c = 0; c < W; ++c) vp[c] = sv[u * W + c];
+        ov[u] = val;
+    }
+    for (int u = lead + nv * W + t; u < n; u += nthreads) out[u] = st[u];
 }
 
 // x-segment length of a box finish block: whole 128-byte lines of FP64 state

@@ -142,6 +142,11 @@ int32_t launch_export(Mesh &m, int32_t what, void *out, hipStream_t s);
 int32_t launch_init_state(Mesh &m, const numa_ic &ic, const double *noise, double *q, hipStream_t s);
 int32_t launch_rhs(Mesh &m, int32_t prec, const double *q, double *evec, hipStream_t s);
 int32_t launch_dss(Mesh &m, int32_t nvar, const double *cin, double *out, int32_t flags, hipStream_t s);
+void filter_sigma(int N, double order, int32_t cutoff, double *sigma);
+void filter_matrix(int N, const double *xi, const double *w, double order, int32_t cutoff, double *F);
+int32_t launch_filter(Mesh &m, double order, int32_t cutoff, double *q, hipStream_t s);
+int32_t launch_box_plain_finish(const Mesh &m, const double *ev, double *q, hipStream_t s);
+int32_t launch_shell_plain_finish(Mesh &m, const double *ev, double *q, hipStream_t s);
 int32_t launch_rk_stage(Mesh &m, int32_t stage, double dt, const double *qn, const double *qs,
                         const double *r, double *qout, hipStream_t s);
 // One solve of a batch at one stage: states and the E-vector scratch.

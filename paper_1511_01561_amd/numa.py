@@ -25,7 +25,7 @@ EXPORTED = ["numa_last_error", "numa_gll", "numa_mesh_create", "numa_mesh_destro
             "numa_geometry", "numa_export", "numa_init_state", "numa_rhs", "numa_dss",
             "numa_rk_stage", "numa_step", "numa_profile", "numa_profile_read", "numa_step_scratch_bytes",
             "numa_step_batch", "numa_batch_capture", "numa_graph_launch", "numa_graph_destroy",
-            "numa_mesh_set_metric"]
+            "numa_mesh_set_metric", "numa_filter", "numa_filter_matrix"]
 
 
 class numa_mesh_desc(ct.Structure):
@@ -79,6 +79,8 @@ def lib():
         "numa_rhs": (I32, [P, I32, P, P, P]),
         "numa_dss": (I32, [P, I32, P, P, I32, P]),
         "numa_rk_stage": (I32, [P, I32, D, P, P, P, P, P]),
+        "numa_filter": (I32, [P, D, I32, P, P]),
+        "numa_filter_matrix": (I32, [I32, D, I32, P]),
         "numa_step": (I32, [P, I32, D, I32, P, P]),
         "numa_profile": (I32, [P, I32]),
         "numa_profile_read": (I32, [P, P]),
@@ -107,6 +109,13 @@ def numa_gll(order: int):
     xi = np.zeros(order + 1); w = np.zeros(order + 1); D = np.zeros((order + 1, order + 1))
     check(lib().numa_gll(order, xi.ctypes.data, w.ctypes.data, D.ctypes.data))
     return xi, w, D
+
+
+def numa_filter_matrix(order: int, filter_order: float, cutoff: int):
+    import numpy as np
+    F = np.zeros((order + 1, order + 1))
+    check(lib().numa_filter_matrix(order, float(filter_order), int(cutoff), F.ctypes.data))
+    return F
 
 
 def _stream(stream):
@@ -208,6 +217,11 @@ class Mesh:
             out = self._empty(nvar, self.n_unique)
         check(lib().numa_dss(self._h, nvar, _ptr(c_elem), _ptr(out), flags, _stream(stream)))
         return out
+
+    def filter(self, q, filter_order, cutoff, stream=None):
+        """Boyd-Vandeven filter of the state q [5][n_unique] in place."""
+        check(lib().numa_filter(self._h, float(filter_order), int(cutoff), _ptr(q), _stream(stream)))
+        return q
 
     def rk_stage(self, stage, dt, qn, qs, r, out=None, stream=None):
         if out is None:

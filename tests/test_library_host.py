@@ -190,3 +190,27 @@ def test_empty_batch_rejected(L):
     assert b"no items" in L.numa_last_error()
     h = ct.c_void_p()
     assert L.numa_batch_capture(None, 0, 0, 1, None, ct.byref(h)) == -1
+
+
+@pytest.mark.parametrize("N,order,cutoff", [(1, 12.0, 0), (2, 12.0, 0), (4, 12.0, 1), (5, 6.0, 2), (6, 36.0, 3),
+                                            (7, 8.0, 0), (8, 16.0, 4), (8, 16.0, 8), (3, 2.0, 9)])
+def test_library_filter_matrix_matches_oracle(L, oracle_mod, N, order, cutoff):
+    """Host part of numa_filter: the library's nodal filter matrix (V^-1 from
+    the discrete GLL orthogonality) against the oracle's (Gauss-Jordan)."""
+    F = numa.numa_filter_matrix(N, order, cutoff)
+    np.testing.assert_allclose(F, oracle_mod.filter_matrix(N, order, cutoff), rtol=0, atol=5e-15 * N)
+
+
+def test_filter_rejects_bad_parameters(L):
+    buf = np.zeros(100)
+    for order, fo, cut in ((0, 12.0, 1), (9, 12.0, 1), (4, 0.0, 1), (4, -1.0, 1), (4, float("nan"), 1),
+                           (4, float("inf"), 1), (4, 12.0, -1)):
+        assert L.numa_filter_matrix(order, fo, cut, buf.ctypes.data) == -1, (order, fo, cut)
+        assert len(L.numa_last_error()) > 0
+    assert L.numa_filter_matrix(4, 12.0, 1, None) == -1
+    rc, h = _create(MESHES[0])
+    assert rc == 0
+    try:   # no workspace: refused before touching the GPU
+        assert L.numa_filter(h, 12.0, 1, ct.c_void_p(16), None) == -2
+    finally:
+        L.numa_mesh_destroy(h)
