@@ -215,8 +215,19 @@ int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn,
  * ascending element-local order (the order of numa_dss), applies M^-1, the
  * wall projection and the update.  Uses the workspace scratch; equals the
  * composition of numa_rhs, numa_dss and numa_rk_stage up to rounding.
+ * With a filter set on the mesh (numa_mesh_set_filter) every step ends with
+ * numa_filter (Code example 1: the filter follows the stages).
  * The stream must not run other work on q or the workspace meanwhile. */
 int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double *q, void *stream);
+
+/* Make numa_step, numa_step_batch and numa_batch_capture end every step with
+ * numa_filter(m, filter_order, cutoff) on the state (enable != 0), or stop
+ * doing so (enable == 0: the other arguments are ignored).  Parameters as for
+ * numa_filter (NUMA_EINVAL otherwise).  The filter of a batch item uses its
+ * mesh's scratch, one item after another on the batch's stream, so items may
+ * share a mesh; a captured graph keeps the setting of its capture.  Host
+ * only. */
+int32_t numa_mesh_set_filter(numa_mesh_t m, int32_t enable, double filter_order, int32_t cutoff);
 
 /* ---- Batched stages (continuous batching of independent solves) ----
  * An item is one solve: a mesh whose geometry may be shared with other items
@@ -227,7 +238,8 @@ int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double
  * items must have the same order and precision, be box meshes whose x element
  * count is a multiple of the finish segment (4 for N <= 6, 2 for N = 7, 8),
  * and have distinct states and scratch.  Each item's result is bitwise the
- * result of numa_step on it alone (the same per-element and per-node code). */
+ * result of numa_step on it alone (the same per-element and per-node code),
+ * the filter of its mesh included. */
 typedef struct numa_batch_item {
     numa_mesh_t mesh;
     double *q;

@@ -308,6 +308,19 @@ int32_t numa_filter_matrix(int32_t order, double filter_order, int32_t cutoff, d
     return NUMA_OK;
 }
 
+int32_t numa_mesh_set_filter(numa_mesh_t m, int32_t enable, double filter_order, int32_t cutoff)
+{
+    if (!m) {
+        set_error("numa_mesh_set_filter: null mesh handle");
+        return NUMA_EINVAL;
+    }
+    if (enable && !filter_params_ok("numa_mesh_set_filter", filter_order, cutoff)) return NUMA_EINVAL;
+    m->filter_on = enable != 0;
+    m->filter_order = enable ? filter_order : 0.0;
+    m->filter_cutoff = enable ? cutoff : 0;
+    return NUMA_OK;
+}
+
 int32_t numa_filter(numa_mesh_t m, double filter_order, int32_t cutoff, double *q, void *stream)
 {
     int32_t rc = need_ready(m, "numa_filter");
@@ -380,6 +393,13 @@ static int32_t run_stage(numa_mesh_t m, int32_t prec, int32_t stage, double dt, 
     return mark(m, m->ev_fin, false, s);
 }
 
+// the filter at the end of a step (Code example 1), when set on the mesh
+static int32_t run_filter(numa_mesh_t m, double *q, hipStream_t s)
+{
+    if (!m->filter_on) return NUMA_OK;
+    return numa::launch_filter(*m, m->filter_order, m->filter_cutoff, q, s);
+}
+
 int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double *q, void *stream)
 {
     int32_t rc = need_ready(m, "numa_step");
@@ -394,15 +414,18 @@ int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double
     if (numa::box_batchable(*m)) {
         void *ev = prec == NUMA_PREC_MIXED ? (void *)m->dv.ev32 : (void *)m->dv.ev64;
         numa::StepItem st[3] = {{m, q, q, qs, ev, dt}, {m, q, qs, qs, ev, dt}, {m, q, qs, q, ev, dt}};
-        for (int n = 0; n < nsteps; ++n)
+        for (int n = 0; n < nsteps; ++n) {
             for (int k = 0; k < 3; ++k)
                 if ((rc = run_batch_stage(&st[k], 1, prec, k, s))) return rc;
+            if ((rc = run_filter(m, q, s))) return rc;
+        }
         return NUMA_OK;
     }
     for (int n = 0; n < nsteps; ++n) {
         if ((rc = run_stage(m, prec, 0, dt, q, q, qs, s))) return rc;
         if ((rc = run_stage(m, prec, 1, dt, q, qs, qs, s))) return rc;
         if ((rc = run_stage(m, prec, 2, dt, q, qs, q, s))) return rc;
+        if ((rc = run_filter(m, q, s))) return rc;
     }
     return NUMA_OK;
 }
@@ -474,9 +497,12 @@ int32_t numa_step_batch(const numa_batch_item *items, int32_t n, int32_t prec, i
         st[n + k] = {m, q, qs, qs, ev, items[k].dt};
         st[2 * n + k] = {m, q, qs, q, ev, items[k].dt};
     }
-    for (int32_t step = 0; step < nsteps; ++step)
+    for (int32_t step = 0; step < nsteps; ++step) {
         for (int stage = 0; stage < 3; ++stage)
             if ((rc = run_batch_stage(&st[(size_t)stage * n], n, prec, stage, s))) return rc;
+        for (int32_t k = 0; k < n; ++k)  // one after another: items may share a mesh's scratch
+            if ((rc = run_filter(items[k].mesh, items[k].q, s))) return rc;
+    }
     return NUMA_OK;
 }
 

@@ -123,6 +123,9 @@ struct Mesh {
     DeviceView dv;
     bool uploaded = false, geom = false;
     int metric_mode = 0;  // NUMA_METRIC_STORED or NUMA_METRIC_RECOMPUTE (box)
+    bool filter_on = false;     // numa_step applies the filter after every step
+    double filter_order = 0.0;  // Boyd-Vandeven order p
+    int filter_cutoff = 0;      // modes 0..cutoff pass unchanged
     numa_phys ph{};
     double gamma = 0.0;
 };

@@ -25,7 +25,7 @@ EXPORTED = ["numa_last_error", "numa_gll", "numa_mesh_create", "numa_mesh_destro
             "numa_geometry", "numa_export", "numa_init_state", "numa_rhs", "numa_dss",
             "numa_rk_stage", "numa_step", "numa_profile", "numa_profile_read", "numa_step_scratch_bytes",
             "numa_step_batch", "numa_batch_capture", "numa_graph_launch", "numa_graph_destroy",
-            "numa_mesh_set_metric", "numa_filter", "numa_filter_matrix"]
+            "numa_mesh_set_metric", "numa_filter", "numa_filter_matrix", "numa_mesh_set_filter"]
 
 
 class numa_mesh_desc(ct.Structure):
@@ -81,6 +81,7 @@ def lib():
         "numa_rk_stage": (I32, [P, I32, D, P, P, P, P, P]),
         "numa_filter": (I32, [P, D, I32, P, P]),
         "numa_filter_matrix": (I32, [I32, D, I32, P]),
+        "numa_mesh_set_filter": (I32, [P, I32, D, I32]),
         "numa_step": (I32, [P, I32, D, I32, P, P]),
         "numa_profile": (I32, [P, I32]),
         "numa_profile_read": (I32, [P, P]),
@@ -222,6 +223,11 @@ class Mesh:
         """Boyd-Vandeven filter of the state q [5][n_unique] in place."""
         check(lib().numa_filter(self._h, float(filter_order), int(cutoff), _ptr(q), _stream(stream)))
         return q
+
+    def set_filter(self, filter_order=None, cutoff=0):
+        """Filter after every step of step() and the batched steps (None: off)."""
+        on = filter_order is not None
+        check(lib().numa_mesh_set_filter(self._h, 1 if on else 0, float(filter_order or 0.0), int(cutoff)))
 
     def rk_stage(self, stage, dt, qn, qs, r, out=None, stream=None):
         if out is None:

@@ -122,3 +122,84 @@ def test_filter_full_size(torch_cuda, oracle_mod):
     q = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 7))
     q[0] += 1e-3 * inputs.random_state(p.nu, seed=97)[0]
     filter_pair(p, q, 16.0, 1, "full-size filter")
+
+
+@pytest.mark.parametrize("which", ["box", "generic", "shell"])
+def test_step_with_mesh_filter_is_step_then_filter(torch_cuda, oracle_mod, which):
+    """numa_mesh_set_filter: every step of numa_step ends with the filter, the
+    same kernels as calling numa_filter after each step (bitwise), and the
+    oracle's stages-then-filter loop within the FP64 tolerance."""
+    wl = {"box": terrain_box(4), "generic": terrain_box(4, ne=(5, 3, 2)), "shell": small_shell(4)}[which]
+    p = Pair(wl, oracle_mod)
+    q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 8) if which != "shell" else None)
+    a, b = p.dev(q0), p.dev(q0)
+    p.g.set_filter(16.0, 1)
+    p.g.step(a, 0.05, 3)
+    p.g.set_filter(None)
+    for _ in range(3):
+        p.g.step(b, 0.05, 1)
+        p.g.filter(b, 16.0, 1)
+    torch_cuda.cuda.synchronize()
+    assert torch_cuda.equal(a, b)
+    qo = q0.copy()
+    for _ in range(3):
+        qo = p.o.filter(p.o.step(qo, 0.05, 1), 16.0, 1)
+    assert_groups(p.host(a), qo, TOL64, "%s step with mesh filter" % which)
+    c = p.dev(q0)                        # the filter switched off again
+    p.g.step(c, 0.05, 1)
+    assert_groups(p.host(c), p.o.step(q0, 0.05, 1), TOL64, "%s step after the filter is off" % which)
+
+
+def _box_item(n, N, seed, nz):
+    Lx, H = n * 6250.0, nz * 1250.0
+    return inputs.box_workload(n, n, nz, N, Lx, Lx, H, terrain=500.0, bubble_centre=(Lx / 3, Lx / 2, H / 2))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_with_filter_equals_alone_bitwise(torch_cuda, prec):
+    """Two items on one filtered mesh and one unfiltered item: each batched
+    result is bitwise its result alone."""
+    from paper_1511_01561_amd import numa
+    torch = torch_cuda
+    wa, wb = _box_item(8, 4, 1, 4), _box_item(4, 4, 2, 3)
+    ga = numa.Mesh(wa["mesh"], wa["phys"], prec_mask=3)
+    gb = numa.Mesh(wb["mesh"], wb["phys"], prec_mask=3)
+    ga.set_filter(12.0, 1)
+    qs = [ga.init_state(wa["ic"], inputs.device_noise(ga.n_unique, 1)),
+          ga.init_state(wa["ic"], inputs.device_noise(ga.n_unique, 2)),
+          gb.init_state(wb["ic"], inputs.device_noise(gb.n_unique, 3))]
+    meshes = [ga, ga, gb]
+    ref = [q.clone() for q in qs]
+    numa.step_batch([(g, q, numa.alloc_scratch(g, prec), 0.05) for g, q in zip(meshes, qs)], 3, prec)
+    for g, r in zip(meshes, ref):
+        g.step(r, 0.05, 3, prec=prec)
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(qs, ref))
+    # the filtered items differ from an unfiltered run
+    ga.set_filter(None)
+    u = ga.init_state(wa["ic"], inputs.device_noise(ga.n_unique, 1))
+    ga.step(u, 0.05, 3, prec=prec)
+    torch.cuda.synchronize()
+    assert not torch.equal(u, qs[0])
+
+
+def test_graph_with_filter_replays_match_eager(torch_cuda):
+    from paper_1511_01561_amd import numa
+    torch = torch_cuda
+    wa = _box_item(8, 4, 4, 4)
+    g = numa.Mesh(wa["mesh"], wa["phys"], prec_mask=1)
+    g.set_filter(10.0, 2)
+    q = g.init_state(wa["ic"], inputs.device_noise(g.n_unique, 4))
+    e = q.clone()
+    s = torch.cuda.Stream()
+    sg, se = numa.alloc_scratch(g, 0), numa.alloc_scratch(g, 0)
+    graph = numa.Graph([(g, q, sg, 0.05)], 2, 0, s)
+    for rep in range(3):
+        graph.launch(s)
+        s.synchronize()
+        numa.step_batch([(g, e, se, 0.05)], 2, 0)
+        junk = torch.randn(1 << 18, device="cuda", dtype=torch.float64).sum()
+        torch.cuda.synchronize()
+        assert torch.equal(q, e), rep
+    graph.close()
+    del junk

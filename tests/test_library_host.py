@@ -214,3 +214,16 @@ def test_filter_rejects_bad_parameters(L):
         assert L.numa_filter(h, 12.0, 1, ct.c_void_p(16), None) == -2
     finally:
         L.numa_mesh_destroy(h)
+
+
+def test_set_filter_validates_on_the_host(L):
+    rc, h = _create(MESHES[0])
+    assert rc == 0
+    try:
+        assert L.numa_mesh_set_filter(h, 1, 12.0, 1) == 0
+        assert L.numa_mesh_set_filter(h, 1, 0.0, 1) == -1
+        assert L.numa_mesh_set_filter(h, 1, 12.0, -1) == -1
+        assert L.numa_mesh_set_filter(h, 0, float("nan"), -5) == 0     # off: parameters ignored
+        assert L.numa_mesh_set_filter(None, 0, 0.0, 0) == -1
+    finally:
+        L.numa_mesh_destroy(h)
