@@ -237,6 +237,43 @@ def sweep(orders, shell_steps, long_steps, oracle_check=True):
     return res
 
 
+FILTER_ORDER, FILTER_CUTOFF = 16.0, 1
+
+
+def filter_leg(g, q0, dt, steps, stream):
+    """The Boyd-Vandeven filter on the bench state: the element filter and
+    its DSS (two launches), timed with events on the launch stream, against
+    the state read once and written once (80 B per unique node); and the FP64
+    step with the filter at its end."""
+    import torch
+    from paper_1511_01561_amd import numa
+    q = q0.clone()
+    for _ in range(2):
+        g.filter(q, FILTER_ORDER, FILTER_CUTOFF)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        g.filter(q, FILTER_ORDER, FILTER_CUTOFF)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / steps
+    algo = 80 * g.n_unique
+    g.set_filter(FILTER_ORDER, FILTER_CUTOFF)
+    q = q0.clone()
+    g.step(q, dt, 1)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    g.step(q, dt, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    g.set_filter(None)
+    assert torch.isfinite(q).all().item()
+    return {"order": FILTER_ORDER, "cutoff": FILTER_CUTOFF, "avg_us": s * 1e6, "algorithmic_bytes": algo,
+            "achieved_GBs": algo / s / 1e9, "frac": algo / s / 1e9 / HBM_PEAK_GBS,
+            "step_with_filter_ms": e0.elapsed_time(e1) / steps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -341,6 +378,9 @@ def main():
                     algorithmic_bytes=dom["algorithmic_bytes"], avg_launch_us=dom["avg_launch_us"],
                     other_kernel=(fin if dom is el else el))
     g.set_metric(numa.METRIC_RECOMPUTE)
+    filt = filter_leg(g, q0, dt, args.steps, stream)
+    _log("filter (p=%g, cutoff %d): %.1f us per launch pair, %.0f GB/s algorithmic; step with filter %.3f ms"
+         % (filt["order"], filt["cutoff"], filt["avg_us"], filt["achieved_GBs"], filt["step_with_filter_ms"]))
 
     if args.copy_probe:
         n = args.copy_probe * (1 << 20) // 8
@@ -383,6 +423,7 @@ def main():
         "mixed": mixed,
         "stored_metric": stored,
         "roofline": roofline,
+        "filter": filt,
         "serving": serve,
         "cpu_baseline": cpu,
     }

@@ -30,12 +30,23 @@ namespace {
 using namespace dev;
 
 struct FilterArgs {
-    const int32_t *G;    // [n_elem][np] gather map
-    const double *met;   // [n_elem][10][np], J w in component 9
-    const double *q;     // [5][n_unique]
-    double *c;           // [5][n_local] J w (F q) at every element-local node
+    const int32_t *G;     // [n_elem][np] gather map
+    const double *met;    // [n_elem][10][np], J w in component 9
+    const double *hcol;   // box: [nx*ny][4][(N+1)^2] column factors, J w_i w_j in factor 0
+    const double *q;      // [5][n_unique]
+    double *c;            // J w (F q) at every element-local node
     int64_t ne, nl, nu;
+    int ni, nj, nk;       // box lattice extents (nk = -1 unless z is periodic)
+    FastDiv fx, fy;       // division by the box element counts along x and y
+    double w[kMaxP];      // GLL weights
     double F[kMaxP * kMaxP];   // F[i * P + m]
+};
+
+// where an element's unique ids and J w come from
+enum FilterGeo {
+    kGeoStored = 0,   // gather map and stored J w (shell)
+    kGeoBox = 1,      // box lattice ids, stored J w
+    kGeoBoxCol = 2,   // box lattice ids, J w from the column factors (recomputed metric)
 };
 
 template <int N>
@@ -56,7 +67,7 @@ constexpr int filter_threads()
 // and shell finish kernels), staged in LDS so that the block's consecutive
 // elements go out as one run of 16-byte stores; else element-major
 // ([5][n_local], for the generic DSS).
-template <int N, bool NM>
+template <int N, bool NM, int GEO>
 __global__ void __launch_bounds__(filter_threads<N>()) k_filter(FilterArgs a)
 {
     constexpr int P = N + 1, PP = P * P, NP = PP * P, EB = filter_eb<N>(), NE = EB * NP;
@@ -69,13 +80,31 @@ __global__ void __launch_bounds__(filter_threads<N>()) k_filter(FilterArgs a)
     const int le = t / NP, l = t - le * NP;
     const int64_t e = e0 + le;
     const bool on = t < NE && e < a.ne;
-    if (t < NE) {
-        const int64_t g = on ? a.G[e * NP + l] : 0;
+    const int i = l % P, j = (l / P) % P, k = l / PP;
+    double Jw = 0.0;
+    if (on) {
+        int64_t g;
+        if constexpr (GEO == kGeoStored) {
+            g = a.G[e * NP + l];
+        } else {   // lattice corner of the element plus the local offset, wrapped where periodic
+            const uint32_t ty = fdiv((uint32_t)e, a.fx), ez = fdiv(ty, a.fy);
+            const int ex = (int)((uint32_t)e - ty * a.fx.d), ey = (int)(ty - ez * a.fy.d);
+            int gi = ex * N + i, gj = ey * N + j, gk = (int)ez * N + k;
+            if (gi == a.ni) gi = 0;
+            if (gj == a.nj) gj = 0;
+            if (gk == a.nk) gk = 0;
+            g = gi + (int64_t)a.ni * (gj + (int64_t)a.nj * gk);
+            if constexpr (GEO == kGeoBoxCol)
+                Jw = a.hcol[(int64_t)(ex + (int)a.fx.d * ey) * (4 * PP) + i + P * j] * a.w[k];
+        }
+        if constexpr (GEO != kGeoBoxCol) Jw = a.met[(e * 10 + 9) * NP + l];
 #pragma unroll
-        for (int v = 0; v < 5; ++v) s0[v][t] = on ? a.q[v * a.nu + g] : 0.0;
+        for (int v = 0; v < 5; ++v) s0[v][t] = a.q[v * a.nu + g];
+    } else if (t < NE) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) s0[v][t] = 0.0;
     }
     __syncthreads();
-    const int i = l % P, j = (l / P) % P, k = l / PP;
     if (t < NE) {   // xi: s1 = F s0 along i
         const int b = t - i;
 #pragma unroll
@@ -101,7 +130,6 @@ __global__ void __launch_bounds__(filter_threads<N>()) k_filter(FilterArgs a)
     double r[5] = {0, 0, 0, 0, 0};
     if (t < NE) {   // zeta along k, times J w
         const int b = t - k * PP;
-        const double Jw = on ? a.met[(e * 10 + 9) * NP + l] : 0.0;
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             double x = 0.0;
@@ -126,15 +154,23 @@ __global__ void __launch_bounds__(filter_threads<N>()) k_filter(FilterArgs a)
     }
 }
 
-template <int N>
-void launch_filter_n(const FilterArgs &a, bool node_major, hipStream_t s)
+template <int N, int GEO>
+void launch_filter_g(const FilterArgs &a, bool node_major, hipStream_t s)
 {
     constexpr int EB = filter_eb<N>();
     const unsigned blocks = (unsigned)((a.ne + EB - 1) / EB);
     if (node_major)
-        hipLaunchKernelGGL((k_filter<N, true>), dim3(blocks), dim3(filter_threads<N>()), 0, s, a);
+        hipLaunchKernelGGL((k_filter<N, true, GEO>), dim3(blocks), dim3(filter_threads<N>()), 0, s, a);
     else
-        hipLaunchKernelGGL((k_filter<N, false>), dim3(blocks), dim3(filter_threads<N>()), 0, s, a);
+        hipLaunchKernelGGL((k_filter<N, false, GEO>), dim3(blocks), dim3(filter_threads<N>()), 0, s, a);
+}
+
+template <int N>
+void launch_filter_n(const FilterArgs &a, int geo, bool node_major, hipStream_t s)
+{
+    if (geo == kGeoStored) launch_filter_g<N, kGeoStored>(a, node_major, s);
+    else if (geo == kGeoBox) launch_filter_g<N, kGeoBox>(a, node_major, s);
+    else launch_filter_g<N, kGeoBoxCol>(a, node_major, s);
 }
 
 // Legendre P_0..P_N at x by the three-term recurrence.
@@ -181,29 +217,39 @@ void filter_matrix(int N, const double *xi, const double *w, double order, int32
 
 int32_t launch_filter(Mesh &m, double order, int32_t cutoff, double *q, hipStream_t s)
 {
-    FilterArgs a;
+    FilterArgs a{};
     a.G = m.dv.G;
     a.met = m.dv.met;
+    a.hcol = m.dv.hcol;
     a.q = q;
     a.c = m.dv.ev64;
     a.ne = m.ne;
     a.nl = m.nl;
     a.nu = m.nu;
+    const bool shell = m.d.kind == NUMA_MESH_SHELL;
+    if (!shell) {
+        a.ni = (int)m.ni;
+        a.nj = (int)m.nj;
+        a.nk = m.d.periodic[2] ? (int)m.nk : -1;
+        a.fx = fast_div((uint32_t)m.d.ne[0]);
+        a.fy = fast_div((uint32_t)m.d.ne[1]);
+    }
+    for (int k = 0; k < m.P; ++k) a.w[k] = m.w[k];
     filter_matrix(m.N, m.xi, m.w, order, cutoff, a.F);
+    const int geo = shell ? kGeoStored : (m.metric_mode == NUMA_METRIC_RECOMPUTE ? kGeoBoxCol : kGeoBox);
     // the box (x extent a multiple of the finish segment) and the shell sum
     // node-major contributions with their stage finish kernels; other boxes
     // take the generic DSS
-    const bool shell = m.d.kind == NUMA_MESH_SHELL;
     const bool nm = shell || box_batchable(m);
     switch (m.N) {
-    case 1: launch_filter_n<1>(a, nm, s); break;
-    case 2: launch_filter_n<2>(a, nm, s); break;
-    case 3: launch_filter_n<3>(a, nm, s); break;
-    case 4: launch_filter_n<4>(a, nm, s); break;
-    case 5: launch_filter_n<5>(a, nm, s); break;
-    case 6: launch_filter_n<6>(a, nm, s); break;
-    case 7: launch_filter_n<7>(a, nm, s); break;
-    default: launch_filter_n<8>(a, nm, s); break;
+    case 1: launch_filter_n<1>(a, geo, nm, s); break;
+    case 2: launch_filter_n<2>(a, geo, nm, s); break;
+    case 3: launch_filter_n<3>(a, geo, nm, s); break;
+    case 4: launch_filter_n<4>(a, geo, nm, s); break;
+    case 5: launch_filter_n<5>(a, geo, nm, s); break;
+    case 6: launch_filter_n<6>(a, geo, nm, s); break;
+    case 7: launch_filter_n<7>(a, geo, nm, s); break;
+    default: launch_filter_n<8>(a, geo, nm, s); break;
     }
     NUMA_HIP(hipGetLastError());
     if (shell) return launch_shell_plain_finish(m, m.dv.ev64, q, s);

@@ -31,13 +31,16 @@ def filter_pair(p, q, order, cutoff, what):
     return qo
 
 
+@pytest.mark.parametrize("metric", [0, 1])
 @pytest.mark.parametrize("N", range(1, 9))
-def test_filter_parity_all_orders(torch_cuda, oracle_mod, N):
+def test_filter_parity_all_orders(torch_cuda, oracle_mod, N, metric):
+    """Stored J w and J w from the column factors of the recomputed metric."""
     # 4 x 3 x 3 = 36 elements: a ragged last block for every elements-per-block count above 1
     p = Pair(terrain_box(N), oracle_mod)
+    p.g.set_metric(metric)
     q = inputs.random_state(p.nu, seed=70 + N)
     cutoff = max(0, N // 2 - 1)
-    qo = filter_pair(p, q, 12.0, cutoff, "filter N=%d cutoff=%d" % (N, cutoff))
+    qo = filter_pair(p, q, 12.0, cutoff, "filter N=%d cutoff=%d metric=%d" % (N, cutoff, metric))
     assert np.abs(qo - q).max() > 0
 
 
@@ -56,11 +59,13 @@ def test_filter_parity_shell(torch_cuda, oracle_mod, N):
     filter_pair(p, q, 12.0, N // 2, "shell filter N=%d" % N)
 
 
+@pytest.mark.parametrize("metric", [0, 1])
 @pytest.mark.parametrize("N,ne", [(4, (5, 3, 2)), (6, (3, 2, 2)), (7, (3, 3, 1))])
-def test_filter_parity_generic_box_path(torch_cuda, oracle_mod, N, ne):
+def test_filter_parity_generic_box_path(torch_cuda, oracle_mod, N, ne, metric):
     """x extents that the box finish segments do not divide: element-major
     contributions and the generic DSS."""
     p = Pair(terrain_box(N, ne=ne), oracle_mod)
+    p.g.set_metric(metric)
     filter_pair(p, inputs.random_state(p.nu, seed=60 + N), 12.0, 1, "generic-path filter N=%d ne=%s" % (N, ne))
 
 
@@ -117,11 +122,18 @@ def test_filter_rejects_bad_parameters(torch_cuda, oracle_mod):
 
 
 def test_filter_full_size(torch_cuda, oracle_mod):
-    """64 x 64 x 16 elements, N = 4, terrain 500 m: the whole filtered state."""
+    """64 x 64 x 16 elements, N = 4, terrain 500 m: the whole filtered state,
+    with the stored and the recomputed metric (the bench's mode)."""
+    from paper_1511_01561_amd import numa
     p = Pair(inputs.gpu_box(), oracle_mod)
     q = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 7))
     q[0] += 1e-3 * inputs.random_state(p.nu, seed=97)[0]
-    filter_pair(p, q, 16.0, 1, "full-size filter")
+    qo = p.o.filter(q, 16.0, 1)
+    for mode in (numa.METRIC_STORED, numa.METRIC_RECOMPUTE):
+        p.g.set_metric(mode)
+        qg = p.dev(q)
+        p.g.filter(qg, 16.0, 1)
+        assert_groups(p.host(qg), qo, TOL64, "full-size filter metric=%d" % mode)
 
 
 @pytest.mark.parametrize("which", ["box", "generic", "shell"])
