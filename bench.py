@@ -24,7 +24,9 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 # the stage kernels' sources: a traffic record holds only while they are unchanged
 _STAGE_SOURCES = [os.path.join(ROOT, "paper_1511_01561_amd", "csrc", f) for f in ("kernels.h", "batch.hip")]
-KERNEL_SOURCES = {"element": _STAGE_SOURCES, "finish": _STAGE_SOURCES}
+_FILTER_SOURCES = _STAGE_SOURCES + [os.path.join(ROOT, "paper_1511_01561_amd", "csrc", "filter.hip")]
+KERNEL_SOURCES = {"element": _STAGE_SOURCES, "finish": _STAGE_SOURCES, "filter": _FILTER_SOURCES,
+                  "filter_finish": _FILTER_SOURCES}
 
 
 def _log(msg):
@@ -240,7 +242,7 @@ def sweep(orders, shell_steps, long_steps, oracle_check=True):
 FILTER_ORDER, FILTER_CUTOFF = 16.0, 1
 
 
-def filter_leg(g, q0, dt, steps, stream):
+def filter_leg(g, q0, dt, steps, stream, workload):
     """The Boyd-Vandeven filter on the bench state: the element filter and
     its DSS (two launches), timed with events on the launch stream, against
     the state read once and written once (80 B per unique node); and the FP64
@@ -269,8 +271,10 @@ def filter_leg(g, q0, dt, steps, stream):
     torch.cuda.synchronize()
     g.set_filter(None)
     assert torch.isfinite(q).all().item()
+    tf, tn = load_traffic("filter", workload), load_traffic("filter_finish", workload)
     return {"order": FILTER_ORDER, "cutoff": FILTER_CUTOFF, "avg_us": s * 1e6, "algorithmic_bytes": algo,
             "achieved_GBs": algo / s / 1e9, "frac": algo / s / 1e9 / HBM_PEAK_GBS,
+            "traffic": tf + tn if tf is not None and tn is not None else None,
             "step_with_filter_ms": e0.elapsed_time(e1) / steps}
 
 
@@ -378,7 +382,7 @@ def main():
                     algorithmic_bytes=dom["algorithmic_bytes"], avg_launch_us=dom["avg_launch_us"],
                     other_kernel=(fin if dom is el else el))
     g.set_metric(numa.METRIC_RECOMPUTE)
-    filt = filter_leg(g, q0, dt, args.steps, stream)
+    filt = filter_leg(g, q0, dt, args.steps, stream, workload)
     _log("filter (p=%g, cutoff %d): %.1f us per launch pair, %.0f GB/s algorithmic; step with filter %.3f ms"
          % (filt["order"], filt["cutoff"], filt["avg_us"], filt["achieved_GBs"], filt["step_with_filter_ms"]))
 
