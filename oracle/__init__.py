@@ -72,6 +72,9 @@ def lib():
         L.or_filter_sigma.argtypes = [ct.c_int, ct.c_double, ct.c_int, P]
         L.or_filter_matrix.argtypes = [ct.c_int, ct.c_double, ct.c_int, P]
         L.or_filter.argtypes = [P, ct.c_double, ct.c_int, P]
+        L.or_rk53_coeffs.argtypes = [P, P]
+        L.or_rk53_combine.argtypes = [ct.c_int64, ct.c_int, ct.c_double, P, P, P]
+        L.or_step_rk53.argtypes = [P, ct.c_double, ct.c_int, P]
         _lib = L
     return _lib
 
@@ -217,9 +220,11 @@ class OracleMesh:
             raise ValueError("oracle filter (%d)" % rc)
         return q
 
-    def step(self, q: np.ndarray, dt: float, nsteps: int) -> np.ndarray:
+    def step(self, q: np.ndarray, dt: float, nsteps: int, scheme: str = "ssp33") -> np.ndarray:
+        """nsteps steps of SSP-RK3 (scheme "ssp33") or SSP-RK(5,3) ("ssp53")."""
         q = np.array(q, dtype=np.float64, copy=True).reshape(5, self.n_unique)
-        if lib().or_step(self._h, dt, nsteps, _p(q)) != 0:
+        fn = {"ssp33": lib().or_step, "ssp53": lib().or_step_rk53}[scheme]
+        if fn(self._h, dt, nsteps, _p(q)) != 0:
             raise MemoryError("oracle step")
         return q
 
@@ -238,6 +243,24 @@ def filter_matrix(N: int, order: float, cutoff: int) -> np.ndarray:
     if lib().or_filter_matrix(N, float(order), int(cutoff), _p(F)) != 0:
         raise ValueError("filter parameters")
     return F
+
+
+def rk53_coeffs():
+    """alpha, beta ([6][5]) of the oracle's SSP-RK(5,3) Shu-Osher form."""
+    a, b = np.zeros((6, 5)), np.zeros((6, 5))
+    lib().or_rk53_coeffs(_p(a), _p(b))
+    return a, b
+
+
+def rk53_combine(i: int, dt: float, U: np.ndarray, L: np.ndarray) -> np.ndarray:
+    """Stage i (1..5) from the stage values U [6][n] and L(u_k) [5][n]."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    n = U.shape[1]
+    out = np.zeros(n)
+    if lib().or_rk53_combine(n, i, float(dt), _p(U), _p(L), _p(out)) != 0:
+        raise ValueError("stage index")
+    return out
 
 
 def num_threads() -> int:

@@ -851,6 +851,82 @@ int or_step(const or_ctx *C, double dt, int nsteps, double *q)
 }
 
 /*
+ * The paper's fully explicit scheme has five stages and third order (Sec.
+ * "Time Discretization") but the text gives no coefficients.  Reading: the
+ * optimal five-stage, third-order strong-stability-preserving Runge-Kutta
+ * method of Spiteri and Ruuth (SIAM J. Numer. Anal. 40(2), 2002), in
+ * Shu-Osher form
+ *   u_0 = q^n,  u_i = sum_{k<i} (alpha_ik u_k + beta_ik dt L(u_k)),  i = 1..5,
+ *   q^{n+1} = u_5,
+ * with L(u) = DSS_M(create_rhs(u)) as for SSP-RK3.  The nonzero coefficients
+ * as published (15 digits); every other alpha_ik, beta_ik is zero.
+ */
+static const double RK53_ALPHA[6][5] = {
+    {0, 0, 0, 0, 0},
+    {1.0, 0, 0, 0, 0},
+    {0, 1.0, 0, 0, 0},
+    {0.355909775063327, 0, 0.644090224936674, 0, 0},
+    {0.367933791638137, 0, 0, 0.632066208361863, 0},
+    {0, 0, 0.237593836598569, 0, 0.762406163401431},
+};
+static const double RK53_BETA[6][5] = {
+    {0, 0, 0, 0, 0},
+    {0.377268915331368, 0, 0, 0, 0},
+    {0, 0.377268915331368, 0, 0, 0},
+    {0, 0, 0.242995220537396, 0, 0},
+    {0, 0, 0, 0.238458932846290, 0},
+    {0, 0, 0, 0, 0.287632146308408},
+};
+
+/* the tables above, row-major [6][5] each */
+void or_rk53_coeffs(double *alpha, double *beta)
+{
+    for (int i = 0; i < 6; i++)
+        for (int k = 0; k < 5; k++) {
+            alpha[i * 5 + k] = RK53_ALPHA[i][k];
+            beta[i * 5 + k] = RK53_BETA[i][k];
+        }
+}
+
+/* stage i (1..5) of the Shu-Osher form on n values: out = sum over k < i of
+ * alpha_ik U_k + beta_ik dt L_k, where U and L hold u_k and L(u_k) row by row
+ * ([6][n] and [5][n]); terms with zero coefficients are skipped */
+int or_rk53_combine(int64_t n, int i, double dt, const double *U, const double *L, double *out)
+{
+    if (i < 1 || i > 5) return -1;
+    for (int64_t a = 0; a < n; a++) {
+        double s = 0.0;
+        for (int k = 0; k < i; k++) {
+            if (RK53_ALPHA[i][k] != 0.0) s += RK53_ALPHA[i][k] * U[k * n + a];
+            if (RK53_BETA[i][k] != 0.0) s += RK53_BETA[i][k] * dt * L[k * n + a];
+        }
+        out[a] = s;
+    }
+    return 0;
+}
+
+/* nsteps SSP-RK(5,3) steps in place on q ([5][nu]); every stage value u_k and
+ * every L(u_k) is kept for the step */
+int or_step_rk53(const or_ctx *C, double dt, int nsteps, double *q)
+{
+    int64_t n = 5 * C->nu;
+    double *cbuf = (double *)malloc(sizeof(double) * 5 * C->nl);
+    double *U = (double *)malloc(sizeof(double) * 6 * n);
+    double *L = (double *)malloc(sizeof(double) * 5 * n);
+    if (!cbuf || !U || !L) { free(cbuf); free(U); free(L); return -2; }
+    for (int s = 0; s < nsteps; s++) {
+        memcpy(U, q, sizeof(double) * n);
+        for (int i = 1; i <= 5; i++) {
+            full_rhs(C, U + (i - 1) * n, cbuf, L + (i - 1) * n);
+            or_rk53_combine(n, i, dt, U, L, U + i * n);
+        }
+        memcpy(q, U + 5 * n, sizeof(double) * n);
+    }
+    free(cbuf); free(U); free(L);
+    return 0;
+}
+
+/*
  * Boyd-Vandeven filter (Sec. "Filter"; Code example 1: "compute filter",
  * then "DSS and multiply with inverse mass matrix").  The paper names the
  * filter -- a spectral transformation of the element's nodal values that

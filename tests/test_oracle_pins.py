@@ -689,3 +689,92 @@ def test_filter_conserves_mass_and_respects_walls(oracle_mod):
     assert np.abs(out - q).max() > 0.1
     nrm, isb = m.get("normals"), m.get("isbnd").astype(bool)
     assert np.abs((out[1:4] * nrm).sum(0)[isb]).max() < 1e-14
+
+
+# --------------------------------------------------------------------------
+# SSP-RK(5,3) (Sec. "Time Discretization": five stages, third order; the
+# coefficients are those of Spiteri and Ruuth's optimal SSP(5,3) method)
+# --------------------------------------------------------------------------
+def _butcher(alpha, beta):
+    """Shu-Osher (alpha, beta) -> Butcher A (rows: stages 1..5 in terms of L(u_0..u_4))."""
+    A = np.zeros((6, 5))
+    for i in range(1, 6):
+        for k in range(i):
+            A[i] += alpha[i, k] * A[k]
+            A[i, k] += beta[i, k]
+    return A[:5], A[5]
+
+
+def test_rk53_order_conditions(oracle_mod):
+    alpha, beta = oracle_mod.rk53_coeffs()
+    np.testing.assert_allclose(alpha[1:].sum(1), 1.0, rtol=0, atol=2e-15)     # consistency
+    assert np.all(alpha >= 0) and np.all(beta >= 0)                            # SSP form
+    A, b = _butcher(alpha, beta)
+    c = A.sum(1)
+    assert abs(b.sum() - 1) < 2e-15
+    assert abs(b @ c - 1 / 2) < 2e-15
+    assert abs(b @ c ** 2 - 1 / 3) < 2e-15
+    assert abs(b @ A @ c - 1 / 6) < 2e-15
+    # third order exactly: the fourth-order conditions fail
+    assert abs(b @ c ** 3 - 1 / 4) > 1e-3 or abs(b @ A @ A @ c - 1 / 24) > 1e-3
+    # an optimal SSP method: every nonzero beta_ik has the same alpha_ik / beta_ik
+    r = alpha[beta > 0] / beta[beta > 0]
+    assert np.ptp(r) < 1e-12 * r[0] and 2.6 < r[0] < 2.7
+
+
+def test_rk53_linear_amplification(oracle_mod):
+    """L(u) = lam u through the stage combination: R(z) agrees with the
+    Butcher form's polynomial, whose first four terms are those of exp(z)."""
+    alpha, beta = oracle_mod.rk53_coeffs()
+    A, b = _butcher(alpha, beta)
+    coef = [1.0] + [b @ np.linalg.matrix_power(A, k) @ np.ones(5) for k in range(5)]
+    np.testing.assert_allclose(coef[:4], [1, 1, 1 / 2, 1 / 6], rtol=0, atol=2e-15)
+    for z in (-0.3, -1.2, -2.5):
+        lam, dt = z, 1.0
+        U, L = np.zeros((6, 1)), np.zeros((5, 1))
+        U[0] = 1.0
+        for i in range(1, 6):
+            L[i - 1] = lam * U[i - 1]
+            U[i] = oracle_mod.rk53_combine(i, dt, U, L)
+        assert abs(U[5, 0] - sum(cf * z ** k for k, cf in enumerate(coef))) < 1e-14
+
+
+def test_rk53_third_order_convergence(oracle_mod):
+    """y' = -y^2, y(0) = 1 (y = 1/(1+t)) to t = 1: the error falls 8x per halving."""
+    def run(dt):
+        y = np.array([[1.0]])
+        for _ in range(int(round(1.0 / dt))):
+            U, L = np.zeros((6, 1)), np.zeros((5, 1))
+            U[0] = y[0]
+            for i in range(1, 6):
+                L[i - 1] = -U[i - 1] ** 2
+                U[i] = oracle_mod.rk53_combine(i, dt, U, L)
+            y = U[5:6]
+        return abs(y[0, 0] - 0.5)
+    e = [run(dt) for dt in (0.2, 0.1, 0.05)]
+    rates = np.log2(np.array(e[:-1]) / np.array(e[1:]))
+    assert np.all((rates > 2.8) & (rates < 3.3)), rates
+
+
+def test_rk53_mesh_invariants(small):
+    m, wl = small
+    q0 = m.init_state(wl["ic"], inputs.noise(m.n_unique, 0))
+    M = m.get("mass")
+    rb = m.get("ref")[0]
+    q = m.step(q0, 0.05, 6, scheme="ssp53")
+    assert abs((M * q[0]).sum() - (M * q0[0]).sum()) <= 1e-13 * (M * rb).sum()
+    assert np.array_equal(q, m.step(m.step(q0, 0.05, 3, scheme="ssp53"), 0.05, 3, scheme="ssp53"))
+
+
+def test_rk53_and_rk3_agree_to_third_order(small):
+    """Both schemes are third order: their difference after a fixed time falls
+    about 8x when dt halves."""
+    m, wl = small
+    q0 = m.init_state(wl["ic"], inputs.noise(m.n_unique, 0))
+    d = []
+    for dt, n in ((0.4, 4), (0.2, 8), (0.1, 16)):
+        a = m.step(q0, dt, n, scheme="ssp53")
+        b = m.step(q0, dt, n)
+        d.append(np.abs(a[4] - b[4]).max())
+    rates = np.log2(np.array(d[:-1]) / np.array(d[1:]))
+    assert np.all((rates > 2.6) & (rates < 3.4)), (d, rates)
