@@ -53,6 +53,9 @@ extern "C" {
 #define NUMA_METRIC_STORED 0     /* metric terms and J w read per element-local node */
 #define NUMA_METRIC_RECOMPUTE 1  /* box: recomputed in the element kernel every stage */
 
+#define NUMA_RK_SSP33 0      /* three-stage third-order SSP Runge-Kutta (Shu-Osher) */
+#define NUMA_RK_SSP53 1      /* five-stage third-order SSP Runge-Kutta (Spiteri-Ruuth) */
+
 #define NUMA_DSS_MASS 1     /* divide the summed contributions by the mass matrix */
 #define NUMA_DSS_NOFLUX 2   /* project components 1..3 of a 5-variable field at walls */
 
@@ -208,7 +211,8 @@ int32_t numa_filter_matrix(int32_t order, double filter_order, int32_t cutoff, d
 int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn, const double *qs,
                       const double *r, double *qout, void *stream);
 
-/* nsteps SSP-RK3 steps in place on q [5][n_unique] (device), each stage being
+/* nsteps Runge-Kutta steps in place on q [5][n_unique] (device) with the mesh's
+ * integrator (numa_mesh_set_integrator; SSP-RK3 unless set), each stage being
  * rhs -> DSS (mass, no-flux) -> stage update, fused into two kernels: the
  * element kernel updates nodes that have a single copy and stores the other
  * copies' contributions by unique node; the finish kernel sums them in
@@ -219,6 +223,22 @@ int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn,
  * numa_filter (Code example 1: the filter follows the stages).
  * The stream must not run other work on q or the workspace meanwhile. */
 int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double *q, void *stream);
+
+/* The time integrator of numa_step, numa_step_batch and numa_batch_capture
+ * (Sec. "Time Discretization": explicit Runge-Kutta; the paper's scheme has
+ * five stages and third order, its coefficients are not in the text):
+ * NUMA_RK_SSP33, the three-stage third-order SSP scheme in Shu-Osher form
+ * (default), or NUMA_RK_SSP53, the optimal five-stage third-order SSP scheme
+ * of Spiteri and Ruuth (SIAM J. Numer. Anal. 40(2), 2002):
+ *   u1 = u0 + b10 dt L(u0), u2 = u1 + b21 dt L(u1),
+ *   u3 = a30 u0 + a32 u2 + b32 dt L(u2), u4 = a40 u0 + a43 u3 + b43 dt L(u3),
+ *   q^{n+1} = a52 u2 + a54 u4 + b54 dt L(u4)
+ * (15-digit coefficients in api.cpp).  Every stage is one fused stage as in
+ * numa_step; SSP53 keeps a second stage state (in the workspace, and in batch
+ * scratch: numa_step_scratch_bytes grows by 40 n_unique bytes, so size the
+ * scratch after choosing the integrator).  NUMA_EINVAL for an unknown value.
+ * Host only. */
+int32_t numa_mesh_set_integrator(numa_mesh_t m, int32_t integrator);
 
 /* Make numa_step, numa_step_batch and numa_batch_capture end every step with
  * numa_filter(m, filter_order, cutoff) on the state (enable != 0), or stop
@@ -232,10 +252,12 @@ int32_t numa_mesh_set_filter(numa_mesh_t m, int32_t enable, double filter_order,
 /* ---- Batched stages (continuous batching of independent solves) ----
  * An item is one solve: a mesh whose geometry may be shared with other items
  * (read only), its state q [5][n_unique] (device, updated in place), private
- * device scratch of numa_step_scratch_bytes() (256-byte aligned), and its dt.
- * numa_step_batch advances all items by nsteps SSP-RK3 steps with one
+ * device scratch of at least numa_step_scratch_bytes() (256-byte aligned; its
+ * size in scratch_bytes, NUMA_ENOMEM if short), and its dt.
+ * numa_step_batch advances all items by nsteps Runge-Kutta steps with one
  * element launch and one finish launch per stage for every 16 items.  All
- * items must have the same order and precision, be box meshes whose x element
+ * items must have the same order, precision, metric mode and integrator, be
+ * box meshes whose x element
  * count is a multiple of the finish segment (4 for N <= 6, 2 for N = 7, 8),
  * and have distinct states and scratch.  Each item's result is bitwise the
  * result of numa_step on it alone (the same per-element and per-node code),
@@ -244,6 +266,7 @@ typedef struct numa_batch_item {
     numa_mesh_t mesh;
     double *q;
     void *scratch;
+    uint64_t scratch_bytes;  /* size of scratch: at least numa_step_scratch_bytes() */
     double dt;
 } numa_batch_item;
 

@@ -367,29 +367,29 @@ static int32_t mark(numa_mesh_t m, std::vector<std::pair<int, int>> &log, bool b
 
 // one fused stage of a batch: element kernels then finish kernels; events are
 // recorded on the first item's mesh when it is profiling
-static int32_t run_batch_stage(const numa::StepItem *items, int n, int32_t prec, int32_t stage, hipStream_t s)
+static int32_t run_batch_stage(const numa::StepItem *items, int n, int32_t prec, hipStream_t s)
 {
     numa_mesh_t m0 = static_cast<numa_mesh_t>(const_cast<Mesh *>(items[0].mesh));
     int32_t rc;
     if ((rc = mark(m0, m0->ev_elem, true, s))) return rc;
-    if ((rc = numa::launch_batch_stage(items, n, prec, stage, 0, s))) return rc;
+    if ((rc = numa::launch_batch_stage(items, n, prec, 0, s))) return rc;
     if ((rc = mark(m0, m0->ev_elem, false, s))) return rc;
     if ((rc = mark(m0, m0->ev_fin, true, s))) return rc;
-    if ((rc = numa::launch_batch_stage(items, n, prec, stage, 1, s))) return rc;
+    if ((rc = numa::launch_batch_stage(items, n, prec, 1, s))) return rc;
     return mark(m0, m0->ev_fin, false, s);
 }
 
 // one fused stage of a single mesh through the general kernels (shell, or a
 // box whose x extent does not fit the batched finish)
-static int32_t run_stage(numa_mesh_t m, int32_t prec, int32_t stage, double dt, const double *qn, const double *qs,
+static int32_t run_stage(numa_mesh_t m, int32_t prec, const numa::StageCoef &c, const double *qn, const double *qs,
                          double *qout, hipStream_t s)
 {
     int32_t rc;
     if ((rc = mark(m, m->ev_elem, true, s))) return rc;
-    if ((rc = numa::launch_stage_elements(*m, prec, stage, dt, qn, qs, qout, s))) return rc;
+    if ((rc = numa::launch_stage_elements(*m, prec, qs, s))) return rc;
     if ((rc = mark(m, m->ev_elem, false, s))) return rc;
     if ((rc = mark(m, m->ev_fin, true, s))) return rc;
-    if ((rc = numa::launch_stage_finish(*m, prec, stage, dt, qn, qs, qout, s))) return rc;
+    if ((rc = numa::launch_stage_finish(*m, prec, c, qn, qs, qout, s))) return rc;
     return mark(m, m->ev_fin, false, s);
 }
 
@@ -398,6 +398,58 @@ static int32_t run_filter(numa_mesh_t m, double *q, hipStream_t s)
 {
     if (!m->filter_on) return NUMA_OK;
     return numa::launch_filter(*m, m->filter_order, m->filter_cutoff, q, s);
+}
+
+// The stages of one step in Shu-Osher form.  Buffers: 0 = q (u_0 = q^n at the
+// start, q^{n+1} at the end), 1 and 2 = stage scratch.  A stage evaluates the
+// right-hand side on buffer `in` and writes a q_ref + b (u_in + (beta/b) dt R)
+// to `out` (ref is not read when a = 0).  `out` may equal `in`: the finish is
+// pointwise and the element kernel has read `in` before it runs.
+struct StagePlan {
+    int in, ref, out;
+    double a, b, beta;
+};
+// SSP-RK3 (Shu-Osher): (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3), beta = b
+static const StagePlan kSsp33[3] = {
+    {0, 0, 1, 0.0, 1.0, 1.0}, {1, 0, 1, 0.75, 0.25, 0.25}, {1, 0, 0, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0}};
+// Five-stage third-order SSP Runge-Kutta (Spiteri and Ruuth, SIAM J. Numer.
+// Anal. 40(2), 2002), the paper's explicit scheme class (Sec. "Time
+// Discretization": five stages, third order):
+//   u1 = u0 + b10 dt L(u0),  u2 = u1 + b21 dt L(u1),
+//   u3 = a30 u0 + a32 u2 + b32 dt L(u2),  u4 = a40 u0 + a43 u3 + b43 dt L(u3),
+//   u5 = a52 u2 + a54 u4 + b54 dt L(u4).
+// Buffer 1 holds u1, u3, u4; buffer 2 holds u2 until the last stage.
+static const StagePlan kSsp53[5] = {
+    {0, 0, 1, 0.0, 1.0, 0.377268915331368},
+    {1, 0, 2, 0.0, 1.0, 0.377268915331368},
+    {2, 0, 1, 0.355909775063327, 0.644090224936674, 0.242995220537396},
+    {1, 0, 1, 0.367933791638137, 0.632066208361863, 0.238458932846290},
+    {1, 2, 0, 0.237593836598569, 0.762406163401431, 0.287632146308408}};
+
+static const StagePlan *stage_plan(int integrator, int *nstages)
+{
+    *nstages = integrator == NUMA_RK_SSP53 ? 5 : 3;
+    return integrator == NUMA_RK_SSP53 ? kSsp53 : kSsp33;
+}
+
+static numa::StageCoef stage_coef(const StagePlan &p, double dt)
+{
+    // SSP-RK3 keeps cdt = dt exactly (beta = b)
+    return numa::StageCoef{p.a, p.b, p.beta == p.b ? dt : (p.beta / p.b) * dt};
+}
+
+int32_t numa_mesh_set_integrator(numa_mesh_t m, int32_t integrator)
+{
+    if (!m) {
+        set_error("numa_mesh_set_integrator: null mesh handle");
+        return NUMA_EINVAL;
+    }
+    if (integrator != NUMA_RK_SSP33 && integrator != NUMA_RK_SSP53) {
+        set_error("numa_mesh_set_integrator: unknown integrator %d", integrator);
+        return NUMA_EINVAL;
+    }
+    m->integrator = integrator;
+    return NUMA_OK;
 }
 
 int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double *q, void *stream)
@@ -410,21 +462,23 @@ int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double
         return NUMA_EINVAL;
     }
     hipStream_t s = as_stream(stream);
-    double *qs = m->dv.qs;
-    if (numa::box_batchable(*m)) {
-        void *ev = prec == NUMA_PREC_MIXED ? (void *)m->dv.ev32 : (void *)m->dv.ev64;
-        numa::StepItem st[3] = {{m, q, q, qs, ev, dt}, {m, q, qs, qs, ev, dt}, {m, q, qs, q, ev, dt}};
-        for (int n = 0; n < nsteps; ++n) {
-            for (int k = 0; k < 3; ++k)
-                if ((rc = run_batch_stage(&st[k], 1, prec, k, s))) return rc;
-            if ((rc = run_filter(m, q, s))) return rc;
-        }
-        return NUMA_OK;
-    }
+    double *buf[3] = {q, m->dv.qs, m->dv.qs2};
+    int ns;
+    const StagePlan *plan = stage_plan(m->integrator, &ns);
+    const bool batched = numa::box_batchable(*m);
+    void *ev = prec == NUMA_PREC_MIXED ? (void *)m->dv.ev32 : (void *)m->dv.ev64;
     for (int n = 0; n < nsteps; ++n) {
-        if ((rc = run_stage(m, prec, 0, dt, q, q, qs, s))) return rc;
-        if ((rc = run_stage(m, prec, 1, dt, q, qs, qs, s))) return rc;
-        if ((rc = run_stage(m, prec, 2, dt, q, qs, q, s))) return rc;
+        for (int k = 0; k < ns; ++k) {
+            const StagePlan &p = plan[k];
+            const numa::StageCoef c = stage_coef(p, dt);
+            if (batched) {
+                numa::StepItem it = {m, buf[p.ref], buf[p.in], buf[p.out], ev, c};
+                rc = run_batch_stage(&it, 1, prec, s);
+            } else {
+                rc = run_stage(m, prec, c, buf[p.ref], buf[p.in], buf[p.out], s);
+            }
+            if (rc) return rc;
+        }
         if ((rc = run_filter(m, q, s))) return rc;
     }
     return NUMA_OK;
@@ -432,13 +486,21 @@ int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
+// batch-item scratch: stage state, contributions, and for SSP-RK(5,3) the
+// second stage state
+static uint64_t scratch_bytes(const Mesh &m, int32_t prec)
+{
+    return align256(40ull * m.nu) + align256((prec == NUMA_PREC_MIXED ? 20ull : 40ull) * m.nl) +
+           (m.integrator == NUMA_RK_SSP53 ? align256(40ull * m.nu) : 0);
+}
+
 int32_t numa_step_scratch_bytes(numa_mesh_t m, int32_t prec, uint64_t *bytes)
 {
     if (!m || !bytes) {
         set_error("numa_step_scratch_bytes: null argument");
         return NUMA_EINVAL;
     }
-    *bytes = align256(40ull * m->nu) + align256((prec == NUMA_PREC_MIXED ? 20ull : 40ull) * m->nl);
+    *bytes = scratch_bytes(*m, prec);
     return NUMA_OK;
 }
 
@@ -465,9 +527,18 @@ static int32_t check_batch(const numa_batch_item *items, int32_t n, int32_t prec
             set_error("%s: item %d uses another metric mode than item 0 (one mode per batch)", fn, k);
             return NUMA_EINVAL;
         }
+        if (m->integrator != items[0].mesh->integrator) {
+            set_error("%s: item %d uses another integrator than item 0 (one integrator per batch)", fn, k);
+            return NUMA_EINVAL;
+        }
         if (!items[k].q || !items[k].scratch || reinterpret_cast<uintptr_t>(items[k].scratch) % 256) {
             set_error("%s: item %d: null state or scratch not 256-byte aligned", fn, k);
             return NUMA_EINVAL;
+        }
+        if (items[k].scratch_bytes < scratch_bytes(*m, prec)) {
+            set_error("%s: item %d: scratch of %llu bytes, the item needs %llu", fn, k,
+                      (unsigned long long)items[k].scratch_bytes, (unsigned long long)scratch_bytes(*m, prec));
+            return NUMA_ENOMEM;
         }
         for (int32_t j = 0; j < k; ++j)
             if (items[j].q == items[k].q || items[j].scratch == items[k].scratch) {
@@ -487,19 +558,24 @@ int32_t numa_step_batch(const numa_batch_item *items, int32_t n, int32_t prec, i
         return NUMA_EINVAL;
     }
     hipStream_t s = as_stream(stream);
-    std::vector<numa::StepItem> st(3 * (size_t)n);
+    int ns;
+    const StagePlan *plan = stage_plan(items[0].mesh->integrator, &ns);
+    std::vector<numa::StepItem> st((size_t)ns * n);
     for (int32_t k = 0; k < n; ++k) {
         const Mesh *m = items[k].mesh;
-        double *q = items[k].q;
-        double *qs = static_cast<double *>(items[k].scratch);
-        void *ev = static_cast<char *>(items[k].scratch) + align256(40ull * m->nu);
-        st[k] = {m, q, q, qs, ev, items[k].dt};
-        st[n + k] = {m, q, qs, qs, ev, items[k].dt};
-        st[2 * n + k] = {m, q, qs, q, ev, items[k].dt};
+        char *scr = static_cast<char *>(items[k].scratch);
+        const uint64_t evb = align256((prec == NUMA_PREC_MIXED ? 20ull : 40ull) * m->nl);
+        double *buf[3] = {items[k].q, reinterpret_cast<double *>(scr),
+                          reinterpret_cast<double *>(scr + align256(40ull * m->nu) + evb)};
+        void *ev = scr + align256(40ull * m->nu);
+        for (int j = 0; j < ns; ++j) {
+            const StagePlan &p = plan[j];
+            st[(size_t)j * n + k] = {m, buf[p.ref], buf[p.in], buf[p.out], ev, stage_coef(p, items[k].dt)};
+        }
     }
     for (int32_t step = 0; step < nsteps; ++step) {
-        for (int stage = 0; stage < 3; ++stage)
-            if ((rc = run_batch_stage(&st[(size_t)stage * n], n, prec, stage, s))) return rc;
+        for (int j = 0; j < ns; ++j)
+            if ((rc = run_batch_stage(&st[(size_t)j * n], n, prec, s))) return rc;
         for (int32_t k = 0; k < n; ++k)  // one after another: items may share a mesh's scratch
             if ((rc = run_filter(items[k].mesh, items[k].q, s))) return rc;
     }

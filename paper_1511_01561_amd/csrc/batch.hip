@@ -18,7 +18,7 @@ constexpr int kMaxBatch = 16;  // items per launch (kernel-argument table)
 struct BatchItem {
     const double *qs;  // stage input state [5][nu]
     double *qout;      // stage output state
-    const double *qn;  // state at the start of the step
+    const double *qn;  // reference state of the stage update (q^n or an earlier stage)
     const double *ref, *Minv, *nrm;
     const void *met;      // [ne][10][np] of T
     void *ev;             // [nl][5] of T: contributions of this stage, node-major
@@ -29,7 +29,7 @@ struct BatchItem {
     int ne;               // elements
     int mblk;             // finish blocks of the main layers: (nx/SEG) ny nz
     FastDiv fx, fy, fseg;  // division by nx, ny and nx/SEG
-    double dt;
+    double cdt;            // (beta / b) dt of the stage update
     double theta0;         // the box reference is isentropic: theta_bar = theta0 everywhere
     BoxMetric bm;          // constants of the recomputed metric
     int eoff, boff;        // first element / finish block of this item in the launch (eoff: a
@@ -37,7 +37,8 @@ struct BatchItem {
 };
 
 struct Batch {
-    int n, stage;
+    int n;
+    double ca, cb;  // weights of the reference state and of the stage in the update (same for all items)
     double gamma, g0;
     const void *D;
     const double *xi, *w, *Dd;  // FP64 GLL nodes, weights, derivative matrix
@@ -442,16 +443,17 @@ __global__ void k_fin_batch(Batch B)
     b.ni = it.ni;
     b.nj = it.nj;
     box_finish_node<N, SEG, T, PLAIN>(p, b, (const T *)it.ev, sx, ey, kbase == 0 ? (int)ez : it.nz - 1, threadIdx.x,
-                                      kbase, klayers, B.stage, it.dt, it.qn, it.qs, it.qout);
+                                      kbase, klayers, StageCoef{B.ca, B.cb, it.cdt}, it.qn, it.qs, it.qout);
 }
 
 template <int N, typename T>
-int32_t run_chunk(const StepItem *items, int n, int stage, int phase, hipStream_t s)
+int32_t run_chunk(const StepItem *items, int n, int phase, hipStream_t s)
 {
     constexpr int SEG = seg_for<N>();
     Batch B;
     B.n = n;
-    B.stage = stage;
+    B.ca = items[0].c.a;
+    B.cb = items[0].c.b;
     B.gamma = items[0].mesh->gamma;
     B.g0 = items[0].mesh->ph.g0;
     B.D = std::is_same<T, float>::value ? (const void *)items[0].mesh->dv.D32 : (const void *)items[0].mesh->dv.D64;
@@ -492,7 +494,7 @@ int32_t run_chunk(const StepItem *items, int n, int stage, int phase, hipStream_
         it.fseg = fast_div((uint32_t)(m.d.ne[0] / SEG));
         const int64_t mblk = (int64_t)(m.d.ne[0] / SEG) * m.d.ne[1] * m.d.ne[2];
         it.mblk = (int)mblk;
-        it.dt = items[k].dt;
+        it.cdt = items[k].c.cdt;
         it.theta0 = m.ph.T0;
         it.bm = box_metric(m);
         it.ne = (int)m.ne;
@@ -533,7 +535,8 @@ int32_t run_plain_finish(const Mesh &m, const double *ev, double *q, hipStream_t
     constexpr int SEG = seg_for<N>();
     Batch B{};
     B.n = 1;
-    B.stage = 0;
+    B.ca = 0.0;
+    B.cb = 1.0;
     BatchItem &it = B.it[0];
     it.qout = q;
     it.Minv = m.dv.Minv;
@@ -559,20 +562,20 @@ int32_t run_plain_finish(const Mesh &m, const double *ev, double *q, hipStream_t
 }
 
 template <typename T>
-int32_t run_stage_t(const StepItem *items, int n, int stage, int phase, hipStream_t s)
+int32_t run_stage_t(const StepItem *items, int n, int phase, hipStream_t s)
 {
     for (int c0 = 0; c0 < n; c0 += kMaxBatch) {
         const int c = n - c0 < kMaxBatch ? n - c0 : kMaxBatch;
         int32_t rc;
         switch (items[0].mesh->N) {
-        case 1: rc = run_chunk<1, T>(items + c0, c, stage, phase, s); break;
-        case 2: rc = run_chunk<2, T>(items + c0, c, stage, phase, s); break;
-        case 3: rc = run_chunk<3, T>(items + c0, c, stage, phase, s); break;
-        case 4: rc = run_chunk<4, T>(items + c0, c, stage, phase, s); break;
-        case 5: rc = run_chunk<5, T>(items + c0, c, stage, phase, s); break;
-        case 6: rc = run_chunk<6, T>(items + c0, c, stage, phase, s); break;
-        case 7: rc = run_chunk<7, T>(items + c0, c, stage, phase, s); break;
-        default: rc = run_chunk<8, T>(items + c0, c, stage, phase, s); break;
+        case 1: rc = run_chunk<1, T>(items + c0, c, phase, s); break;
+        case 2: rc = run_chunk<2, T>(items + c0, c, phase, s); break;
+        case 3: rc = run_chunk<3, T>(items + c0, c, phase, s); break;
+        case 4: rc = run_chunk<4, T>(items + c0, c, phase, s); break;
+        case 5: rc = run_chunk<5, T>(items + c0, c, phase, s); break;
+        case 6: rc = run_chunk<6, T>(items + c0, c, phase, s); break;
+        case 7: rc = run_chunk<7, T>(items + c0, c, phase, s); break;
+        default: rc = run_chunk<8, T>(items + c0, c, phase, s); break;
         }
         if (rc) return rc;
     }
@@ -612,10 +615,10 @@ int32_t launch_box_plain_finish(const Mesh &m, const double *ev, double *q, hipS
     }
 }
 
-int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int32_t stage, int phase, hipStream_t s)
+int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int phase, hipStream_t s)
 {
-    if (prec == NUMA_PREC_MIXED) return run_stage_t<float>(items, n, stage, phase, s);
-    return run_stage_t<double>(items, n, stage, phase, s);
+    if (prec == NUMA_PREC_MIXED) return run_stage_t<float>(items, n, phase, s);
+    return run_stage_t<double>(items, n, phase, s);
 }
 
 }  // namespace numa

@@ -36,12 +36,12 @@ __global__ void k_dss(PointArgs p, int nvar, const double *cin, double *out, int
     }
 }
 
-__global__ void k_rk_stage(int64_t n, int stage, double dt, const double *qn, const double *qs,
-                           const double *r, double *qout)
+__global__ void k_rk_stage(int64_t n, StageCoef c, const double *qn, const double *qs, const double *r,
+                           double *qout)
 {
     int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= n) return;
-    qout[a] = rk_update(stage, stage == 0 ? 0.0 : qn[a], qs[a], dt, r[a]);
+    qout[a] = rk_update(c, c.a == 0.0 ? 0.0 : qn[a], qs[a], r[a]);
 }
 
 // Second half of a fused stage: DSS (mass-weighted), no-flux projection and
@@ -53,7 +53,7 @@ __global__ void k_rk_stage(int64_t n, int stage, double dt, const double *qn, co
 // qs or qn (one lane per node).
 template <typename T>
 __global__ void k_stage_finish(PointArgs p, const int32_t *own, const int32_t *toff, const int32_t *tidx,
-                               const T *ev, int stage, double dt, const double *qn, const double *qs, double *qout)
+                               const T *ev, StageCoef c, const double *qn, const double *qs, double *qout)
 {
     int64_t t = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (t >= p.nu) return;
@@ -71,7 +71,7 @@ __global__ void k_stage_finish(PointArgs p, const int32_t *own, const int32_t *t
     noflux(p, I, r[1], r[2], r[3]);
 #pragma unroll
     for (int v = 0; v < 5; ++v)
-        qout[v * p.nu + I] = rk_update(stage, stage == 0 ? 0.0 : qn[v * p.nu + I], qs[v * p.nu + I], dt, r[v]);
+        qout[v * p.nu + I] = rk_update(c, c.a == 0.0 ? 0.0 : qn[v * p.nu + I], qs[v * p.nu + I], r[v]);
 }
 
 // Finish of a fused stage on the shell: one lane per unique node in unique
@@ -90,7 +90,7 @@ struct ShellFin {
 };
 
 template <int N, typename T, bool PLAIN = false>
-__global__ void k_shell_finish(PointArgs p, ShellFin sf, const T *ev, int stage, double dt, const double *qn,
+__global__ void k_shell_finish(PointArgs p, ShellFin sf, const T *ev, StageCoef c, const double *qn,
                                const double *qs, double *qout)
 {
     constexpr int P = N + 1, PP = P * P;
@@ -106,7 +106,7 @@ __global__ void k_shell_finish(PointArgs p, ShellFin sf, const T *ev, int stage,
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             qsv[v] = qsi[v * p.nu];
-            qnv[v] = stage == 0 ? 0.0 : qni[v * p.nu];
+            qnv[v] = c.a == 0.0 ? 0.0 : qni[v * p.nu];
         }
     // radial copies: (layer, local k)
     int ez[2], kz[2], nzc = 1;
@@ -147,13 +147,13 @@ __global__ void k_shell_finish(PointArgs p, ShellFin sf, const T *ev, int stage,
     noflux(p, I, r[1], r[2], r[3]);
     double *qoi = qout + I;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) qoi[v * p.nu] = PLAIN ? r[v] : rk_update(stage, qnv[v], qsv[v], dt, r[v]);
+    for (int v = 0; v < 5; ++v) qoi[v * p.nu] = PLAIN ? r[v] : rk_update(c, qnv[v], qsv[v], r[v]);
 }
 
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 template <typename T, bool PLAIN = false>
-void launch_shell_finish_t(Mesh &m, const T *ev, int32_t stage, double dt, const double *qn, const double *qs,
+void launch_shell_finish_t(Mesh &m, const T *ev, const StageCoef &c, const double *qn, const double *qs,
                            double *qout, hipStream_t s)
 {
     ShellFin sf;
@@ -164,14 +164,14 @@ void launch_shell_finish_t(Mesh &m, const T *ev, int32_t stage, double dt, const
     sf.layer = 6 * (int64_t)m.d.ne[0] * m.d.ne[0] * m.np;
     const dim3 grid(nblocks(m.nu, 256)), block(256);
     switch (m.N) {
-    case 1: hipLaunchKernelGGL((k_shell_finish<1, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
-    case 2: hipLaunchKernelGGL((k_shell_finish<2, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
-    case 3: hipLaunchKernelGGL((k_shell_finish<3, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
-    case 4: hipLaunchKernelGGL((k_shell_finish<4, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
-    case 5: hipLaunchKernelGGL((k_shell_finish<5, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
-    case 6: hipLaunchKernelGGL((k_shell_finish<6, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
-    case 7: hipLaunchKernelGGL((k_shell_finish<7, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
-    default: hipLaunchKernelGGL((k_shell_finish<8, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, stage, dt, qn, qs, qout); break;
+    case 1: hipLaunchKernelGGL((k_shell_finish<1, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, qn, qs, qout); break;
+    case 2: hipLaunchKernelGGL((k_shell_finish<2, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, qn, qs, qout); break;
+    case 3: hipLaunchKernelGGL((k_shell_finish<3, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, qn, qs, qout); break;
+    case 4: hipLaunchKernelGGL((k_shell_finish<4, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, qn, qs, qout); break;
+    case 5: hipLaunchKernelGGL((k_shell_finish<5, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, qn, qs, qout); break;
+    case 6: hipLaunchKernelGGL((k_shell_finish<6, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, qn, qs, qout); break;
+    case 7: hipLaunchKernelGGL((k_shell_finish<7, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, qn, qs, qout); break;
+    default: hipLaunchKernelGGL((k_shell_finish<8, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, qn, qs, qout); break;
     }
 }
 
@@ -184,39 +184,47 @@ int32_t launch_dss(Mesh &m, int32_t nvar, const double *cin, double *out, int32_
     return NUMA_OK;
 }
 
+StageCoef ssp33_stage(int stage, double dt)
+{
+    if (stage == 0) return StageCoef{0.0, 1.0, dt};
+    if (stage == 1) return StageCoef{0.75, 0.25, dt};
+    return StageCoef{1.0 / 3.0, 2.0 / 3.0, dt};
+}
+
 int32_t launch_rk_stage(Mesh &m, int32_t stage, double dt, const double *qn, const double *qs, const double *r,
                         double *qout, hipStream_t s)
 {
     int64_t n = 5 * m.nu;
-    hipLaunchKernelGGL(k_rk_stage, dim3(nblocks(n, 256)), dim3(256), 0, s, n, stage, dt, qn, qs, r, qout);
+    hipLaunchKernelGGL(k_rk_stage, dim3(nblocks(n, 256)), dim3(256), 0, s, n, ssp33_stage(stage, dt), qn, qs, r,
+                       qout);
     NUMA_HIP(hipGetLastError());
     return NUMA_OK;
 }
 
 int32_t launch_shell_plain_finish(Mesh &m, const double *ev, double *q, hipStream_t s)
 {
-    launch_shell_finish_t<double, true>(m, ev, 0, 0.0, nullptr, nullptr, q, s);
+    launch_shell_finish_t<double, true>(m, ev, StageCoef{0.0, 1.0, 0.0}, nullptr, nullptr, q, s);
     NUMA_HIP(hipGetLastError());
     return NUMA_OK;
 }
 
-int32_t launch_stage_finish(Mesh &m, int32_t prec, int32_t stage, double dt, const double *qn, const double *qs,
+int32_t launch_stage_finish(Mesh &m, int32_t prec, const StageCoef &c, const double *qn, const double *qs,
                             double *qout, hipStream_t s)
 {
     if (m.d.kind == NUMA_MESH_SHELL) {  // node-major contributions (launch_stage_elements)
         if (prec == NUMA_PREC_MIXED)
-            launch_shell_finish_t<float>(m, m.dv.ev32, stage, dt, qn, qs, qout, s);
+            launch_shell_finish_t<float>(m, m.dv.ev32, c, qn, qs, qout, s);
         else
-            launch_shell_finish_t<double>(m, m.dv.ev64, stage, dt, qn, qs, qout, s);
+            launch_shell_finish_t<double>(m, m.dv.ev64, c, qn, qs, qout, s);
         NUMA_HIP(hipGetLastError());
         return NUMA_OK;
     }
     if (prec == NUMA_PREC_MIXED)
         hipLaunchKernelGGL(k_stage_finish<float>, dim3(nblocks(m.nu, 256)), dim3(256), 0, s, point_args(m), m.dv.own,
-                           m.dv.toff, m.dv.tidx, m.dv.ev32, stage, dt, qn, qs, qout);
+                           m.dv.toff, m.dv.tidx, m.dv.ev32, c, qn, qs, qout);
     else
         hipLaunchKernelGGL(k_stage_finish<double>, dim3(nblocks(m.nu, 256)), dim3(256), 0, s, point_args(m), m.dv.own,
-                           m.dv.toff, m.dv.tidx, m.dv.ev64, stage, dt, qn, qs, qout);
+                           m.dv.toff, m.dv.tidx, m.dv.ev64, c, qn, qs, qout);
     NUMA_HIP(hipGetLastError());
     return NUMA_OK;
 }

@@ -398,16 +398,15 @@ __device__ inline void noflux(const PointArgs &p, int64_t I, double &r1, double 
     r3 -= dn * n2;
 }
 
-// SSP-RK3 stage update (Shu-Osher form): y = q_s + dt R, then
-// q_out = a q^n + b y with (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3).  The
-// contractions are written out (fma) so that every kernel that updates a
-// state rounds it the same way.
-__device__ inline double rk_update(int stage, double qn, double qs, double dt, double r)
+// Runge-Kutta stage update (Shu-Osher form, StageCoef): y = q_s + cdt R, then
+// q_out = a q_ref + b y (y itself when a = 0 and b = 1).  The contractions are
+// written out (fma) so that every kernel that updates a state rounds it the
+// same way.
+__device__ inline double rk_update(const StageCoef &c, double qref, double qs, double r)
 {
-    const double y = fma(dt, r, qs);
-    if (stage == 0) return y;
-    if (stage == 1) return fma(0.25, y, 0.75 * qn);
-    return fma(2.0 / 3.0, y, (1.0 / 3.0) * qn);
+    const double y = fma(c.cdt, r, qs);
+    if (c.a == 0.0 && c.b == 1.0) return y;
+    return fma(c.b, y, c.a * qref);
 }
 
 // Finish of a fused stage on the box.  A block takes SEG consecutive elements
@@ -428,7 +427,7 @@ struct BoxFin {
 
 template <int N, int SEG, typename T, bool PLAIN = false>
 __device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin &b, const T *ev, int sx, int ey,
-                                                int ez, int lane, int kbase, int klayers, int stage, double dt,
+                                                int ez, int lane, int kbase, int klayers, const StageCoef &sc,
                                                 const double *qn, const double *qs, double *qout)
 {
     constexpr int P = N + 1, NP = P * P * P, W = SEG * N;
@@ -477,7 +476,7 @@ __device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
             qsv[v] = qsi[v * p.nu];
-            qnv[v] = stage == 0 ? 0.0 : qni[v * p.nu];
+            qnv[v] = sc.a == 0.0 ? 0.0 : qni[v * p.nu];
         }
     // copies of one z layer: the up to four (y, x) copies are loaded together
     // (absent ones re-read the first copy and count zero), so a node waits
@@ -510,7 +509,7 @@ __device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin
     for (int v = 0; v < 5; ++v) r[v] *= mi;
     noflux(p, I, r[1], r[2], r[3]);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) qoi[v * p.nu] = PLAIN ? r[v] : rk_update(stage, qnv[v], qsv[v], dt, r[v]);
+    for (int v = 0; v < 5; ++v) qoi[v * p.nu] = PLAIN ? r[v] : rk_update(sc, qnv[v], qsv[v], r[v]);
 }
 
 // Copy n values staged in LDS (st) to out with 16-byte stores: the leading values until out is 16-byte aligned one by one, then

@@ -306,6 +306,7 @@ uint64_t layout_workspace(Mesh &m, int32_t prec_mask, char *base)
     v.ev64 = (double *)take(40ull * m.nl);
     if (prec_mask & 2) v.ev32 = (float *)take(20ull * m.nl);
     v.qs = (double *)take(40ull * m.nu);
+    v.qs2 = (double *)take(40ull * m.nu);
     v.D64 = (double *)take(8ull * kMaxP * kMaxP);
     v.D32 = (float *)take(4ull * kMaxP * kMaxP);
     v.xi64 = (double *)take(8ull * kMaxP);

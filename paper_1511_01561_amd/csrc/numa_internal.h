@@ -94,6 +94,7 @@ struct DeviceView {
     double *ev64 = nullptr;    // [5][n_local] element contributions of a fused stage, FP64 path
     float *ev32 = nullptr;     // same, mixed path
     double *qs = nullptr;      // [5][n_unique] stage state scratch
+    double *qs2 = nullptr;     // [5][n_unique] second stage state (SSP-RK(5,3) keeps u_2)
     double *D64 = nullptr;     // [(N+1)^2] derivative matrix
     double *xi64 = nullptr;    // [N+1] GLL nodes
     double *w64 = nullptr;     // [N+1] GLL weights
@@ -123,6 +124,7 @@ struct Mesh {
     DeviceView dv;
     bool uploaded = false, geom = false;
     int metric_mode = 0;  // NUMA_METRIC_STORED or NUMA_METRIC_RECOMPUTE (box)
+    int integrator = 0;         // NUMA_RK_SSP33 or NUMA_RK_SSP53
     bool filter_on = false;     // numa_step applies the filter after every step
     double filter_order = 0.0;  // Boyd-Vandeven order p
     int filter_cutoff = 0;      // modes 0..cutoff pass unchanged
@@ -150,25 +152,33 @@ void filter_matrix(int N, const double *xi, const double *w, double order, int32
 int32_t launch_filter(Mesh &m, double order, int32_t cutoff, double *q, hipStream_t s);
 int32_t launch_box_plain_finish(const Mesh &m, const double *ev, double *q, hipStream_t s);
 int32_t launch_shell_plain_finish(Mesh &m, const double *ev, double *q, hipStream_t s);
+// The update of one Runge-Kutta stage in Shu-Osher form, written as
+// q_out = a q_ref + b (q_s + cdt R): a is the weight of the reference state
+// (q^n or an earlier stage; not read when a = 0), b the weight of the stage
+// the right-hand side R was taken from, cdt = (beta / b) dt.
+struct StageCoef {
+    double a, b, cdt;
+};
+StageCoef ssp33_stage(int stage, double dt);
+
 int32_t launch_rk_stage(Mesh &m, int32_t stage, double dt, const double *qn, const double *qs,
                         const double *r, double *qout, hipStream_t s);
 // One solve of a batch at one stage: states and the E-vector scratch.
 struct StepItem {
     const Mesh *mesh;
-    const double *qn, *qs;
+    const double *qn, *qs;   // qn: the stage's reference state
     double *qout;
     void *ev;
-    double dt;
+    StageCoef c;
 };
 
 // Box meshes whose x extent fits the finish block's segment take the batched
 // kernels; phase 0 launches the element kernels, phase 1 the finish kernels.
 bool box_batchable(const Mesh &m);
-int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int32_t stage, int phase, hipStream_t s);
+int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int phase, hipStream_t s);
 
-int32_t launch_stage_elements(Mesh &m, int32_t prec, int32_t stage, double dt, const double *qn, const double *qs,
-                              double *qout, hipStream_t s);
-int32_t launch_stage_finish(Mesh &m, int32_t prec, int32_t stage, double dt, const double *qn, const double *qs,
+int32_t launch_stage_elements(Mesh &m, int32_t prec, const double *qs, hipStream_t s);
+int32_t launch_stage_finish(Mesh &m, int32_t prec, const StageCoef &c, const double *qn, const double *qs,
                             double *qout, hipStream_t s);
 
 }  // namespace numa

@@ -139,8 +139,7 @@ int32_t launch_rhs(Mesh &m, int32_t prec, const double *q, double *evec, hipStre
 
 // element half of a fused stage: contributions into the workspace E-vector
 // (FP32 on the mixed path)
-int32_t launch_stage_elements(Mesh &m, int32_t prec, int32_t, double, const double *, const double *qs, double *,
-                              hipStream_t s)
+int32_t launch_stage_elements(Mesh &m, int32_t prec, const double *qs, hipStream_t s)
 {
     // the shell's finish reads node-major contributions, the generic one element-major
     const bool nm = m.d.kind == NUMA_MESH_SHELL;

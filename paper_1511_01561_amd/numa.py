@@ -18,6 +18,7 @@ MESH_BOX, MESH_SHELL = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 DSS_MASS, DSS_NOFLUX = 1, 2
 METRIC_STORED, METRIC_RECOMPUTE = 0, 1
+RK_SSP33, RK_SSP53 = 0, 1
 FIELD_MASS, FIELD_REF, FIELD_COORDS, FIELD_METRIC, FIELD_GRAVITY, FIELD_LOCAL_COORDS = range(6)
 
 EXPORTED = ["numa_last_error", "numa_gll", "numa_mesh_create", "numa_mesh_destroy", "numa_mesh_info",
@@ -25,7 +26,8 @@ EXPORTED = ["numa_last_error", "numa_gll", "numa_mesh_create", "numa_mesh_destro
             "numa_geometry", "numa_export", "numa_init_state", "numa_rhs", "numa_dss",
             "numa_rk_stage", "numa_step", "numa_profile", "numa_profile_read", "numa_step_scratch_bytes",
             "numa_step_batch", "numa_batch_capture", "numa_graph_launch", "numa_graph_destroy",
-            "numa_mesh_set_metric", "numa_filter", "numa_filter_matrix", "numa_mesh_set_filter"]
+            "numa_mesh_set_metric", "numa_filter", "numa_filter_matrix", "numa_mesh_set_filter",
+            "numa_mesh_set_integrator"]
 
 
 class numa_mesh_desc(ct.Structure):
@@ -44,7 +46,8 @@ class numa_ic(ct.Structure):
 
 
 class numa_batch_item(ct.Structure):
-    _fields_ = [("mesh", ct.c_void_p), ("q", ct.c_void_p), ("scratch", ct.c_void_p), ("dt", ct.c_double)]
+    _fields_ = [("mesh", ct.c_void_p), ("q", ct.c_void_p), ("scratch", ct.c_void_p), ("scratch_bytes", ct.c_uint64),
+                ("dt", ct.c_double)]
 
 
 class NumaError(RuntimeError):
@@ -82,6 +85,7 @@ def lib():
         "numa_filter": (I32, [P, D, I32, P, P]),
         "numa_filter_matrix": (I32, [I32, D, I32, P]),
         "numa_mesh_set_filter": (I32, [P, I32, D, I32]),
+        "numa_mesh_set_integrator": (I32, [P, I32]),
         "numa_step": (I32, [P, I32, D, I32, P, P]),
         "numa_profile": (I32, [P, I32]),
         "numa_profile_read": (I32, [P, P]),
@@ -224,6 +228,10 @@ class Mesh:
         check(lib().numa_filter(self._h, float(filter_order), int(cutoff), _ptr(q), _stream(stream)))
         return q
 
+    def set_integrator(self, integrator: int):
+        """RK_SSP33 (default) or RK_SSP53 for step() and the batched steps."""
+        check(lib().numa_mesh_set_integrator(self._h, int(integrator)))
+
     def set_filter(self, filter_order=None, cutoff=0):
         """Filter after every step of step() and the batched steps (None: off)."""
         on = filter_order is not None
@@ -250,7 +258,7 @@ class Mesh:
         return tuple(out)
 
     def step(self, q, dt, nsteps, prec=PREC_FP64, stream=None):
-        """nsteps SSP-RK3 steps in place on q (device [5][n_unique] FP64)."""
+        """nsteps steps of the mesh's integrator in place on q (device [5][n_unique] FP64)."""
         check(lib().numa_step(self._h, prec, float(dt), int(nsteps), _ptr(q), _stream(stream)))
         return q
 
@@ -277,13 +285,14 @@ def _items(items):
         arr[k].mesh = m._h.value if isinstance(m._h, ct.c_void_p) else m._h
         arr[k].q = q.data_ptr()
         arr[k].scratch = scr.data_ptr()
+        arr[k].scratch_bytes = scr.numel() * scr.element_size()
         arr[k].dt = float(dt)
     return arr
 
 
 def step_batch(items, nsteps: int, prec: int = PREC_FP64, stream=None):
-    """Advance every (mesh, q, scratch, dt) item by nsteps SSP-RK3 steps in
-    batched launches (same order, box meshes)."""
+    """Advance every (mesh, q, scratch, dt) item by nsteps steps in batched
+    launches (same order, metric mode and integrator, box meshes)."""
     arr = _items(items)
     check(lib().numa_step_batch(arr, len(items), prec, int(nsteps), _stream(stream)))
 

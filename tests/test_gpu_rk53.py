@@ -1,0 +1,175 @@
+"""The five-stage third-order SSP Runge-Kutta integrator (NUMA_RK_SSP53)
+against the oracle's SSP-RK(5,3) step: FP64 states within 1e-12 relative
+max-norm per variable group, mixed precision within 1e-4 of the increment;
+batched and graph-replayed steps bitwise equal to the same steps alone."""
+import numpy as np
+import pytest
+
+from paper_1511_01561_amd import inputs
+from test_gpu_parity import TOL64, Pair, assert_groups, group_err, small_shell
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def terrain_box(N, ne=(4, 3, 3), perz=False):
+    return inputs.box_workload(*ne, N, 12e3, 9e3, 6e3, terrain=400.0, bubble_centre=(6e3, 4.5e3, 2e3),
+                               bubble_radius=2.5e3, periodic_z=perz)
+
+
+def rk53_pair(wl, oracle_mod, metric=0):
+    from paper_1511_01561_amd import numa
+    p = Pair(wl, oracle_mod)
+    p.g.set_metric(metric)
+    p.g.set_integrator(numa.RK_SSP53)
+    return p
+
+
+@pytest.mark.parametrize("metric", [0, 1])
+@pytest.mark.parametrize("N", range(1, 9))
+def test_rk53_step_parity_all_orders(torch_cuda, oracle_mod, N, metric):
+    p = rk53_pair(terrain_box(N), oracle_mod, metric)
+    q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 20 + N))
+    qo = p.o.step(q0, 0.05, 3, scheme="ssp53")
+    qg = p.dev(q0)
+    p.g.step(qg, 0.05, 3)
+    assert_groups(p.host(qg), qo, TOL64, "ssp53 N=%d metric=%d" % (N, metric))
+
+
+@pytest.mark.parametrize("which", ["generic", "periodic_z", "shell"])
+def test_rk53_step_parity_other_paths(torch_cuda, oracle_mod, which):
+    """The general stage kernels (box whose x extent the finish segment does not
+    divide, and the shell) and a box periodic in z."""
+    wl = {"generic": terrain_box(4, ne=(5, 3, 2)), "periodic_z": terrain_box(3, perz=True),
+          "shell": small_shell(4)}[which]
+    p = rk53_pair(wl, oracle_mod)
+    q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 30) if which != "shell" else None)
+    dt = 0.5 if which == "shell" else 0.05
+    qo = p.o.step(q0, dt, 3, scheme="ssp53")
+    qg = p.dev(q0)
+    p.g.step(qg, dt, 3)
+    assert_groups(p.host(qg), qo, TOL64, "ssp53 %s" % which)
+
+
+@pytest.mark.parametrize("N", [3, 4, 6])
+def test_rk53_mixed_precision(torch_cuda, oracle_mod, N):
+    from paper_1511_01561_amd import numa
+    p = rk53_pair(terrain_box(N), oracle_mod, metric=1)
+    q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 40 + N))
+    qo = p.o.step(q0, 0.05, 2, scheme="ssp53")
+    qg = p.dev(q0)
+    p.g.step(qg, 0.05, 2, prec=numa.PREC_MIXED)
+    e = group_err(p.host(qg) - q0, qo - q0)
+    print("ssp53 mixed N=%d increment" % N, {k: "%.1e" % v for k, v in e.items()}, flush=True)
+    assert max(e.values()) <= 1e-4
+
+
+def test_rk53_differs_from_rk3_by_third_order_terms(torch_cuda, oracle_mod):
+    """Both integrators through the library: their difference after a fixed
+    time falls about 8x when dt halves (both third order)."""
+    from paper_1511_01561_amd import numa
+    p = Pair(inputs.small_box(), oracle_mod)
+    q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 0))
+    d = []
+    for dt, n in ((0.4, 4), (0.2, 8), (0.1, 16)):
+        a, b = p.dev(q0), p.dev(q0)
+        p.g.set_integrator(numa.RK_SSP53)
+        p.g.step(a, dt, n)
+        p.g.set_integrator(numa.RK_SSP33)
+        p.g.step(b, dt, n)
+        d.append(np.abs(p.host(a)[4] - p.host(b)[4]).max())
+    rates = np.log2(np.array(d[:-1]) / np.array(d[1:]))
+    print("ssp53 - ssp33 differences", d, rates, flush=True)
+    assert np.all((rates > 2.6) & (rates < 3.4))
+
+
+def test_rk53_with_filter(torch_cuda, oracle_mod):
+    p = rk53_pair(terrain_box(4), oracle_mod, metric=1)
+    q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 50))
+    qo = q0.copy()
+    for _ in range(2):
+        qo = p.o.filter(p.o.step(qo, 0.05, 1, scheme="ssp53"), 16.0, 1)
+    p.g.set_filter(16.0, 1)
+    qg = p.dev(q0)
+    p.g.step(qg, 0.05, 2)
+    assert_groups(p.host(qg), qo, TOL64, "ssp53 + filter")
+
+
+def _box_item(n, N, nz):
+    Lx, H = n * 6250.0, nz * 1250.0
+    return inputs.box_workload(n, n, nz, N, Lx, Lx, H, terrain=500.0, bubble_centre=(Lx / 3, Lx / 2, H / 2))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_rk53_batch_equals_alone_bitwise(torch_cuda, prec):
+    from paper_1511_01561_amd import numa
+    torch = torch_cuda
+    wls = [_box_item(8, 4, 4), _box_item(4, 4, 3), _box_item(12, 4, 2)]
+    gs = [numa.Mesh(wl["mesh"], wl["phys"], prec_mask=3) for wl in wls]
+    for g in gs:
+        g.set_metric(numa.METRIC_RECOMPUTE)
+        g.set_integrator(numa.RK_SSP53)
+    qs = [g.init_state(wl["ic"], inputs.device_noise(g.n_unique, 60 + k)) for k, (g, wl) in enumerate(zip(gs, wls))]
+    ref = [q.clone() for q in qs]
+    numa.step_batch([(g, q, numa.alloc_scratch(g, prec), 0.05) for g, q in zip(gs, qs)], 3, prec)
+    for g, r in zip(gs, ref):
+        g.step(r, 0.05, 3, prec=prec)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(qs, ref))
+
+
+def test_rk53_graph_replays_match_eager(torch_cuda):
+    from paper_1511_01561_amd import numa
+    torch = torch_cuda
+    wl = _box_item(8, 4, 4)
+    g = numa.Mesh(wl["mesh"], wl["phys"], prec_mask=1)
+    g.set_integrator(numa.RK_SSP53)
+    q = g.init_state(wl["ic"], inputs.device_noise(g.n_unique, 70))
+    e = q.clone()
+    s = torch.cuda.Stream()
+    sg, se = numa.alloc_scratch(g, 0), numa.alloc_scratch(g, 0)
+    graph = numa.Graph([(g, q, sg, 0.05)], 2, 0, s)
+    for rep in range(3):
+        graph.launch(s)
+        s.synchronize()
+        numa.step_batch([(g, e, se, 0.05)], 2, 0)
+        junk = torch.randn(1 << 18, device="cuda", dtype=torch.float64).sum()
+        torch.cuda.synchronize()
+        assert torch.equal(q, e), rep
+    graph.close()
+    del junk
+
+
+def test_rk53_batch_refuses_short_scratch_and_mixed_integrators(torch_cuda):
+    from paper_1511_01561_amd import numa
+    wl = _box_item(4, 3, 2)
+    g = numa.Mesh(wl["mesh"], wl["phys"], prec_mask=1)
+    h = numa.Mesh(wl["mesh"], wl["phys"], prec_mask=1)
+    q = g.init_state(wl["ic"], None)
+    r = h.init_state(wl["ic"], None)
+    short = numa.alloc_scratch(g, 0)                 # sized for SSP-RK3
+    g.set_integrator(numa.RK_SSP53)
+    before = q.clone()
+    with pytest.raises(numa.NumaError, match="scratch"):
+        numa.step_batch([(g, q, short, 0.05)], 1, 0)
+    with pytest.raises(numa.NumaError, match="integrator"):
+        numa.step_batch([(g, q, numa.alloc_scratch(g, 0), 0.05), (h, r, numa.alloc_scratch(h, 0), 0.05)], 1, 0)
+    torch_cuda.cuda.synchronize()
+    assert torch_cuda.equal(q, before)
+
+
+def test_rk53_full_size(torch_cuda, oracle_mod):
+    """64 x 64 x 16 elements, N = 4, recomputed metric: two SSP-RK(5,3) steps."""
+    p = rk53_pair(inputs.gpu_box(), oracle_mod, metric=1)
+    q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 0))
+    qo = p.o.step(q0, 0.05, 2, scheme="ssp53")
+    qg = p.dev(q0)
+    p.g.step(qg, 0.05, 2)
+    assert_groups(p.host(qg), qo, TOL64, "full-size ssp53")

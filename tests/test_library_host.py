@@ -227,3 +227,21 @@ def test_set_filter_validates_on_the_host(L):
         assert L.numa_mesh_set_filter(None, 0, 0.0, 0) == -1
     finally:
         L.numa_mesh_destroy(h)
+
+
+def test_integrator_setting_and_scratch_size(L):
+    rc, h = _create(MESHES[0])
+    assert rc == 0
+    try:
+        a, b = ct.c_uint64(), ct.c_uint64()
+        assert L.numa_step_scratch_bytes(h, 0, ct.byref(a)) == 0
+        assert L.numa_mesh_set_integrator(h, numa.RK_SSP53) == 0
+        assert L.numa_step_scratch_bytes(h, 0, ct.byref(b)) == 0
+        nu = ct.c_int64()
+        assert L.numa_mesh_info(h, None, None, ct.byref(nu), None, None) == 0
+        assert b.value - a.value == (40 * nu.value + 255) // 256 * 256    # the second stage state
+        assert L.numa_mesh_set_integrator(h, 2) == -1 and L.numa_mesh_set_integrator(h, -1) == -1
+        assert L.numa_mesh_set_integrator(None, 0) == -1
+        assert L.numa_mesh_set_integrator(h, numa.RK_SSP33) == 0
+    finally:
+        L.numa_mesh_destroy(h)
