@@ -75,6 +75,8 @@ def lib():
         L.or_rk53_coeffs.argtypes = [P, P]
         L.or_rk53_combine.argtypes = [ct.c_int64, ct.c_int, ct.c_double, P, P, P]
         L.or_step_rk53.argtypes = [P, ct.c_double, ct.c_int, P]
+        L.or_imex_V.argtypes = [P, P, P]
+        L.or_imex_step.argtypes = [P, ct.c_double, ct.c_double, ct.c_int, P, P, P, ct.c_int]
         _lib = L
     return _lib
 
@@ -219,6 +221,25 @@ class OracleMesh:
         if rc != 0:
             raise ValueError("oracle filter (%d)" % rc)
         return q
+
+    def imex_V(self, q: np.ndarray) -> np.ndarray:
+        """The vertical linear operator of the 1D-IMEX correction."""
+        q = np.ascontiguousarray(q, dtype=np.float64).reshape(5, self.n_unique)
+        out = np.zeros((5, self.n_unique))
+        if lib().or_imex_V(self._h, _p(q), _p(out)) != 0:
+            raise MemoryError("oracle imex_V")
+        return out
+
+    def imex_step(self, qprev, qcur, dt: float, ra: float, nsteps: int, lines=None):
+        """nsteps 1D-IMEX leap-frog steps; returns the new (qprev, qcur)."""
+        a = np.array(qprev, dtype=np.float64, copy=True).reshape(5, self.n_unique)
+        b = np.array(qcur, dtype=np.float64, copy=True).reshape(5, self.n_unique)
+        ln = None if lines is None else np.ascontiguousarray(lines, dtype=np.int32)
+        rc = lib().or_imex_step(self._h, float(dt), float(ra), int(nsteps), _p(a), _p(b),
+                                None if ln is None else _p(ln), 0 if ln is None else len(ln))
+        if rc != 0:
+            raise ValueError("oracle imex step (%d)" % rc)
+        return a, b
 
     def step(self, q: np.ndarray, dt: float, nsteps: int, scheme: str = "ssp33") -> np.ndarray:
         """nsteps steps of SSP-RK3 (scheme "ssp33") or SSP-RK(5,3) ("ssp53")."""

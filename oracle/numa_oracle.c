@@ -927,6 +927,196 @@ int or_step_rk53(const or_ctx *C, double dt, int nsteps, double *q)
 }
 
 /*
+ * 1D-IMEX (Sec. "Time Discretization"; Code example 1: "compute IMEX
+ * corrections for each vertical column of grid points").  The paper makes
+ * implicit corrections along the vertical columns after an explicit leap-frog
+ * step and refers the scheme to another paper.  Reading (box with no-flux
+ * walls only):
+ *   V(q) is the linearisation about the hydrostatic reference of the terms
+ *   that carry vertically propagating sound and gravity:
+ *     V_rho'  = -d(rho_bar w)/dz,
+ *     V_w     = -(1/rho_bar) dp_L/dz + g_z rho'/rho_bar,
+ *                p_L = (gamma p_bar / rho_bar) (rho' + rho_bar theta'/theta_bar),
+ *     V_theta' = -w dtheta_bar/dz,   V_u = V_v = 0,
+ *   discretised like create_rhs (element-local derivatives through the metric,
+ *   J w weighting, DSS and M^-1), the momentum rows set to zero at the walls
+ *   (the wall velocity is that of the explicit step);
+ *   a step is the leap-frog step with V taken as the trapezoidal mean of the
+ *   new and the old level:
+ *     q* = q^{n-1} + 2 dt L(q^n)                     (explicit leap-frog)
+ *     (I - dt V) q^{n+1} = q* - dt V(2 q^n - q^{n-1})  (vertical correction)
+ *   followed by the Robert-Asselin filter with coefficient ra:
+ *     q^n <- q^n + ra (q^{n-1} - 2 q^n + q^{n+1}).
+ * V couples only the nodes of one vertical lattice line (x = x(xi), y = y(eta)
+ * in the terrain-following map: d/dz acts along zeta), so the correction is one
+ * linear solve per line.
+ */
+int or_imex_V(const or_ctx *C, const double *q, double *out)
+{
+    int P = C->P, np = C->np;
+    int64_t nu = C->nu, nl = C->nl;
+    double cv = C->ph.cp - C->ph.R, gamma = C->ph.cp / cv;
+    double *cbuf = (double *)malloc(sizeof(double) * 5 * nl);
+    if (!cbuf) return -2;
+#pragma omp parallel for
+    for (int64_t e = 0; e < C->ne; e++) {
+        double F[3][OR_MAXP * OR_MAXP * OR_MAXP];
+        for (int l = 0; l < np; l++) {
+            int64_t I = C->G[e * np + l];
+            double rb = C->ref[I], tb = C->ref[nu + I], pb = C->ref[2 * nu + I];
+            F[0][l] = rb * q[3 * nu + I];
+            F[1][l] = gamma * pb / rb * (q[I] + rb * q[4 * nu + I] / tb);
+            F[2][l] = tb;
+        }
+        for (int k = 0; k < P; k++)
+            for (int j = 0; j < P; j++)
+                for (int i = 0; i < P; i++) {
+                    int l = i + P * (j + P * k);
+                    int64_t g = e * np + l, I = C->G[g];
+                    double dz[3];
+                    for (int f = 0; f < 3; f++) {
+                        double a = 0.0, b = 0.0, c = 0.0;
+                        for (int m = 0; m < P; m++) {
+                            a += C->D[i * P + m] * F[f][m + P * (j + P * k)];
+                            b += C->D[j * P + m] * F[f][i + P * (m + P * k)];
+                            c += C->D[k * P + m] * F[f][i + P * (j + P * m)];
+                        }
+                        dz[f] = a * C->met[2 * nl + g] + b * C->met[5 * nl + g] + c * C->met[8 * nl + g];
+                    }
+                    double rb = C->ref[I];
+                    double V[5];
+                    V[0] = -dz[0];
+                    V[1] = 0.0;
+                    V[2] = 0.0;
+                    V[3] = -dz[1] / rb + C->grav[2 * nu + I] * q[I] / rb;
+                    V[4] = -q[3 * nu + I] * dz[2];
+                    double Jw = C->met[9 * nl + g];
+                    for (int s = 0; s < 5; s++) cbuf[s * nl + g] = Jw * V[s];
+                }
+    }
+    or_dss(C, 5, cbuf, 1, out);
+    for (int64_t I = 0; I < nu; I++)
+        if (C->isbnd[I]) out[nu + I] = out[2 * nu + I] = out[3 * nu + I] = 0.0;
+    free(cbuf);
+    return 0;
+}
+
+/* Solve A x = b (n x n, row-major, overwritten) by Gaussian elimination with
+ * partial pivoting. */
+static int dense_solve(int n, double *A, double *b, double *x)
+{
+    for (int c = 0; c < n; c++) {
+        int piv = c;
+        for (int r = c + 1; r < n; r++)
+            if (fabs(A[r * n + c]) > fabs(A[piv * n + c])) piv = r;
+        if (A[piv * n + c] == 0.0) return -1;
+        if (piv != c) {
+            for (int k = 0; k < n; k++) {
+                double t = A[c * n + k];
+                A[c * n + k] = A[piv * n + k];
+                A[piv * n + k] = t;
+            }
+            double t = b[c];
+            b[c] = b[piv];
+            b[piv] = t;
+        }
+        for (int r = c + 1; r < n; r++) {
+            double f = A[r * n + c] / A[c * n + c];
+            if (f == 0.0) continue;
+            for (int k = c; k < n; k++) A[r * n + k] -= f * A[c * n + k];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = n - 1; r >= 0; r--) {
+        double s = b[r];
+        for (int k = r + 1; k < n; k++) s -= A[r * n + k] * x[k];
+        x[r] = s / A[r * n + r];
+    }
+    return 0;
+}
+
+/* the components V acts on, in the order of a line's unknowns */
+static const int IMEX_COMP[3] = {0, 3, 4};
+
+/*
+ * nsteps 1D-IMEX leap-frog steps on the pair (q^{n-1}, q^n) in place (after
+ * the call qprev holds the filtered last-but-one level and qcur the newest).
+ * lines: the vertical lattice lines (gi + ni gj) whose correction is solved,
+ * or NULL for all; the rho', w, theta' of other lines are set to NaN.  The
+ * matrix of V on a line is probed with unit states (one at the same level
+ * and component on every line at once) and each line's system, unknowns
+ * (rho', w, theta') at its levels, is solved densely.
+ */
+int or_imex_step(const or_ctx *C, double dt, double ra, int nsteps, double *qprev, double *qcur,
+                 const int32_t *lines, int nlines)
+{
+    if (C->m.kind != 0 || C->m.periodic[2]) return -3;
+    int64_t nu = C->nu, nh = C->nh, nk = C->nk, n5 = 5 * nu;
+    int nline = lines ? nlines : (int)nh;
+    int nx = 3 * (int)nk;
+    double *Vl = (double *)malloc(sizeof(double) * (size_t)nline * nx * nx);
+    double *E = (double *)calloc(n5, sizeof(double));
+    double *VE = (double *)malloc(sizeof(double) * n5);
+    double *cbuf = (double *)malloc(sizeof(double) * 5 * C->nl);
+    double *R = (double *)malloc(sizeof(double) * n5);
+    double *r = (double *)malloc(sizeof(double) * n5);
+    double *sv = (double *)malloc(sizeof(double) * n5);
+    double *qn1 = (double *)malloc(sizeof(double) * n5);
+    if (!Vl || !E || !VE || !cbuf || !R || !r || !sv || !qn1) {
+        free(Vl); free(E); free(VE); free(cbuf); free(R); free(r); free(sv); free(qn1);
+        return -2;
+    }
+    /* column (c, gk) of every line's matrix of V */
+    for (int c = 0; c < 3; c++)
+        for (int64_t gk = 0; gk < nk; gk++) {
+            for (int64_t L = 0; L < nh; L++) E[IMEX_COMP[c] * nu + L + nh * gk] = 1.0;
+            or_imex_V(C, E, VE);
+            for (int64_t L = 0; L < nh; L++) E[IMEX_COMP[c] * nu + L + nh * gk] = 0.0;
+            for (int a = 0; a < nline; a++) {
+                int64_t L = lines ? lines[a] : a;
+                for (int c2 = 0; c2 < 3; c2++)
+                    for (int64_t k2 = 0; k2 < nk; k2++)
+                        Vl[((size_t)a * nx + c2 * nk + k2) * nx + c * nk + gk] = VE[IMEX_COMP[c2] * nu + L + nh * k2];
+            }
+        }
+    for (int st = 0; st < nsteps; st++) {
+        full_rhs(C, qcur, cbuf, R);
+        for (int64_t a = 0; a < n5; a++) sv[a] = 2.0 * qcur[a] - qprev[a];
+        or_imex_V(C, sv, VE);
+        /* r = q* - dt V(2 q^n - q^{n-1}),  q* = q^{n-1} + 2 dt L(q^n) */
+        for (int64_t a = 0; a < n5; a++) r[a] = (qprev[a] + 2.0 * dt * R[a]) - dt * VE[a];
+        memcpy(qn1, r, sizeof(double) * n5);
+        if (lines)
+            for (int c = 0; c < 3; c++)
+                for (int64_t I = 0; I < nu; I++) qn1[IMEX_COMP[c] * nu + I] = NAN;
+        int fail = 0;
+#pragma omp parallel for reduction(| : fail)
+        for (int a = 0; a < nline; a++) {
+            int64_t L = lines ? lines[a] : a;
+            double *A = (double *)malloc(sizeof(double) * nx * nx);
+            double *b = (double *)malloc(sizeof(double) * nx);
+            double *x = (double *)malloc(sizeof(double) * nx);
+            for (int u = 0; u < nx; u++) {
+                for (int v = 0; v < nx; v++)
+                    A[u * nx + v] = (u == v ? 1.0 : 0.0) - dt * Vl[((size_t)a * nx + u) * nx + v];
+                b[u] = r[IMEX_COMP[u / nk] * nu + L + nh * (u % nk)];
+            }
+            fail |= dense_solve(nx, A, b, x);
+            for (int u = 0; u < nx; u++) qn1[IMEX_COMP[u / nk] * nu + L + nh * (u % nk)] = x[u];
+            free(A); free(b); free(x);
+        }
+        if (fail) break;
+        for (int64_t a = 0; a < n5; a++) {
+            double f = qcur[a] + ra * (qprev[a] - 2.0 * qcur[a] + qn1[a]);
+            qprev[a] = f;
+            qcur[a] = qn1[a];
+        }
+    }
+    free(Vl); free(E); free(VE); free(cbuf); free(R); free(r); free(sv); free(qn1);
+    return 0;
+}
+
+/*
  * Boyd-Vandeven filter (Sec. "Filter"; Code example 1: "compute filter",
  * then "DSS and multiply with inverse mass matrix").  The paper names the
  * filter -- a spectral transformation of the element's nodal values that

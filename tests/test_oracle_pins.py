@@ -778,3 +778,103 @@ def test_rk53_and_rk3_agree_to_third_order(small):
         d.append(np.abs(a[4] - b[4]).max())
     rates = np.log2(np.array(d[:-1]) / np.array(d[1:]))
     assert np.all((rates > 2.6) & (rates < 3.4)), (d, rates)
+
+
+# --------------------------------------------------------------------------
+# 1D-IMEX (Sec. "Time Discretization": implicit vertical corrections after an
+# explicit leap-frog step; Code example 1: IMEX corrections per column)
+# --------------------------------------------------------------------------
+def _isentropic(z, ph):
+    R, cp, g0, p0, T0 = ph["R"], ph["cp"], ph["g0"], ph["p0"], ph["T0"]
+    cv = cp - R
+    pi = 1 - g0 * z / (cp * T0)
+    rb = p0 / (R * T0) * pi ** (cv / R)
+    drb = rb * (cv / R) / pi * (-g0 / (cp * T0))
+    return rb, drb, cp / cv
+
+
+@pytest.mark.parametrize("N,tol", [(4, 1e-6), (6, 1e-9)])
+def test_imex_operator_closed_forms(oracle_mod, N, tol):
+    """V on states whose vertical terms have closed forms over the isentropic
+    reference: w = 1 gives V_rho' = -d rho_bar/dz; rho' = d rho_bar gives
+    V_w = (gamma - 1) g0 d (pressure gradient and buoyancy); momentum rows are
+    zero at the walls and V_u = V_v = 0; V_theta' vanishes (theta_bar const)."""
+    wl = inputs.small_box(N)
+    mm, ph = wl["mesh"], wl["phys"]
+    m = oracle_mod.OracleMesh(mm["kind"], N, mm["ne"], mm["periodic"], mm["extent"], mm["h0"], ph)
+    rb, drb, gam = _isentropic(m.get("xu")[2], ph)
+    q = np.zeros((5, m.n_unique))
+    q[3] = 1.0
+    V = m.imex_V(q)
+    assert np.abs(V[0] + drb).max() <= tol * np.abs(drb).max()
+    assert np.all(V[1:4] == 0.0) and np.abs(V[4]).max() < 1e-12
+    d = 1e-3
+    q = np.zeros((5, m.n_unique))
+    q[0] = d * rb
+    V = m.imex_V(q)
+    isb = m.get("isbnd").astype(bool)
+    want = (gam - 1) * ph["g0"] * d
+    assert np.abs(V[3][~isb] - want).max() <= 10 * tol * want
+    assert np.all(V[3][isb] == 0.0) and np.all(V[0] == 0.0) and np.all(V[[1, 2, 4]] == 0.0)
+
+
+def test_imex_operator_acts_along_vertical_lines(oracle_mod):
+    """A unit value at one node: V's response stays on the node's vertical
+    lattice line (terrain-following map: d/dz acts along zeta), terrain included."""
+    m = _box(oracle_mod, 3, 3, 3, 4, h0=400.0)
+    nh = m.n_horiz
+    for comp in (0, 3, 4):
+        for I in (nh * 5 + 7, nh * 0 + 4, nh * (m.n_levels - 1) + 2):
+            E = np.zeros((5, m.n_unique))
+            E[comp, I] = 1.0
+            V = m.imex_V(E)
+            on = np.zeros(m.n_unique, bool)
+            on[I % nh::nh] = True
+            assert np.abs(V[:, ~on]).max() <= 1e-13 * max(np.abs(V[:, on]).max(), 1.0)
+
+
+def test_imex_conserves_mass_flat_box(small):
+    m, wl = small
+    q0 = m.init_state(wl["ic"], inputs.noise(m.n_unique, 0))
+    M, rb = m.get("mass"), m.get("ref")[0]
+    a, b = m.imex_step(q0, q0, 0.1, 0.05, 6)
+    for x in (a, b):
+        assert abs((M * x[0]).sum() - (M * q0[0]).sum()) <= 1e-13 * (M * rb).sum()
+    assert np.abs(b - q0).max() > 0
+
+
+def test_imex_second_order(small):
+    """Against a fine SSP-RK3 reference to t = 0.8 s, started from the exact
+    previous level (one RK3 step back): the error falls 4x per halving of dt
+    (leap-frog with a trapezoidal vertical part, no Robert-Asselin filter)."""
+    m, wl = small
+    q0 = m.init_state(wl["ic"], inputs.noise(m.n_unique, 0))
+    ref = m.step(q0, 0.005, 160)
+    err = []
+    for dt in (0.2, 0.1, 0.05):
+        _, b = m.imex_step(m.step(q0, -dt, 1), q0, dt, 0.0, int(round(0.8 / dt)))
+        err.append([np.abs(b[v] - ref[v]).max() for v in (0, 3, 4)])
+    rates = np.log2(np.array(err[:-1]) / np.array(err[1:]))
+    assert np.all((rates > 1.8) & (rates < 2.3)), rates
+
+
+def test_imex_stable_beyond_the_vertical_acoustic_limit(oracle_mod):
+    """Vertical spacing 8x finer than horizontal: explicit SSP-RK3 blows up at
+    dt = 0.5 s; the 1D-IMEX step stays bounded at dt = 2 s."""
+    wl = inputs.box_workload(4, 4, 8, 4, 40e3, 40e3, 5e3, terrain=0.0, bubble_centre=(20e3, 20e3, 2e3),
+                             bubble_radius=2e3)
+    mm = wl["mesh"]
+    m = oracle_mod.OracleMesh(mm["kind"], mm["N"], mm["ne"], mm["periodic"], mm["extent"], mm["h0"], wl["phys"])
+    q0 = m.init_state(wl["ic"], inputs.noise(m.n_unique, 0))
+    with np.errstate(all="ignore"):
+        x = m.step(q0, 0.5, 80)
+    assert not np.all(np.isfinite(x)) or np.abs(x[3]).max() > 1e3
+    a, b = m.imex_step(q0, q0, 2.0, 0.05, 20)
+    assert np.all(np.isfinite(b)) and np.abs(b[3]).max() < 2 * np.abs(m.step(q0, 0.1, 400)[3]).max()
+
+
+def test_imex_refuses_periodic_z_and_shell(oracle_mod):
+    m = _box(oracle_mod, 2, 2, 2, 3, periodic_z=1)
+    q = np.zeros((5, m.n_unique))
+    with pytest.raises(ValueError):
+        m.imex_step(q, q, 0.1, 0.0, 1)
