@@ -224,6 +224,30 @@ int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn,
  * The stream must not run other work on q or the workspace meanwhile. */
 int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double *q, void *stream);
 
+/* 1D-IMEX (Sec. "Time Discretization": implicit corrections along the vertical
+ * columns after an explicit leap-frog step; Code example 1: IMEX corrections
+ * per vertical column), nsteps steps on the pair (qprev = q^{n-1},
+ * qcur = q^n), both [5][n_unique] on the device, updated in place to
+ * (filtered q^n, q^{n+1}):
+ *   q* = q^{n-1} + 2 dt L(q^n)   (a fused stage, L as in numa_step),
+ *   (I - dt V) q^{n+1} = q* - dt V(2 q^n - q^{n-1})   (per vertical line),
+ *   q^n <- q^n + ra (q^{n-1} - 2 q^n + q^{n+1})       (Robert-Asselin filter).
+ * V is the linearisation about the hydrostatic reference of the vertical
+ * terms: V_rho' = -d(rho_bar w)/dz, V_w = -(1/rho_bar) d p_L/dz
+ * + g_z rho'/rho_bar with p_L = (gamma p_bar/rho_bar)(rho' + rho_bar
+ * theta'/theta_bar), V_theta' = -w d theta_bar/dz (zero: the box reference is
+ * isentropic), V_u = V_v = 0, discretised like create_rhs (DSS, M^-1) with zero
+ * momentum rows at the walls; the scheme's details are not in the paper (it
+ * cites another), this is the reading used.  Box meshes with no-flux walls
+ * only (NUMA_EUNSUPPORTED otherwise, and when a line of n_levels levels needs
+ * more than 64 KB of LDS); dt finite, 0 <= ra < 1, distinct states
+ * (NUMA_EINVAL).  prec selects the explicit step's arithmetic; the line solves
+ * are FP64.  The mesh's filter and integrator settings are not used.  Uses
+ * the workspace scratch like numa_step.  To start, pass qprev = qcur (a
+ * forward first step) or a state one step back. */
+int32_t numa_imex_step(numa_mesh_t m, int32_t prec, double dt, double ra, int32_t nsteps, double *qprev,
+                       double *qcur, void *stream);
+
 /* The time integrator of numa_step, numa_step_batch and numa_batch_capture
  * (Sec. "Time Discretization": explicit Runge-Kutta; the paper's scheme has
  * five stages and third order, its coefficients are not in the text):

@@ -484,6 +484,45 @@ int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double
     return NUMA_OK;
 }
 
+int32_t numa_imex_step(numa_mesh_t m, int32_t prec, double dt, double ra, int32_t nsteps, double *qprev,
+                       double *qcur, void *stream)
+{
+    int32_t rc = need_ready(m, "numa_imex_step");
+    if (rc) return rc;
+    if ((rc = check_prec(m, prec, "numa_imex_step"))) return rc;
+    if (!qprev || !qcur || qprev == qcur || nsteps < 0) {
+        set_error("numa_imex_step: null or identical states, or negative step count");
+        return NUMA_EINVAL;
+    }
+    if (!std::isfinite(dt) || !(ra >= 0.0 && ra < 1.0)) {
+        set_error("numa_imex_step: dt must be finite and the Robert-Asselin coefficient in [0, 1)");
+        return NUMA_EINVAL;
+    }
+    if (m->d.kind != NUMA_MESH_BOX || !m->walls) {
+        set_error("numa_imex_step: the vertical correction needs a box mesh with no-flux walls (z not periodic)");
+        return NUMA_EUNSUPPORTED;
+    }
+    if (numa::imex_lds_bytes(*m) > 65536) {
+        set_error("numa_imex_step: %llu levels need more than 64 KB of LDS per vertical line",
+                  (unsigned long long)m->nk);
+        return NUMA_EUNSUPPORTED;
+    }
+    hipStream_t s = as_stream(stream);
+    const numa::StageCoef c{1.0, 0.0, 2.0 * dt};  // q* = q^{n-1} + 2 dt L(q^n)
+    void *ev = prec == NUMA_PREC_MIXED ? (void *)m->dv.ev32 : (void *)m->dv.ev64;
+    for (int n = 0; n < nsteps; ++n) {
+        if (numa::box_batchable(*m)) {
+            numa::StepItem it = {m, qprev, qcur, m->dv.qs, ev, c};
+            rc = run_batch_stage(&it, 1, prec, s);
+        } else {
+            rc = run_stage(m, prec, c, qprev, qcur, m->dv.qs, s);
+        }
+        if (rc) return rc;
+        if ((rc = numa::launch_imex_correction(*m, dt, ra, qprev, qcur, s))) return rc;
+    }
+    return NUMA_OK;
+}
+
 static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 // batch-item scratch: stage state, contributions, and for SSP-RK(5,3) the

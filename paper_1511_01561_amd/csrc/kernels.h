@@ -399,11 +399,13 @@ __device__ inline void noflux(const PointArgs &p, int64_t I, double &r1, double 
 }
 
 // Runge-Kutta stage update (Shu-Osher form, StageCoef): y = q_s + cdt R, then
-// q_out = a q_ref + b y (y itself when a = 0 and b = 1).  The contractions are
-// written out (fma) so that every kernel that updates a state rounds it the
-// same way.
+// q_out = a q_ref + b y (y itself when a = 0 and b = 1); with b = 0 the update
+// is q_ref a + cdt R (the explicit leap-frog step: q_s is not used).  The
+// contractions are written out (fma) so that every kernel that updates a state
+// rounds it the same way.
 __device__ inline double rk_update(const StageCoef &c, double qref, double qs, double r)
 {
+    if (c.b == 0.0) return fma(c.cdt, r, c.a * qref);
     const double y = fma(c.cdt, r, qs);
     if (c.a == 0.0 && c.b == 1.0) return y;
     return fma(c.b, y, c.a * qref);

@@ -152,10 +152,13 @@ void filter_matrix(int N, const double *xi, const double *w, double order, int32
 int32_t launch_filter(Mesh &m, double order, int32_t cutoff, double *q, hipStream_t s);
 int32_t launch_box_plain_finish(const Mesh &m, const double *ev, double *q, hipStream_t s);
 int32_t launch_shell_plain_finish(Mesh &m, const double *ev, double *q, hipStream_t s);
+uint64_t imex_lds_bytes(const Mesh &m);
+int32_t launch_imex_correction(Mesh &m, double dt, double ra, double *qprev, double *qcur, hipStream_t s);
 // The update of one Runge-Kutta stage in Shu-Osher form, written as
 // q_out = a q_ref + b (q_s + cdt R): a is the weight of the reference state
 // (q^n or an earlier stage; not read when a = 0), b the weight of the stage
-// the right-hand side R was taken from, cdt = (beta / b) dt.
+// the right-hand side R was taken from, cdt = (beta / b) dt.  b = 0 means
+// q_out = a q_ref + cdt R (the explicit leap-frog step).
 struct StageCoef {
     double a, b, cdt;
 };

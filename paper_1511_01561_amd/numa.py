@@ -27,7 +27,7 @@ EXPORTED = ["numa_last_error", "numa_gll", "numa_mesh_create", "numa_mesh_destro
             "numa_rk_stage", "numa_step", "numa_profile", "numa_profile_read", "numa_step_scratch_bytes",
             "numa_step_batch", "numa_batch_capture", "numa_graph_launch", "numa_graph_destroy",
             "numa_mesh_set_metric", "numa_filter", "numa_filter_matrix", "numa_mesh_set_filter",
-            "numa_mesh_set_integrator"]
+            "numa_mesh_set_integrator", "numa_imex_step"]
 
 
 class numa_mesh_desc(ct.Structure):
@@ -86,6 +86,7 @@ def lib():
         "numa_filter_matrix": (I32, [I32, D, I32, P]),
         "numa_mesh_set_filter": (I32, [P, I32, D, I32]),
         "numa_mesh_set_integrator": (I32, [P, I32]),
+        "numa_imex_step": (I32, [P, I32, D, D, I32, P, P, P]),
         "numa_step": (I32, [P, I32, D, I32, P, P]),
         "numa_profile": (I32, [P, I32]),
         "numa_profile_read": (I32, [P, P]),
@@ -227,6 +228,12 @@ class Mesh:
         """Boyd-Vandeven filter of the state q [5][n_unique] in place."""
         check(lib().numa_filter(self._h, float(filter_order), int(cutoff), _ptr(q), _stream(stream)))
         return q
+
+    def imex_step(self, qprev, qcur, dt, ra, nsteps, prec=PREC_FP64, stream=None):
+        """nsteps 1D-IMEX leap-frog steps on the pair (q^{n-1}, q^n), in place."""
+        check(lib().numa_imex_step(self._h, prec, float(dt), float(ra), int(nsteps), _ptr(qprev), _ptr(qcur),
+                                   _stream(stream)))
+        return qprev, qcur
 
     def set_integrator(self, integrator: int):
         """RK_SSP33 (default) or RK_SSP53 for step() and the batched steps."""
