@@ -128,8 +128,10 @@ int32_t numa_mesh_info(numa_mesh_t m, int64_t *n_elem, int64_t *n_local, int64_t
 int32_t numa_mesh_gather_map(numa_mesh_t m, int32_t *host_out);
 
 /* Device workspace needed for the precisions in prec_mask (bit 0: FP64 path,
- * bit 1: mixed path).  The FP64 data (geometry, reference, maps, scratch) is
- * always included. */
+ * bit 1: mixed path) and, with bit 2 (NUMA_WS_IMEX, box meshes), the factors
+ * of numa_imex_step's vertical line systems (8 (4N+1) n_levels n_horiz bytes).
+ * The FP64 data (geometry, reference, maps, scratch) is always included. */
+#define NUMA_WS_IMEX 4
 int32_t numa_mesh_workspace_bytes(numa_mesh_t m, int32_t prec_mask, uint64_t *bytes);
 
 /* Bind a caller-owned device buffer (256-byte aligned) as the workspace.
@@ -242,9 +244,13 @@ int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double
  * only (NUMA_EUNSUPPORTED otherwise, and when a line of n_levels levels needs
  * more than 64 KB of LDS); dt finite, 0 <= ra < 1, distinct states
  * (NUMA_EINVAL).  prec selects the explicit step's arithmetic; the line solves
- * are FP64.  The mesh's filter and integrator settings are not used.  Uses
- * the workspace scratch like numa_step.  To start, pass qprev = qcur (a
- * forward first step) or a state one step back. */
+ * are FP64.  The line matrices I - dt V depend only on dt and the reference
+ * state: they are factored (band LU, in one workgroup per line) into the
+ * workspace at the first call and whenever dt changes, so the workspace must
+ * be attached with NUMA_WS_IMEX (NUMA_ENOMEM otherwise); each step then solves
+ * all lines with one lane per line.  The mesh's filter and integrator settings
+ * are not used.  Uses the workspace scratch like numa_step.  To start, pass
+ * qprev = qcur (a forward first step) or a state one step back. */
 int32_t numa_imex_step(numa_mesh_t m, int32_t prec, double dt, double ra, int32_t nsteps, double *qprev,
                        double *qcur, void *stream);
 

@@ -175,6 +175,7 @@ int32_t numa_mesh_attach_workspace(numa_mesh_t m, void *dev_ptr, uint64_t bytes,
     numa::layout_workspace(*m, m->prec_mask, m->ws);
     m->uploaded = false;
     m->geom = false;
+    m->imex_ok = false;
     return NUMA_OK;
 }
 
@@ -214,6 +215,7 @@ int32_t numa_geometry(numa_mesh_t m, const numa_phys *ph, void *stream)
     m->gamma = ph->cp / (ph->cp - ph->R);
     int32_t rc = numa::launch_geometry(*m, as_stream(stream));
     m->geom = rc == NUMA_OK;
+    m->imex_ok = false;  // the reference state may have changed
     return rc;
 }
 
@@ -507,7 +509,16 @@ int32_t numa_imex_step(numa_mesh_t m, int32_t prec, double dt, double ra, int32_
                   (unsigned long long)m->nk);
         return NUMA_EUNSUPPORTED;
     }
+    if (!m->dv.imexLU) {
+        set_error("numa_imex_step: attach the workspace with NUMA_WS_IMEX for the line factors");
+        return NUMA_ENOMEM;
+    }
     hipStream_t s = as_stream(stream);
+    if (!m->imex_ok || m->imex_dt != dt) {  // factors of I - dt V, once per dt
+        if ((rc = numa::launch_imex_factor(*m, dt, s))) return rc;
+        m->imex_dt = dt;
+        m->imex_ok = true;
+    }
     const numa::StageCoef c{1.0, 0.0, 2.0 * dt};  // q* = q^{n-1} + 2 dt L(q^n)
     void *ev = prec == NUMA_PREC_MIXED ? (void *)m->dv.ev32 : (void *)m->dv.ev64;
     for (int n = 0; n < nsteps; ++n) {

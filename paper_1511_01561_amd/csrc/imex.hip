@@ -18,13 +18,13 @@
 // (the horizontal copies of a node contribute identical terms).  So each line
 // is an independent system in (rho', w, theta'): theta' = r_theta, and
 // eliminating rho' = r_rho - dt G(rho_bar w) leaves for w
-//   [I - dt^2 (1/rho_bar) G c2 G rho_bar + dt^2 (g_z/rho_bar) G rho_bar] w
-//       = r_w - dt (1/rho_bar) G(c2 r_rho + kap r_theta) + dt (g_z/rho_bar) r_rho
-// (wall rows: w = r_w), a band matrix of half-width 2N, factored without
-// pivoting (I plus dt^2 times a vertical acoustic operator).
-//
-// One 64-lane workgroup per vertical line; the band matrix, the band of G and
-// the line's vectors live in LDS (dynamic size, nk levels).
+//   A w = r_w - dt (1/rho_bar) G(c2 r_rho + kap r_theta) + dt (g_z/rho_bar) r_rho,
+//   A = I - dt^2 (1/rho_bar) G c2 G rho_bar + dt^2 (g_z/rho_bar) G rho_bar
+// (wall rows: w = r_w), a band matrix of half-width 2N that depends on dt and
+// the reference state only.  It is factored once per dt (LU without pivoting:
+// I plus dt^2 times a vertical acoustic operator) into the workspace; every
+// step then streams each line bottom to top and back, one lane per line, so
+// that neighbouring lanes read neighbouring lattice lines (coalesced).
 #include "kernels.h"
 
 namespace numa {
@@ -35,13 +35,25 @@ struct ImexArgs {
     double *qcur, *qprev;  // in: q^n, q^{n-1}; out: q^{n+1}, the filtered q^n
     const double *ref;     // [3][n_unique]: rho_bar, theta_bar, p_bar
     const double *hcol;    // box column factors, 1/z_zeta in factor 1
+    double *lu;            // [n_levels][4N+1][n_lines]: L below, 1/U_gg on, U above the diagonal
+    double *sr, *sx;       // [n_levels][n_lines] line vectors: r_rho; r_w, then y, then w
     int64_t nu;
     int ni, nj, nk, nx;    // lattice extents, elements along x
     double dt, ra, gamma, gz, theta0;
     double D[kMaxP * kMaxP], w[kMaxP];
 };
 
-// (G)_{g m} on a line of nk = nz N + 1 levels, z_zeta^-1 = izz
+// 1/z_zeta of the element column of line L (the same for every element of it)
+template <int N>
+__device__ __forceinline__ double line_izz(const ImexArgs &a, int64_t L)
+{
+    constexpr int P = N + 1, PP = P * P;
+    const int gi = (int)(L % a.ni), gj = (int)(L / a.ni);
+    const int ex = gi / N, ey = gj / N;
+    return a.hcol[(int64_t)(ex + a.nx * ey) * (4 * PP) + PP + (gi - ex * N) + P * (gj - ey * N)];
+}
+
+// (G)_{g m} on a line of nk = nz N + 1 levels
 template <int N>
 __device__ double g_entry(const ImexArgs &a, int g, int m, double izz)
 {
@@ -61,90 +73,31 @@ __device__ double g_entry(const ImexArgs &a, int g, int m, double izz)
     return num / den * izz;
 }
 
+// The factors of A for every line: one 64-lane workgroup per line builds the
+// band of G and of A in LDS, factors it and writes the band out.
 template <int N>
-__global__ __launch_bounds__(64) void k_imex_line(ImexArgs a)
+__global__ __launch_bounds__(64) void k_imex_factor(ImexArgs a)
 {
-    constexpr int B = 2 * N, W = 2 * B + 1, GW = 2 * N + 1, P = N + 1, PP = P * P;
+    constexpr int B = 2 * N, W = 2 * B + 1, GW = 2 * N + 1;
     extern __shared__ double sm[];
     const int nk = a.nk, lane = threadIdx.x;
     double *Ab = sm;               // [nk][W]: A_{g m} at g W + m - g + B
     double *Gb = Ab + nk * W;      // [nk][GW]: G_{g m} at g GW + m - g + N
-    double *rb = Gb + nk * GW, *c2 = rb + nk, *kap = c2 + nk;
-    double *rr = kap + nk, *rw = rr + nk, *rt = rw + nk;  // r = q* - dt V(2 q^n - q^{n-1})
-    double *f = rt + nk, *h = f + nk, *x = h + nk;
-    double *qc = x + nk, *qp = qc + 3 * nk;  // [3][nk] q^n, q^{n-1} of rho', w, theta'
+    double *rb = Gb + nk * GW, *c2 = rb + nk;
     const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
-    const int gi = (int)(L % a.ni), gj = (int)(L / a.ni);
-    const int64_t nh = (int64_t)a.ni * a.nj, nu = a.nu;
-    const int ex = gi / N, ey = gj / N;
-    const double izz = a.hcol[(int64_t)(ex + a.nx * ey) * (4 * PP) + PP + (gi - ex * N) + P * (gj - ey * N)];
-    const double dt = a.dt;
-    // line data; u and v are final here (no vertical terms): q^{n+1} = q*
+    const int64_t nh = (int64_t)a.ni * a.nj;
+    const double izz = line_izz<N>(a, L);
     for (int g = lane; g < nk; g += 64) {
         const int64_t I = L + nh * g;
-        const double rbar = a.ref[I], pbar = a.ref[2 * nu + I];
-        const double cc = a.gamma * pbar / rbar;
-        rb[g] = rbar;
-        c2[g] = cc;
-        kap[g] = cc * rbar / a.theta0;
-        const int cv[3] = {0, 3, 4};
-        double s[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double vc = a.qcur[cv[c] * nu + I], vp = a.qprev[cv[c] * nu + I];
-            qc[c * nk + g] = vc;
-            qp[c * nk + g] = vp;
-            s[c] = 2.0 * vc - vp;
-        }
-        f[g] = rbar * s[1];
-        h[g] = cc * s[0] + kap[g] * s[2];
-        const bool wall = g == 0 || g == nk - 1;
-        rr[g] = a.qs[I];
-        rw[g] = wall ? a.qs[3 * nu + I] : a.qs[3 * nu + I] - dt * (a.gz * s[0] / rbar);
-        rt[g] = a.qs[4 * nu + I];
-#pragma unroll
-        for (int v = 1; v < 3; ++v) {
-            const double vs = a.qs[v * nu + I], vc = a.qcur[v * nu + I], vp = a.qprev[v * nu + I];
-            a.qprev[v * nu + I] = vc + a.ra * (vp - 2.0 * vc + vs);
-            a.qcur[v * nu + I] = vs;
-        }
+        rb[g] = a.ref[I];
+        c2[g] = a.gamma * a.ref[2 * a.nu + I] / a.ref[I];
     }
     for (int t = lane; t < nk * GW; t += 64) {
         const int g = t / GW, m = g + t % GW - N;
         Gb[t] = (m >= 0 && m < nk) ? g_entry<N>(a, g, m, izz) : 0.0;
     }
     __syncthreads();
-    // r_rho = q*_rho + dt G(rho_bar s_w); r_w += dt G(p_L(s)) / rho_bar (interior)
-    for (int g = lane; g < nk; g += 64) {
-        double gf = 0.0, gh = 0.0;
-#pragma unroll
-        for (int d = 0; d < GW; ++d) {
-            const int m = g + d - N;
-            if (m < 0 || m >= nk) continue;
-            gf += Gb[g * GW + d] * f[m];
-            gh += Gb[g * GW + d] * h[m];
-        }
-        rr[g] += dt * gf;
-        if (g != 0 && g != nk - 1) rw[g] += dt * gh / rb[g];
-    }
-    __syncthreads();
-    for (int g = lane; g < nk; g += 64) h[g] = c2[g] * rr[g] + kap[g] * rt[g];
-    __syncthreads();
-    // right-hand side of the w system, and its band matrix
-    for (int g = lane; g < nk; g += 64) {
-        if (g == 0 || g == nk - 1) {
-            x[g] = rw[g];
-            continue;
-        }
-        double gh = 0.0;
-#pragma unroll
-        for (int d = 0; d < GW; ++d) {
-            const int m = g + d - N;
-            if (m >= 0 && m < nk) gh += Gb[g * GW + d] * h[m];
-        }
-        x[g] = rw[g] - dt * gh / rb[g] + dt * a.gz * rr[g] / rb[g];
-    }
-    const double dt2 = dt * dt;
+    const double dt2 = a.dt * a.dt;
     for (int t = lane; t < nk * W; t += 64) {
         const int g = t / W, m = g + t % W - B;
         double v = 0.0;
@@ -153,10 +106,9 @@ __global__ __launch_bounds__(64) void k_imex_line(ImexArgs a)
                 v = m == g ? 1.0 : 0.0;
             } else {
                 double acc = 0.0;  // (G c2 G)_{g m}
-                for (int p = g - N; p <= g + N; ++p) {
-                    if (p < 0 || p >= nk || m - p < -N || m - p > N) continue;
+                const int p0 = (g > m ? g : m) - N, p1 = (g < m ? g : m) + N;
+                for (int p = p0 < 0 ? 0 : p0; p <= p1 && p < nk; ++p)
                     acc += Gb[g * GW + p - g + N] * c2[p] * Gb[p * GW + m - p + N];
-                }
                 const double gm = (m - g >= -N && m - g <= N) ? Gb[g * GW + m - g + N] : 0.0;
                 v = (m == g ? 1.0 : 0.0) - dt2 / rb[g] * acc * rb[m] + dt2 * a.gz / rb[g] * gm * rb[m];
             }
@@ -164,7 +116,7 @@ __global__ __launch_bounds__(64) void k_imex_line(ImexArgs a)
         Ab[t] = v;
     }
     __syncthreads();
-    // band LU without pivoting: multipliers stored below the diagonal
+    // band LU without pivoting; multipliers below the diagonal
     for (int k = 0; k < nk - 1; ++k) {
         const int rmax = k + B < nk - 1 ? k + B : nk - 1;
         if (lane < B && k + 1 + lane <= rmax) {
@@ -174,65 +126,172 @@ __global__ __launch_bounds__(64) void k_imex_line(ImexArgs a)
         __syncthreads();
         for (int t = lane; t < B * B; t += 64) {
             const int r = k + 1 + t / B, c = k + 1 + t % B;
-            if (r <= rmax && c <= rmax)
-                Ab[r * W + c - r + B] -= Ab[r * W + k - r + B] * Ab[k * W + c - k + B];
+            if (r <= rmax && c <= rmax) Ab[r * W + c - r + B] -= Ab[r * W + k - r + B] * Ab[k * W + c - k + B];
         }
         __syncthreads();
     }
-    // forward and back substitution (one lane)
-    if (lane == 0) {
-        for (int r = 1; r < nk; ++r) {
-            double s = x[r];
-            for (int c = r - B > 0 ? r - B : 0; c < r; ++c) s -= Ab[r * W + c - r + B] * x[c];
-            x[r] = s;
-        }
-        for (int r = nk - 1; r >= 0; --r) {
-            double s = x[r];
-            const int cmax = r + B < nk - 1 ? r + B : nk - 1;
-            for (int c = r + 1; c <= cmax; ++c) s -= Ab[r * W + c - r + B] * x[c];
-            x[r] = s / Ab[r * W + B];
-        }
-    }
-    __syncthreads();
-    for (int g = lane; g < nk; g += 64) f[g] = rb[g] * x[g];
-    __syncthreads();
-    // rho' = r_rho - dt G(rho_bar w), theta' = r_theta; Robert-Asselin filter
-    for (int g = lane; g < nk; g += 64) {
-        double gf = 0.0;
-#pragma unroll
-        for (int d = 0; d < GW; ++d) {
-            const int m = g + d - N;
-            if (m >= 0 && m < nk) gf += Gb[g * GW + d] * f[m];
-        }
-        const double nv[3] = {rr[g] - dt * gf, x[g], rt[g]};
-        const int cv[3] = {0, 3, 4};
-        const int64_t I = L + nh * g;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const double vc = qc[c * nk + g], vp = qp[c * nk + g];
-            a.qprev[cv[c] * nu + I] = vc + a.ra * (vp - 2.0 * vc + nv[c]);
-            a.qcur[cv[c] * nu + I] = nv[c];
-        }
-    }
+    // out, [g][d][line]; entries outside the line are zero, the diagonal is
+    // stored as its reciprocal
+    for (int t = lane; t < nk * W; t += 64) a.lu[(int64_t)t * nh + L] = t % W == B ? 1.0 / Ab[t] : Ab[t];
 }
 
+// D f on one element's nodes (the zeta derivative without 1/z_zeta); D from
+// LDS (uniform addresses: one broadcast read per entry)
 template <int N>
-int32_t launch_imex_n(const ImexArgs &a, int64_t lines, size_t lds, hipStream_t s)
+__device__ __forceinline__ void dloc(const double *D, const double (&f)[N + 1], double (&df)[N + 1])
 {
-    hipLaunchKernelGGL((k_imex_line<N>), dim3((unsigned)lines), dim3(64), lds, s, a);
-    NUMA_HIP(hipGetLastError());
-    return NUMA_OK;
+    constexpr int P = N + 1;
+    // read D where it is used: kept live across the element loop it would
+    // take (N+1)^2 register pairs
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < P; ++m) s = fma(D[k * P + m], f[m], s);
+        df[k] = s;
+    }
 }
 
-}  // namespace
-
-uint64_t imex_lds_bytes(const Mesh &m)
+// G f at local node k of element e: k = 0 above the bottom combines the
+// element below through its top derivative dprev (the DSS of the two copies)
+template <int N>
+__device__ __forceinline__ double gat(double w0, double wN, int e, int k, const double (&df)[N + 1], double dprev,
+                                      double izz)
 {
-    const uint64_t nk = (uint64_t)m.d.ne[2] * m.N + 1;
-    return 8ull * nk * ((4 * m.N + 1) + (2 * m.N + 1) + 15);
+    if (k == 0 && e > 0) return (wN * dprev + w0 * df[0]) / (wN + w0) * izz;
+    return df[k] * izz;
 }
 
-int32_t launch_imex_correction(Mesh &m, double dt, double ra, double *qprev, double *qcur, hipStream_t s)
+// One step's vertical correction: one lane per line, four passes along it;
+// an element's N+1 nodes at a time, node e N + N finishing with element e + 1
+// (or as the top wall node).
+template <int N>
+__global__ __launch_bounds__(256) void k_imex_solve(ImexArgs a)
+{
+    constexpr int P = N + 1, B = 2 * N, W = 2 * B + 1;
+    __shared__ double D[P * P];
+    if (threadIdx.x < P * P) D[threadIdx.x] = a.D[threadIdx.x];
+    __syncthreads();
+    const int64_t nh = (int64_t)a.ni * a.nj, nu = a.nu;
+    const int64_t L = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (L >= nh) return;
+    const int nk = a.nk, nz = (nk - 1) / N;
+    const double w0 = a.w[0], wN = a.w[N];
+    const double izz = line_izz<N>(a, L), dt = a.dt, gz = a.gz, ith = 1.0 / a.theta0;
+    // pass 1: s = 2 q^n - q^{n-1}; r_rho = q*_rho + dt G(rho_bar s_w),
+    // r_w = q*_w - dt (g_z s_rho/rho_bar - G(p_L(s))/rho_bar) (q*_w at walls)
+    double cf = 0.0, ch = 0.0;
+    for (int e = 0; e < nz; ++e) {
+        double f[P], h[P], s0v[P], rbv[P], df[P], dh[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int64_t I = L + nh * (e * N + k);
+            const double rbar = a.ref[I], cc = a.gamma * a.ref[2 * nu + I] / rbar;
+            const double s0 = 2.0 * a.qcur[I] - a.qprev[I];
+            const double s3 = 2.0 * a.qcur[3 * nu + I] - a.qprev[3 * nu + I];
+            const double s4 = 2.0 * a.qcur[4 * nu + I] - a.qprev[4 * nu + I];
+            f[k] = rbar * s3;
+            h[k] = cc * s0 + cc * rbar * ith * s4;
+            s0v[k] = s0;
+            rbv[k] = rbar;
+        }
+        dloc<N>(D, f, df);
+        dloc<N>(D, h, dh);
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            if (k == N && e != nz - 1) continue;
+            const int g = e * N + k;
+            const int64_t I = L + nh * g;
+            const double gf = gat<N>(w0, wN, e, k, df, cf, izz), gh = gat<N>(w0, wN, e, k, dh, ch, izz);
+            const bool wall = g == 0 || g == nk - 1;
+            const double qw = a.qs[3 * nu + I];
+            a.sr[g * nh + L] = a.qs[I] + dt * gf;
+            a.sx[g * nh + L] = wall ? qw : qw - dt * (gz * s0v[k] / rbv[k]) + dt * gh / rbv[k];
+        }
+        cf = df[N];
+        ch = dh[N];
+    }
+    // pass 2: right side of the w system, and the forward elimination with L
+    double yh[B];  // the last B values, newest first
+#pragma unroll
+    for (int s = 0; s < B; ++s) yh[s] = 0.0;
+    ch = 0.0;
+    for (int e = 0; e < nz; ++e) {
+        double h[P], rr[P], rbv[P], dh[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int64_t I = L + nh * (e * N + k);
+            const double rbar = a.ref[I], cc = a.gamma * a.ref[2 * nu + I] / rbar;
+            rr[k] = a.sr[(e * N + k) * nh + L];
+            h[k] = cc * rr[k] + cc * rbar * ith * a.qs[4 * nu + I];
+            rbv[k] = rbar;
+        }
+        dloc<N>(D, h, dh);
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            if (k == N && e != nz - 1) continue;
+            const int g = e * N + k;
+            const double gh = gat<N>(w0, wN, e, k, dh, ch, izz);
+            const bool wall = g == 0 || g == nk - 1;
+            const double rw = a.sx[g * nh + L];
+            double y = wall ? rw : rw - dt * gh / rbv[k] + dt * gz * rr[k] / rbv[k];
+            const double *lg = a.lu + (int64_t)g * W * nh + L;
+#pragma unroll
+            for (int s = 1; s <= B; ++s) y -= lg[(B - s) * nh] * yh[s - 1];
+#pragma unroll
+            for (int s = B - 1; s > 0; --s) yh[s] = yh[s - 1];
+            yh[0] = y;
+            a.sx[g * nh + L] = y;
+        }
+        ch = dh[N];
+    }
+    // pass 3: back substitution with U, top to bottom
+#pragma unroll
+    for (int s = 0; s < B; ++s) yh[s] = 0.0;
+    for (int g = nk - 1; g >= 0; --g) {
+        const double *ug = a.lu + (int64_t)g * W * nh + L;
+        double w = a.sx[g * nh + L];
+#pragma unroll
+        for (int s = 1; s <= B; ++s) w -= ug[(B + s) * nh] * yh[s - 1];
+        w *= ug[B * nh];
+#pragma unroll
+        for (int s = B - 1; s > 0; --s) yh[s] = yh[s - 1];
+        yh[0] = w;
+        a.sx[g * nh + L] = w;
+    }
+    // pass 4: rho' = r_rho - dt G(rho_bar w), theta' = r_theta, u = u*, v = v*;
+    // the Robert-Asselin filter of q^n
+    cf = 0.0;
+    for (int e = 0; e < nz; ++e) {
+        double f[P], wv[P], df[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int64_t I = L + nh * (e * N + k);
+            wv[k] = a.sx[(e * N + k) * nh + L];
+            f[k] = a.ref[I] * wv[k];
+        }
+        dloc<N>(D, f, df);
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            if (k == N && e != nz - 1) continue;
+            const int g = e * N + k;
+            const int64_t I = L + nh * g;
+            const double gf = gat<N>(w0, wN, e, k, df, cf, izz);
+            const double nv[5] = {a.sr[g * nh + L] - dt * gf, a.qs[nu + I], a.qs[2 * nu + I], wv[k],
+                                  a.qs[4 * nu + I]};
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                const double vc = a.qcur[v * nu + I], vp = a.qprev[v * nu + I];
+                a.qprev[v * nu + I] = vc + a.ra * (vp - 2.0 * vc + nv[v]);
+                a.qcur[v * nu + I] = nv[v];
+            }
+        }
+        cf = df[N];
+    }
+}
+
+ImexArgs imex_args(Mesh &m, double dt, double ra, double *qprev, double *qcur)
 {
     ImexArgs a{};
     a.qs = m.dv.qs;
@@ -240,6 +299,9 @@ int32_t launch_imex_correction(Mesh &m, double dt, double ra, double *qprev, dou
     a.qprev = qprev;
     a.ref = m.dv.ref;
     a.hcol = m.dv.hcol;
+    a.lu = m.dv.imexLU;
+    a.sr = m.dv.qs2;
+    a.sx = m.dv.qs2 + m.nu;
     a.nu = m.nu;
     a.ni = (int)m.ni;
     a.nj = (int)m.nj;
@@ -252,18 +314,59 @@ int32_t launch_imex_correction(Mesh &m, double dt, double ra, double *qprev, dou
     a.theta0 = m.ph.T0;
     for (int k = 0; k < m.P * m.P; ++k) a.D[k] = m.D[k];
     for (int k = 0; k < m.P; ++k) a.w[k] = m.w[k];
+    return a;
+}
+
+template <int N>
+int32_t launch_imex_n(const ImexArgs &a, bool factor, int64_t lines, size_t lds, hipStream_t s)
+{
+    if (factor)
+        hipLaunchKernelGGL((k_imex_factor<N>), dim3((unsigned)lines), dim3(64), lds, s, a);
+    else
+        hipLaunchKernelGGL((k_imex_solve<N>), dim3((unsigned)((lines + 255) / 256)), dim3(256), 0, s, a);
+    NUMA_HIP(hipGetLastError());
+    return NUMA_OK;
+}
+
+int32_t launch_imex(Mesh &m, bool factor, double dt, double ra, double *qprev, double *qcur, hipStream_t s)
+{
+    const ImexArgs a = imex_args(m, dt, ra, qprev, qcur);
     const size_t lds = (size_t)imex_lds_bytes(m);
     const int64_t lines = m.ni * m.nj;
     switch (m.N) {
-    case 1: return launch_imex_n<1>(a, lines, lds, s);
-    case 2: return launch_imex_n<2>(a, lines, lds, s);
-    case 3: return launch_imex_n<3>(a, lines, lds, s);
-    case 4: return launch_imex_n<4>(a, lines, lds, s);
-    case 5: return launch_imex_n<5>(a, lines, lds, s);
-    case 6: return launch_imex_n<6>(a, lines, lds, s);
-    case 7: return launch_imex_n<7>(a, lines, lds, s);
-    default: return launch_imex_n<8>(a, lines, lds, s);
+    case 1: return launch_imex_n<1>(a, factor, lines, lds, s);
+    case 2: return launch_imex_n<2>(a, factor, lines, lds, s);
+    case 3: return launch_imex_n<3>(a, factor, lines, lds, s);
+    case 4: return launch_imex_n<4>(a, factor, lines, lds, s);
+    case 5: return launch_imex_n<5>(a, factor, lines, lds, s);
+    case 6: return launch_imex_n<6>(a, factor, lines, lds, s);
+    case 7: return launch_imex_n<7>(a, factor, lines, lds, s);
+    default: return launch_imex_n<8>(a, factor, lines, lds, s);
     }
+}
+
+}  // namespace
+
+uint64_t imex_lds_bytes(const Mesh &m)
+{
+    const uint64_t nk = (uint64_t)m.d.ne[2] * m.N + 1;
+    return 8ull * nk * ((4 * m.N + 1) + (2 * m.N + 1) + 2);
+}
+
+uint64_t imex_factor_bytes(const Mesh &m)
+{
+    const uint64_t nk = (uint64_t)m.d.ne[2] * m.N + 1;
+    return 8ull * nk * (4 * m.N + 1) * (uint64_t)m.ni * m.nj;
+}
+
+int32_t launch_imex_factor(Mesh &m, double dt, hipStream_t s)
+{
+    return launch_imex(m, true, dt, 0.0, nullptr, nullptr, s);
+}
+
+int32_t launch_imex_correction(Mesh &m, double dt, double ra, double *qprev, double *qcur, hipStream_t s)
+{
+    return launch_imex(m, false, dt, ra, qprev, qcur, s);
 }
 
 }  // namespace numa

@@ -94,7 +94,8 @@ struct DeviceView {
     double *ev64 = nullptr;    // [5][n_local] element contributions of a fused stage, FP64 path
     float *ev32 = nullptr;     // same, mixed path
     double *qs = nullptr;      // [5][n_unique] stage state scratch
-    double *qs2 = nullptr;     // [5][n_unique] second stage state (SSP-RK(5,3) keeps u_2)
+    double *qs2 = nullptr;     // [5][n_unique] second stage state (SSP-RK(5,3) keeps u_2; IMEX line vectors)
+    double *imexLU = nullptr;  // box, workspace bit 2: [n_levels][4N+1][n_horiz] IMEX line factors
     double *D64 = nullptr;     // [(N+1)^2] derivative matrix
     double *xi64 = nullptr;    // [N+1] GLL nodes
     double *w64 = nullptr;     // [N+1] GLL weights
@@ -125,6 +126,8 @@ struct Mesh {
     bool uploaded = false, geom = false;
     int metric_mode = 0;  // NUMA_METRIC_STORED or NUMA_METRIC_RECOMPUTE (box)
     int integrator = 0;         // NUMA_RK_SSP33 or NUMA_RK_SSP53
+    double imex_dt = 0.0;       // dt of the IMEX factors in the workspace (valid when imex_ok)
+    bool imex_ok = false;
     bool filter_on = false;     // numa_step applies the filter after every step
     double filter_order = 0.0;  // Boyd-Vandeven order p
     int filter_cutoff = 0;      // modes 0..cutoff pass unchanged
@@ -153,6 +156,8 @@ int32_t launch_filter(Mesh &m, double order, int32_t cutoff, double *q, hipStrea
 int32_t launch_box_plain_finish(const Mesh &m, const double *ev, double *q, hipStream_t s);
 int32_t launch_shell_plain_finish(Mesh &m, const double *ev, double *q, hipStream_t s);
 uint64_t imex_lds_bytes(const Mesh &m);
+uint64_t imex_factor_bytes(const Mesh &m);
+int32_t launch_imex_factor(Mesh &m, double dt, hipStream_t s);
 int32_t launch_imex_correction(Mesh &m, double dt, double ra, double *qprev, double *qcur, hipStream_t s);
 // The update of one Runge-Kutta stage in Shu-Osher form, written as
 // q_out = a q_ref + b (q_s + cdt R): a is the weight of the reference state

@@ -19,6 +19,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 DSS_MASS, DSS_NOFLUX = 1, 2
 METRIC_STORED, METRIC_RECOMPUTE = 0, 1
 RK_SSP33, RK_SSP53 = 0, 1
+WS_IMEX = 4
 FIELD_MASS, FIELD_REF, FIELD_COORDS, FIELD_METRIC, FIELD_GRAVITY, FIELD_LOCAL_COORDS = range(6)
 
 EXPORTED = ["numa_last_error", "numa_gll", "numa_mesh_create", "numa_mesh_destroy", "numa_mesh_info",

@@ -13,6 +13,11 @@ from test_gpu_parity import TOL64, Pair, assert_groups, group_err, small_shell
 pytestmark = pytest.mark.gpu
 
 
+def Pair_(wl, oracle_mod):
+    """Oracle and library mesh; the workspace holds the IMEX line factors."""
+    return Pair(wl, oracle_mod, prec_mask=7)
+
+
 @pytest.fixture(scope="module")
 def torch_cuda():
     import torch
@@ -38,7 +43,7 @@ def imex_case(p, dt, ra, nsteps, seed, prec=0):
 @pytest.mark.parametrize("metric", [0, 1])
 @pytest.mark.parametrize("N", range(1, 9))
 def test_imex_parity_all_orders(torch_cuda, oracle_mod, N, metric):
-    p = Pair(terrain_box(N), oracle_mod)
+    p = Pair_(terrain_box(N), oracle_mod)
     p.g.set_metric(metric)
     _, (oa, ob), (ga, gb) = imex_case(p, 0.1, 0.05, 3, 10 + N)
     assert_groups(gb, ob, TOL64, "imex q^{n+1} N=%d metric=%d" % (N, metric))
@@ -49,7 +54,7 @@ def test_imex_parity_all_orders(torch_cuda, oracle_mod, N, metric):
 def test_imex_parity_generic_box_path(torch_cuda, oracle_mod, ne):
     """x extents that the box finish segments do not divide: the explicit
     stage runs through the general kernels."""
-    p = Pair(terrain_box(4, ne=ne), oracle_mod)
+    p = Pair_(terrain_box(4, ne=ne), oracle_mod)
     _, (oa, ob), (ga, gb) = imex_case(p, 0.1, 0.1, 2, 20)
     assert_groups(gb, ob, TOL64, "imex generic ne=%s" % (ne,))
     assert_groups(ga, oa, TOL64, "imex generic filtered ne=%s" % (ne,))
@@ -57,7 +62,7 @@ def test_imex_parity_generic_box_path(torch_cuda, oracle_mod, ne):
 
 def test_imex_forward_start_and_no_filter(torch_cuda, oracle_mod):
     """qprev = qcur (a forward first step), ra = 0."""
-    p = Pair(inputs.small_box(), oracle_mod)
+    p = Pair_(inputs.small_box(), oracle_mod)
     q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 3))
     oa, ob = p.o.imex_step(q0, q0, 0.2, 0.0, 4)
     ga, gb = p.dev(q0), p.dev(q0)
@@ -68,7 +73,7 @@ def test_imex_forward_start_and_no_filter(torch_cuda, oracle_mod):
 
 def test_imex_mixed_precision_explicit_stage(torch_cuda, oracle_mod):
     from paper_1511_01561_amd import numa
-    p = Pair(terrain_box(4), oracle_mod)
+    p = Pair_(terrain_box(4), oracle_mod)
     p.g.set_metric(numa.METRIC_RECOMPUTE)
     q0, (_, ob), (_, gb) = imex_case(p, 0.1, 0.05, 2, 30, prec=numa.PREC_MIXED)
     e = group_err(gb - q0, ob - q0)
@@ -81,7 +86,7 @@ def test_imex_stable_beyond_the_vertical_acoustic_limit(torch_cuda, oracle_mod):
     blows up at 0.5 s on this mesh): 20 steps bounded and equal to the oracle."""
     wl = inputs.box_workload(4, 4, 8, 4, 40e3, 40e3, 5e3, terrain=0.0, bubble_centre=(20e3, 20e3, 2e3),
                              bubble_radius=2e3)
-    p = Pair(wl, oracle_mod)
+    p = Pair_(wl, oracle_mod)
     q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 0))
     oa, ob = p.o.imex_step(q0, q0, 2.0, 0.05, 20)
     ga, gb = p.dev(q0), p.dev(q0)
@@ -93,13 +98,13 @@ def test_imex_stable_beyond_the_vertical_acoustic_limit(torch_cuda, oracle_mod):
 
 def test_imex_refusals(torch_cuda, oracle_mod):
     from paper_1511_01561_amd import numa
-    cases = [Pair(terrain_box(3, perz=True), oracle_mod), Pair(small_shell(3), oracle_mod)]
+    cases = [Pair_(terrain_box(3, perz=True), oracle_mod), Pair_(small_shell(3), oracle_mod)]
     for p in cases:
         q = p.dev(np.zeros((5, p.nu)))
         r = p.dev(np.zeros((5, p.nu)))
         with pytest.raises(numa.NumaError, match="walls"):
             p.g.imex_step(q, r, 0.1, 0.0, 1)
-    p = Pair(terrain_box(2), oracle_mod)
+    p = Pair_(terrain_box(2), oracle_mod)
     q = p.dev(np.zeros((5, p.nu)))
     r = p.dev(np.zeros((5, p.nu)))
     for dt, ra in ((0.1, -0.1), (0.1, 1.0), (float("nan"), 0.0)):
@@ -107,9 +112,13 @@ def test_imex_refusals(torch_cuda, oracle_mod):
             p.g.imex_step(q, r, dt, ra, 1)
     with pytest.raises(numa.NumaError):
         p.g.imex_step(q, q, 0.1, 0.0, 1)
-    # 129 levels at N = 8 need more than 64 KB of LDS per line
-    wl = inputs.box_workload(2, 2, 16, 8, 4e3, 4e3, 16e3)
-    g = numa.Mesh(wl["mesh"], wl["phys"], prec_mask=1)
+    # a workspace without the line factors
+    p3 = Pair(terrain_box(2), oracle_mod, prec_mask=3)
+    with pytest.raises(numa.NumaError, match="NUMA_WS_IMEX"):
+        p3.g.imex_step(p3.dev(np.zeros((5, p3.nu))), p3.dev(np.zeros((5, p3.nu))), 0.1, 0.0, 1)
+    # 161 levels at N = 8 need more than 64 KB of LDS per line
+    wl = inputs.box_workload(2, 2, 20, 8, 4e3, 4e3, 20e3)
+    g = numa.Mesh(wl["mesh"], wl["phys"], prec_mask=5)
     z = g.init_state(wl["ic"], None)
     with pytest.raises(numa.NumaError, match="LDS"):
         g.imex_step(z.clone(), z, 0.1, 0.0, 1)
@@ -120,7 +129,7 @@ def test_imex_full_size_sampled_lines(torch_cuda, oracle_mod):
     the oracle solves about 100 sampled vertical lines, some through the warm
     bubble so that every variable group is populated (u and v everywhere)."""
     from paper_1511_01561_amd import numa
-    p = Pair(inputs.gpu_box(), oracle_mod)
+    p = Pair_(inputs.gpu_box(), oracle_mod)
     p.g.set_metric(numa.METRIC_RECOMPUTE)
     q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 1))
     rng = np.random.default_rng(5)
