@@ -216,11 +216,12 @@ int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn,
 /* nsteps Runge-Kutta steps in place on q [5][n_unique] (device) with the mesh's
  * integrator (numa_mesh_set_integrator; SSP-RK3 unless set), each stage being
  * rhs -> DSS (mass, no-flux) -> stage update, fused into two kernels: the
- * element kernel updates nodes that have a single copy and stores the other
- * copies' contributions by unique node; the finish kernel sums them in
- * ascending element-local order (the order of numa_dss), applies M^-1, the
- * wall projection and the update.  Uses the workspace scratch; equals the
- * composition of numa_rhs, numa_dss and numa_rk_stage up to rounding.
+ * element kernel writes every element-local node's contribution J w R
+ * (node-major: a copy's five values together); the finish kernel sums the
+ * copies of each unique node, applies M^-1, the wall projection and the
+ * update.  Uses the workspace scratch; equals the composition of numa_rhs,
+ * numa_dss and numa_rk_stage up to rounding (the copies may be summed in
+ * another order).
  * With a filter set on the mesh (numa_mesh_set_filter) every step ends with
  * numa_filter (Code example 1: the filter follows the stages).
  * The stream must not run other work on q or the workspace meanwhile. */
