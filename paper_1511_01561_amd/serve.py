@@ -1,12 +1,13 @@
 """Continuous-batching serving loop for ensemble and regional solves.
 
-Requests (a box mesh, an order N, an initial perturbation, K steps) arrive over
-time.  The server keeps every admitted state resident in device memory, admits
-requests first-come-first-served while their memory footprint fits a budget,
-groups the active requests by order and advances each group by one SSP-RK3
-step per iteration in batched launches (numa_step_batch: one element launch
-and one finish launch per stage for all members), replaying a HIP graph of
-that step while the group's membership is unchanged.  A request that has run
+Requests (a box mesh, an order N, an initial perturbation, K steps, and
+optionally the five-stage integrator and a filter) arrive over time.  The
+server keeps every admitted state resident in device memory, admits requests
+first-come-first-served while their memory footprint fits a budget, groups the
+active requests by order and integrator and advances each group by one step
+per iteration in batched launches (numa_step_batch: one element launch and one
+finish launch per stage for all members, then each filtered member's filter),
+replaying a HIP graph of that step while the group's membership is unchanged.  A request that has run
 its K steps retires at the end of the iteration, its memory is released and
 waiting requests are admitted.  Latency is completion time minus arrival time.
 
@@ -28,6 +29,8 @@ class Request:
     workload: dict          # inputs.box_workload(...)
     noise_seed: int
     steps: int = 50
+    integrator: int = 0     # numa.RK_SSP33 or numa.RK_SSP53
+    filter: tuple = None    # (filter order p, cutoff) applied after every step, or None
     # filled by the server
     admitted: float = -1.0
     done: float = -1.0
@@ -35,12 +38,23 @@ class Request:
 
     @property
     def key(self):
+        """Requests with equal keys share one geometry (and its step settings)."""
         m = self.workload["mesh"]
-        return (tuple(m["ne"]), m["N"], tuple(m["periodic"]), tuple(m["extent"]), m["h0"])
+        return (tuple(m["ne"]), m["N"], tuple(m["periodic"]), tuple(m["extent"]), m["h0"], self.integrator,
+                self.filter)
 
     @property
     def order(self):
         return self.workload["mesh"]["N"]
+
+    @property
+    def group(self):
+        """Requests batched together: one order and one integrator per launch."""
+        return (self.order, self.integrator)
+
+    @property
+    def stages(self):
+        return 5 if self.integrator == 1 else 3
 
 
 @dataclass
@@ -77,6 +91,9 @@ class GpuExecutor:
                                    device=self.device, stream=self.stream)
                 if req.workload["mesh"]["kind"] == self.numa.MESH_BOX:
                     g.set_metric(self.metric)
+                g.set_integrator(req.integrator)
+                if req.filter is not None:
+                    g.set_filter(*req.filter)
             self._geoms[req.key] = g
         return g
 
@@ -97,18 +114,18 @@ class GpuExecutor:
         # memory only for later work on the same stream: safe to drop here
         return (q, scratch)
 
-    def step_group(self, order: int, slots, dt: float):
+    def step_group(self, group, slots, dt: float):
         items = [(s.geom, s.handle[0], s.handle[1], dt) for s in slots]
-        key = (order, tuple(s.req.id for s in slots))
+        key = (group, tuple(s.req.id for s in slots))
         if not self.use_graphs:
             self.numa.step_batch(items, 1, self.prec, stream=self.stream)
             return
-        g = self._graphs.get(order)
+        g = self._graphs.get(group)
         if g is None or g[0] != key:
             if g is not None:
                 g[1].close()
             g = (key, self.numa.Graph(items, 1, self.prec, self.stream))
-            self._graphs[order] = g
+            self._graphs[group] = g
         g[1].launch(self.stream)
 
     def sync(self):
@@ -130,7 +147,7 @@ class GpuExecutor:
 class ServeStats:
     latencies: list = field(default_factory=list)
     wall: float = 0.0
-    updates: float = 0.0      # grid-point RHS updates (unique nodes x 3 stages x steps)
+    updates: float = 0.0      # grid-point RHS updates (unique nodes x stages x steps)
     iterations: int = 0
     max_active: int = 0
     peak_bytes: int = 0
@@ -194,16 +211,16 @@ class Server:
             st.max_active = max(st.max_active, len(active))
             groups = collections.defaultdict(list)
             for s in active.values():
-                groups[s.req.order].append(s)
-            for order in sorted(groups):
-                self.ex.step_group(order, groups[order], self.dt)
+                groups[s.req.group].append(s)
+            for grp in sorted(groups):
+                self.ex.step_group(grp, groups[grp], self.dt)
             self.ex.sync()
             st.iterations += 1
             now = self.clock() - t0
             for rid in list(active):
                 s = active[rid]
                 s.steps_done += 1
-                st.updates += 3.0 * s.geom.n_unique
+                st.updates += s.req.stages * s.geom.n_unique
                 if s.steps_done >= s.req.steps:
                     s.req.done = now
                     s.req.state = self.ex.finish(s, self.keep)

@@ -151,3 +151,29 @@ def test_serving_results_same_alone_and_in_the_mix(torch_cuda, prec):
         torch.cuda.synchronize()
         assert torch.equal(q, r.state), r.id
     ex.drop_graphs()
+
+
+def test_serving_mixed_integrators_and_filters(torch_cuda):
+    """Requests with the five-stage integrator and with a filter in the same
+    stream: grouped by order and integrator, each result bitwise its run alone."""
+    from paper_1511_01561_amd import numa
+    from paper_1511_01561_amd.serve import GpuExecutor, Request, Server
+    torch = torch_cuda
+    specs = [(8, 4, 0, None), (4, 4, 1, None), (8, 4, 0, (16.0, 1)), (4, 4, 1, (12.0, 2)), (8, 3, 1, None),
+             (4, 3, 0, (16.0, 1))]
+    reqs = [Request(id=i, arrival=0.0, workload=box(n, N, 60 + i, nz=max(2, n // 2)), noise_seed=700 + i,
+                    steps=3 + (i % 2), integrator=integ, filter=filt)
+            for i, (n, N, integ, filt) in enumerate(specs)]
+    ex = GpuExecutor(prec=0)
+    srv = Server(ex, budget_bytes=1 << 34, keep_states=True)
+    srv.prewarm(reqs)
+    st = srv.run(reqs, realtime=False)
+    assert len(st.latencies) == len(reqs)
+    for r in reqs:
+        g = ex.geometry(r)
+        q = g.init_state(r.workload["ic"], inputs.device_noise(g.n_unique, r.noise_seed))
+        g.step(q, 0.05, r.steps)
+        torch.cuda.synchronize()
+        assert torch.equal(q, r.state), r.id
+    ex.drop_graphs()
+

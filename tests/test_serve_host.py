@@ -30,9 +30,9 @@ class FakeExecutor:
         self.live += 1
         return {"steps": 0}
 
-    def step_group(self, order, slots, dt):
-        assert len({s.req.order for s in slots}) == 1 and slots[0].req.order == order
-        self.log.append((self.clock.t, order, tuple(s.req.id for s in slots)))
+    def step_group(self, group, slots, dt):
+        assert len({s.req.group for s in slots}) == 1 and slots[0].req.group == group
+        self.log.append((self.clock.t, group, tuple(s.req.id for s in slots)))
         for s in slots:
             s.handle["steps"] += 1
         self.clock.t += 0.001 * len(slots)
@@ -100,8 +100,24 @@ def test_groups_by_order_and_continuous_batching():
     groups = [g for g in ex.log]
     # orders never mix in one launch; request 2 joins request 0's batch while 0 is running
     assert all(len(set(reqs[i].order for i in ids)) == 1 for _, _, ids in groups)
-    assert any(ids == (0, 2) for _, o, ids in groups if o == 4)
+    assert any(ids == (0, 2) for _, g, ids in groups if g == (4, 0))
     assert reqs[2].done < reqs[0].done
+
+
+def test_integrators_never_share_a_launch_and_updates_count_stages():
+    clk = Clock()
+    ex = FakeExecutor(clk)
+    srv = Server(ex, budget_bytes=10 ** 9, clock=clk, sleep=clk.sleep)
+    reqs = [req(0, 0.0, order=4, steps=4), req(1, 0.0, order=4, steps=4), req(2, 0.0, order=4, steps=4)]
+    reqs[1].integrator = 1
+    reqs[2].filter = (16.0, 1)
+    st = srv.run(reqs, realtime=False)
+    launches = [(g, ids) for _, g, ids in ex.log]
+    assert all(ids == (0, 2) for g, ids in launches if g == (4, 0))      # a filter does not split a group
+    assert all(ids == (1,) for g, ids in launches if g == (4, 1))
+    assert len({r.key for r in reqs}) == 3                              # but it needs its own geometry
+    n = reqs[0].workload["mesh"]["ne"][0] ** 3
+    assert st.updates == 4 * n * (3 + 5 + 3)
 
 
 def test_request_larger_than_budget_is_refused():
