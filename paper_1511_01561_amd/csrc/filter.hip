@@ -50,9 +50,9 @@ enum FilterGeo {
 };
 
 template <int N>
-constexpr int filter_eb()   // elements per block: about 256 lanes
+constexpr int filter_eb()   // elements per block: about 512 lanes (longer x runs of the gathered rows)
 {
-    return (N + 1) * (N + 1) * (N + 1) >= 256 ? 1 : 256 / ((N + 1) * (N + 1) * (N + 1));
+    return (N + 1) * (N + 1) * (N + 1) >= 512 ? 1 : 512 / ((N + 1) * (N + 1) * (N + 1));
 }
 
 template <int N>
