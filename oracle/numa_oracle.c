@@ -931,13 +931,15 @@ int or_step_rk53(const or_ctx *C, double dt, int nsteps, double *q)
  * corrections for each vertical column of grid points").  The paper makes
  * implicit corrections along the vertical columns after an explicit leap-frog
  * step and refers the scheme to another paper.  Reading (box with no-flux
- * walls only):
+ * walls, and the shell):
  *   V(q) is the linearisation about the hydrostatic reference of the terms
- *   that carry vertically propagating sound and gravity:
- *     V_rho'  = -d(rho_bar w)/dz,
- *     V_w     = -(1/rho_bar) dp_L/dz + g_z rho'/rho_bar,
+ *   that carry vertically propagating sound and gravity, with n the unit
+ *   vertical (z on the box, the radial direction on the shell), d/dn = n.grad,
+ *   w_n = u.n and s = r^2 on the shell (1 on the box):
+ *     V_rho'  = -(1/s) d(s rho_bar w_n)/dn,
+ *     V_u     = n (-(1/rho_bar) dp_L/dn + (g.n) rho'/rho_bar),
  *                p_L = (gamma p_bar / rho_bar) (rho' + rho_bar theta'/theta_bar),
- *     V_theta' = -w dtheta_bar/dz,   V_u = V_v = 0,
+ *     V_theta' = -w_n dtheta_bar/dn,
  *   discretised like create_rhs (element-local derivatives through the metric,
  *   J w weighting, DSS and M^-1), the momentum rows set to zero at the walls
  *   (the wall velocity is that of the explicit step);
@@ -947,14 +949,15 @@ int or_step_rk53(const or_ctx *C, double dt, int nsteps, double *q)
  *     (I - dt V) q^{n+1} = q* - dt V(2 q^n - q^{n-1})  (vertical correction)
  *   followed by the Robert-Asselin filter with coefficient ra:
  *     q^n <- q^n + ra (q^{n-1} - 2 q^n + q^{n+1}).
- * V couples only the nodes of one vertical lattice line (x = x(xi), y = y(eta)
- * in the terrain-following map: d/dz acts along zeta), so the correction is one
- * linear solve per line.
+ * V couples only the nodes of one vertical lattice line (d/dn acts along
+ * zeta: xi and eta are constant along n in both maps), so the correction is
+ * one linear solve per line; V changes the velocity only along n.
  */
 int or_imex_V(const or_ctx *C, const double *q, double *out)
 {
     int P = C->P, np = C->np;
     int64_t nu = C->nu, nl = C->nl;
+    int shell = C->m.kind == 1;
     double cv = C->ph.cp - C->ph.R, gamma = C->ph.cp / cv;
     double *cbuf = (double *)malloc(sizeof(double) * 5 * nl);
     if (!cbuf) return -2;
@@ -964,7 +967,10 @@ int or_imex_V(const or_ctx *C, const double *q, double *out)
         for (int l = 0; l < np; l++) {
             int64_t I = C->G[e * np + l];
             double rb = C->ref[I], tb = C->ref[nu + I], pb = C->ref[2 * nu + I];
-            F[0][l] = rb * q[3 * nu + I];
+            double n0 = shell ? C->du[I] : 0.0, n1 = shell ? C->du[nu + I] : 0.0, n2 = shell ? C->du[2 * nu + I] : 1.0;
+            double r = shell ? C->m.extent[0] + C->hu[I] : 1.0;
+            double wn = q[nu + I] * n0 + q[2 * nu + I] * n1 + q[3 * nu + I] * n2;
+            F[0][l] = r * r * rb * wn;
             F[1][l] = gamma * pb / rb * (q[I] + rb * q[4 * nu + I] / tb);
             F[2][l] = tb;
         }
@@ -973,7 +979,9 @@ int or_imex_V(const or_ctx *C, const double *q, double *out)
                 for (int i = 0; i < P; i++) {
                     int l = i + P * (j + P * k);
                     int64_t g = e * np + l, I = C->G[g];
-                    double dz[3];
+                    double n[3] = {shell ? C->du[I] : 0.0, shell ? C->du[nu + I] : 0.0, shell ? C->du[2 * nu + I] : 1.0};
+                    double r = shell ? C->m.extent[0] + C->hu[I] : 1.0;
+                    double dn[3];
                     for (int f = 0; f < 3; f++) {
                         double a = 0.0, b = 0.0, c = 0.0;
                         for (int m = 0; m < P; m++) {
@@ -981,15 +989,22 @@ int or_imex_V(const or_ctx *C, const double *q, double *out)
                             b += C->D[j * P + m] * F[f][i + P * (m + P * k)];
                             c += C->D[k * P + m] * F[f][i + P * (j + P * m)];
                         }
-                        dz[f] = a * C->met[2 * nl + g] + b * C->met[5 * nl + g] + c * C->met[8 * nl + g];
+                        /* n.grad: sum over x, y, z of n_x (d/dxi xi_x + d/deta eta_x + d/dzeta zeta_x) */
+                        dn[f] = 0.0;
+                        for (int x = 0; x < 3; x++)
+                            dn[f] += n[x] * (a * C->met[x * nl + g] + b * C->met[(3 + x) * nl + g] +
+                                             c * C->met[(6 + x) * nl + g]);
                     }
                     double rb = C->ref[I];
+                    double gn = C->grav[I] * n[0] + C->grav[nu + I] * n[1] + C->grav[2 * nu + I] * n[2];
+                    double wn = q[nu + I] * n[0] + q[2 * nu + I] * n[1] + q[3 * nu + I] * n[2];
+                    double Vw = -dn[1] / rb + gn * q[I] / rb;
                     double V[5];
-                    V[0] = -dz[0];
-                    V[1] = 0.0;
-                    V[2] = 0.0;
-                    V[3] = -dz[1] / rb + C->grav[2 * nu + I] * q[I] / rb;
-                    V[4] = -q[3 * nu + I] * dz[2];
+                    V[0] = -dn[0] / (r * r);
+                    V[1] = Vw * n[0];
+                    V[2] = Vw * n[1];
+                    V[3] = Vw * n[2];
+                    V[4] = -wn * dn[2];
                     double Jw = C->met[9 * nl + g];
                     for (int s = 0; s < 5; s++) cbuf[s * nl + g] = Jw * V[s];
                 }
@@ -1035,22 +1050,42 @@ static int dense_solve(int n, double *A, double *b, double *x)
     return 0;
 }
 
-/* the components V acts on, in the order of a line's unknowns */
-static const int IMEX_COMP[3] = {0, 3, 4};
+/* the unit vertical at unique node I (z on the box, radial on the shell) */
+static void vertical(const or_ctx *C, int64_t I, double *n)
+{
+    if (C->m.kind == 1) {
+        n[0] = C->du[I]; n[1] = C->du[C->nu + I]; n[2] = C->du[2 * C->nu + I];
+    } else {
+        n[0] = 0.0; n[1] = 0.0; n[2] = 1.0;
+    }
+}
+
+/* unknown c (0: rho', 1: w_n, 2: theta') of state x at node I */
+static double imex_get(const or_ctx *C, const double *x, int c, int64_t I)
+{
+    int64_t nu = C->nu;
+    if (c == 0) return x[I];
+    if (c == 2) return x[4 * nu + I];
+    double n[3];
+    vertical(C, I, n);
+    return x[nu + I] * n[0] + x[2 * nu + I] * n[1] + x[3 * nu + I] * n[2];
+}
 
 /*
  * nsteps 1D-IMEX leap-frog steps on the pair (q^{n-1}, q^n) in place (after
  * the call qprev holds the filtered last-but-one level and qcur the newest).
- * lines: the vertical lattice lines (gi + ni gj) whose correction is solved,
- * or NULL for all; the rho', w, theta' of other lines are set to NaN.  The
- * matrix of V on a line is probed with unit states (one at the same level
- * and component on every line at once) and each line's system, unknowns
- * (rho', w, theta') at its levels, is solved densely.
+ * lines: the vertical lattice lines (horizontal unique index h of the nodes
+ * h + n_h k) whose correction is solved, or NULL for all; the rho', velocity
+ * and theta' of other lines are set to NaN.  The matrix of V on a line, in the
+ * unknowns (rho', w_n, theta') at its levels, is probed with unit states (one
+ * at the same level and unknown on every line at once) and each line's system
+ * is solved densely; the new velocity is the explicit one with its n
+ * component replaced.
  */
 int or_imex_step(const or_ctx *C, double dt, double ra, int nsteps, double *qprev, double *qcur,
                  const int32_t *lines, int nlines)
 {
-    if (C->m.kind != 0 || C->m.periodic[2]) return -3;
+    if (C->m.kind == 0 && C->m.periodic[2]) return -3;
     int64_t nu = C->nu, nh = C->nh, nk = C->nk, n5 = 5 * nu;
     int nline = lines ? nlines : (int)nh;
     int nx = 3 * (int)nk;
@@ -1069,14 +1104,25 @@ int or_imex_step(const or_ctx *C, double dt, double ra, int nsteps, double *qpre
     /* column (c, gk) of every line's matrix of V */
     for (int c = 0; c < 3; c++)
         for (int64_t gk = 0; gk < nk; gk++) {
-            for (int64_t L = 0; L < nh; L++) E[IMEX_COMP[c] * nu + L + nh * gk] = 1.0;
+            for (int64_t L = 0; L < nh; L++) {
+                int64_t I = L + nh * gk;
+                if (c == 0) {
+                    E[I] = 1.0;
+                } else if (c == 2) {
+                    E[4 * nu + I] = 1.0;
+                } else {  /* unit vertical velocity */
+                    double n[3];
+                    vertical(C, I, n);
+                    for (int d = 0; d < 3; d++) E[(1 + d) * nu + I] = n[d];
+                }
+            }
             or_imex_V(C, E, VE);
-            for (int64_t L = 0; L < nh; L++) E[IMEX_COMP[c] * nu + L + nh * gk] = 0.0;
+            memset(E, 0, sizeof(double) * n5);
             for (int a = 0; a < nline; a++) {
                 int64_t L = lines ? lines[a] : a;
                 for (int c2 = 0; c2 < 3; c2++)
                     for (int64_t k2 = 0; k2 < nk; k2++)
-                        Vl[((size_t)a * nx + c2 * nk + k2) * nx + c * nk + gk] = VE[IMEX_COMP[c2] * nu + L + nh * k2];
+                        Vl[((size_t)a * nx + c2 * nk + k2) * nx + c * nk + gk] = imex_get(C, VE, c2, L + nh * k2);
             }
         }
     for (int st = 0; st < nsteps; st++) {
@@ -1087,8 +1133,8 @@ int or_imex_step(const or_ctx *C, double dt, double ra, int nsteps, double *qpre
         for (int64_t a = 0; a < n5; a++) r[a] = (qprev[a] + 2.0 * dt * R[a]) - dt * VE[a];
         memcpy(qn1, r, sizeof(double) * n5);
         if (lines)
-            for (int c = 0; c < 3; c++)
-                for (int64_t I = 0; I < nu; I++) qn1[IMEX_COMP[c] * nu + I] = NAN;
+            for (int64_t I = 0; I < nu; I++)
+                for (int v = 0; v < 5; v++) qn1[v * nu + I] = NAN;
         int fail = 0;
 #pragma omp parallel for reduction(| : fail)
         for (int a = 0; a < nline; a++) {
@@ -1099,10 +1145,18 @@ int or_imex_step(const or_ctx *C, double dt, double ra, int nsteps, double *qpre
             for (int u = 0; u < nx; u++) {
                 for (int v = 0; v < nx; v++)
                     A[u * nx + v] = (u == v ? 1.0 : 0.0) - dt * Vl[((size_t)a * nx + u) * nx + v];
-                b[u] = r[IMEX_COMP[u / nk] * nu + L + nh * (u % nk)];
+                b[u] = imex_get(C, r, u / (int)nk, L + nh * (u % nk));
             }
             fail |= dense_solve(nx, A, b, x);
-            for (int u = 0; u < nx; u++) qn1[IMEX_COMP[u / nk] * nu + L + nh * (u % nk)] = x[u];
+            for (int64_t k = 0; k < nk; k++) {
+                int64_t I = L + nh * k;
+                double n[3];
+                vertical(C, I, n);
+                double rn = imex_get(C, r, 1, I);
+                qn1[I] = x[k];
+                for (int d = 0; d < 3; d++) qn1[(1 + d) * nu + I] = r[(1 + d) * nu + I] - rn * n[d] + x[nk + k] * n[d];
+                qn1[4 * nu + I] = x[2 * nk + k];
+            }
             free(A); free(b); free(x);
         }
         if (fail) break;

@@ -873,8 +873,81 @@ def test_imex_stable_beyond_the_vertical_acoustic_limit(oracle_mod):
     assert np.all(np.isfinite(b)) and np.abs(b[3]).max() < 2 * np.abs(m.step(q0, 0.1, 400)[3]).max()
 
 
-def test_imex_refuses_periodic_z_and_shell(oracle_mod):
+def test_imex_refuses_periodic_z(oracle_mod):
     m = _box(oracle_mod, 2, 2, 2, 3, periodic_z=1)
     q = np.zeros((5, m.n_unique))
     with pytest.raises(ValueError):
         m.imex_step(q, q, 0.1, 0.0, 1)
+
+
+def _shell(oracle_mod, ne, nz, N, H):
+    wl = inputs.shell_workload(ne=ne, nz=nz, N=N, seed=0, H=H)
+    mm = wl["mesh"]
+    return oracle_mod.OracleMesh(mm["kind"], N, mm["ne"], mm["periodic"], mm["extent"], mm["h0"], wl["phys"]), wl
+
+
+def test_imex_operator_closed_forms_shell(oracle_mod):
+    """Shell, N = 8: w_r = 1 gives V_rho' = -(1/r^2) d(r^2 rho_bar)/dr (the
+    2 rho_bar/r term is 2e-3 of the result), rho' = d rho_bar gives a radial
+    V_u = (gamma - 1) g0 (a/r)^2 d over the isothermal reference; no
+    tangential part, zero momentum rows at the walls."""
+    m, wl = _shell(oracle_mod, 2, 4, 8, 30e3)
+    ph, a = wl["phys"], wl["mesh"]["extent"][0]
+    xu = m.get("xu")
+    r = np.linalg.norm(xu, axis=0)
+    n = xu / r
+    rb = m.get("ref")[0]
+    drb = rb * (-(ph["g0"] * a / (ph["R"] * ph["T0"])) * (a / r ** 2))
+    q = np.zeros((5, m.n_unique))
+    q[1:4] = n
+    V = m.imex_V(q)
+    want = -(2 * rb / r + drb)
+    assert np.abs(V[0] - want).max() <= 1e-7 * np.abs(want).max()
+    d = 1e-3
+    q = np.zeros((5, m.n_unique))
+    q[0] = d * rb
+    V = m.imex_V(q)
+    isb = m.get("isbnd").astype(bool)
+    gam = ph["cp"] / (ph["cp"] - ph["R"])
+    want = (gam - 1) * ph["g0"] * (a / r) ** 2 * d
+    Vn = (V[1:4] * n).sum(0)
+    assert np.abs(Vn[~isb] - want[~isb]).max() <= 1e-7 * want.max()
+    assert np.abs(V[1:4] - Vn * n).max() <= 1e-14 * want.max()
+    assert np.all(V[1:4][:, isb] == 0.0)
+
+
+def test_imex_operator_acts_along_radial_lines(oracle_mod):
+    m, _ = _shell(oracle_mod, 3, 4, 4, 30e3)
+    nh = m.n_horiz
+    for comp in (0, 1, 3, 4):
+        I = nh * 5 + 7
+        E = np.zeros((5, m.n_unique))
+        E[comp, I] = 1.0
+        V = m.imex_V(E)
+        on = np.zeros(m.n_unique, bool)
+        on[I % nh::nh] = True
+        assert np.abs(V[:, ~on]).max() <= 1e-15 * np.abs(V[:, on]).max()
+
+
+def test_imex_second_order_shell(oracle_mod):
+    m, wl = _shell(oracle_mod, 3, 4, 4, 30e3)
+    q0 = m.init_state(wl["ic"], None)
+    ref = m.step(q0, 0.02, 400)
+    err = []
+    for dt in (2.0, 1.0, 0.5):
+        _, b = m.imex_step(m.step(q0, -dt, 1), q0, dt, 0.0, int(round(8.0 / dt)))
+        err.append([np.abs(b[v] - ref[v]).max() for v in (0, 1, 4)])
+    rates = np.log2(np.array(err[:-1]) / np.array(err[1:]))
+    assert np.all((rates > 1.8) & (rates < 2.3)), rates
+
+
+def test_imex_stable_beyond_the_radial_acoustic_limit(oracle_mod):
+    """1.25 km layers under ~840 km horizontal spacing: SSP-RK3 blows up at
+    dt = 2 s; 1D-IMEX stays bounded at dt = 20 s for 200 s."""
+    m, wl = _shell(oracle_mod, 3, 8, 4, 10e3)
+    q0 = m.init_state(wl["ic"], None)
+    with np.errstate(all="ignore"):
+        x = m.step(q0, 2.0, 20)
+    assert not np.all(np.isfinite(x)) or np.abs(x[1:4]).max() > 1e3
+    _, b = m.imex_step(q0, q0, 20.0, 0.05, 10)
+    assert np.all(np.isfinite(b)) and np.abs(b[1:4]).max() < 1.01 * np.abs(q0[1:4]).max()
