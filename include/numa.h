@@ -128,7 +128,7 @@ int32_t numa_mesh_info(numa_mesh_t m, int64_t *n_elem, int64_t *n_local, int64_t
 int32_t numa_mesh_gather_map(numa_mesh_t m, int32_t *host_out);
 
 /* Device workspace needed for the precisions in prec_mask (bit 0: FP64 path,
- * bit 1: mixed path) and, with bit 2 (NUMA_WS_IMEX, box meshes), the factors
+ * bit 1: mixed path) and, with bit 2 (NUMA_WS_IMEX, meshes with walls), the factors
  * of numa_imex_step's vertical line systems (8 (4N+1) n_levels n_horiz bytes).
  * The FP64 data (geometry, reference, maps, scratch) is always included. */
 #define NUMA_WS_IMEX 4
@@ -235,16 +235,19 @@ int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double
  *   q* = q^{n-1} + 2 dt L(q^n)   (a fused stage, L as in numa_step),
  *   (I - dt V) q^{n+1} = q* - dt V(2 q^n - q^{n-1})   (per vertical line),
  *   q^n <- q^n + ra (q^{n-1} - 2 q^n + q^{n+1})       (Robert-Asselin filter).
- * V is the linearisation about the hydrostatic reference of the vertical
- * terms: V_rho' = -d(rho_bar w)/dz, V_w = -(1/rho_bar) d p_L/dz
- * + g_z rho'/rho_bar with p_L = (gamma p_bar/rho_bar)(rho' + rho_bar
- * theta'/theta_bar), V_theta' = -w d theta_bar/dz (zero: the box reference is
- * isentropic), V_u = V_v = 0, discretised like create_rhs (DSS, M^-1) with zero
- * momentum rows at the walls; the scheme's details are not in the paper (it
- * cites another), this is the reading used.  Box meshes with no-flux walls
- * only (NUMA_EUNSUPPORTED otherwise, and when a line of n_levels levels needs
- * more than 64 KB of LDS); dt finite, 0 <= ra < 1, distinct states
- * (NUMA_EINVAL).  prec selects the explicit step's arithmetic; the line solves
+ * With n the unit vertical (z on the box, radial on the shell), w = u.n and
+ * s = 1 (box) or r^2 (shell), V is the linearisation about the hydrostatic
+ * reference of the vertical terms: V_rho' = -(1/s) d(s rho_bar w)/dn,
+ * V_u = n (-(1/rho_bar) d p_L/dn + (g.n) rho'/rho_bar) with
+ * p_L = (gamma p_bar/rho_bar)(rho' + rho_bar theta'/theta_bar),
+ * V_theta' = -w d theta_bar/dn (zero on the isentropic box), discretised like
+ * create_rhs (DSS, M^-1) with zero momentum rows at the walls; it acts along
+ * each vertical lattice line (horizontal unique node h, levels h + n_h k) and
+ * changes the velocity only along n.  The scheme's details are not in the
+ * paper (it cites another); this is the reading used.  Meshes with no-flux
+ * walls (the shell, and boxes not periodic in z; NUMA_EUNSUPPORTED otherwise,
+ * and when a line of n_levels levels needs more than 64 KB of LDS); dt finite,
+ * 0 <= ra < 1, distinct states (NUMA_EINVAL).  prec selects the explicit step's arithmetic; the line solves
  * are FP64.  The line matrices I - dt V depend only on dt and the reference
  * state: they are factored (band LU, in one workgroup per line) into the
  * workspace at the first call and whenever dt changes, so the workspace must

@@ -500,8 +500,8 @@ int32_t numa_imex_step(numa_mesh_t m, int32_t prec, double dt, double ra, int32_
         set_error("numa_imex_step: dt must be finite and the Robert-Asselin coefficient in [0, 1)");
         return NUMA_EINVAL;
     }
-    if (m->d.kind != NUMA_MESH_BOX || !m->walls) {
-        set_error("numa_imex_step: the vertical correction needs a box mesh with no-flux walls (z not periodic)");
+    if (!m->walls) {
+        set_error("numa_imex_step: the vertical correction needs no-flux walls (a box periodic in z has none)");
         return NUMA_EUNSUPPORTED;
     }
     if (numa::imex_lds_bytes(*m) > 65536) {

@@ -307,7 +307,7 @@ uint64_t layout_workspace(Mesh &m, int32_t prec_mask, char *base)
     if (prec_mask & 2) v.ev32 = (float *)take(20ull * m.nl);
     v.qs = (double *)take(40ull * m.nu);
     v.qs2 = (double *)take(40ull * m.nu);
-    if ((prec_mask & 4) && m.d.kind == NUMA_MESH_BOX) v.imexLU = (double *)take(imex_factor_bytes(m));
+    if ((prec_mask & 4) && m.walls) v.imexLU = (double *)take(imex_factor_bytes(m));
     v.D64 = (double *)take(8ull * kMaxP * kMaxP);
     v.D32 = (float *)take(4ull * kMaxP * kMaxP);
     v.xi64 = (double *)take(8ull * kMaxP);
