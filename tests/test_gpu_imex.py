@@ -172,3 +172,12 @@ def test_imex_full_size_sampled_lines(torch_cuda, oracle_mod):
     idx = (lines[None, :] + nh * np.arange(p.o.n_levels)[:, None]).ravel()
     for name, a, b in (("q^{n+1}", gb, ob), ("filtered q^n", ga, oa)):
         assert_groups(a[:, idx], b[:, idx], TOL64, "full-size imex %s, sampled lines" % name)
+
+
+def test_imex_zero_steps_leave_states_untouched(torch_cuda, oracle_mod):
+    p = Pair_(terrain_box(3), oracle_mod)
+    q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 9))
+    a, b = p.dev(q0), p.dev(2.0 * q0)
+    p.g.imex_step(a, b, 0.1, 0.05, 0)
+    torch_cuda.cuda.synchronize()
+    assert np.array_equal(p.host(a), q0) and np.array_equal(p.host(b), 2.0 * q0)

@@ -173,3 +173,11 @@ def test_rk53_full_size(torch_cuda, oracle_mod):
     qg = p.dev(q0)
     p.g.step(qg, 0.05, 2)
     assert_groups(p.host(qg), qo, TOL64, "full-size ssp53")
+
+
+def test_rk53_zero_steps_leave_state_untouched(torch_cuda, oracle_mod):
+    p = rk53_pair(terrain_box(3), oracle_mod)
+    q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 90))
+    q = p.dev(q0)
+    p.g.step(q, 0.05, 0)
+    assert np.array_equal(p.host(q), q0)
