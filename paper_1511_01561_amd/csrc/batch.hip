@@ -139,14 +139,17 @@ __global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
 // registers: the zeta derivatives are contractions with D_km, which is the
 // same for every lane, so they need no LDS.  Only the xi and eta derivatives
 // read the element tile.  The arithmetic per node is that of element_rhs.
-// Elements per workgroup: as many columns as fill two wavefronts (one
-// element at N = 7 and 8), which keeps the tile (8 fields of (N+1)^3 nodes
-// per element) within 47 KB.
+// Elements per workgroup: as many columns as fill four wavefronts up to
+// N = 4 (ten x-consecutive elements at N = 4: longer contiguous runs in the
+// gather and the store, measured ~1 % faster than two wavefronts), two
+// wavefronts for the streaming variant at N = 5, 6 (its larger tile would
+// leave one wavefront per SIMD), one element at N = 7 and 8; the tile (8
+// fields of (N+1)^3 nodes per element) stays within 80 KB.
 template <int N, typename T>
 constexpr int col_eb()
 {
     constexpr int PP = (N + 1) * (N + 1);
-    return N >= 7 ? 1 : (128 / PP > 0 ? 128 / PP : 1);
+    return N >= 7 ? 1 : (N <= 4 ? 256 / PP : 128 / PP);
 }
 template <int N, typename T>
 constexpr int col_threads() { return ((col_eb<N, T>() * (N + 1) * (N + 1) + 63) / 64) * 64; }
