@@ -245,3 +245,17 @@ def test_integrator_setting_and_scratch_size(L):
         assert L.numa_mesh_set_integrator(h, numa.RK_SSP33) == 0
     finally:
         L.numa_mesh_destroy(h)
+
+
+def test_imex_step_refused_before_setup(L):
+    assert L.numa_imex_step(None, 0, 0.1, 0.0, 1, ct.c_void_p(16), ct.c_void_p(32), None) == -1
+    rc, h = _create(MESHES[0])
+    assert rc == 0
+    try:   # no workspace: refused before touching the GPU
+        assert L.numa_imex_step(h, 0, 0.1, 0.0, 1, ct.c_void_p(16), ct.c_void_p(32), None) == -2
+        nb, nb4 = ct.c_uint64(), ct.c_uint64()
+        assert L.numa_mesh_workspace_bytes(h, 1, ct.byref(nb)) == 0
+        assert L.numa_mesh_workspace_bytes(h, 1 | numa.WS_IMEX, ct.byref(nb4)) == 0
+        assert nb4.value > nb.value          # the line factors
+    finally:
+        L.numa_mesh_destroy(h)
