@@ -58,12 +58,15 @@ def element_bytes(nu, nl, prec, metric):
 
 def finish_bytes(nu, nl, n_wall, prec):
     """Algorithmic bytes of one finish launch on the box (averaged over the 3
-    stages): per unique node M^-1 (8 B), the stage state, q^n (2 of 3 stages)
-    and the new state (5 x 8 B each); per element-local node its contribution
+    stages): per unique node M^-1 (8 B), q^n (2 of 3 stages) and the new state
+    (5 x 8 B each); the stage state (5 x 8 B) at the wall nodes in FP64 (the
+    FP64 element kernels fold it into the contributions elsewhere) and at
+    every node in mixed precision; per element-local node its contribution
     (5 x 8 B, or 5 x 4 B mixed); the wall normals.  Copies follow from the
     lattice position."""
     contrib = 20 if prec == "mixed" else 40
-    return nu * (8 + 40 + 40 * 2.0 / 3.0 + 40) + nl * contrib + n_wall * 24
+    qs_nodes = nu if prec == "mixed" else n_wall
+    return nu * (8 + 40 * 2.0 / 3.0 + 40) + qs_nodes * 40 + nl * contrib + n_wall * 24
 
 
 def load_traffic(kernel, workload):

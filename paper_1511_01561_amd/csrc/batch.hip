@@ -38,6 +38,7 @@ struct BatchItem {
 
 struct Batch {
     int n;
+    int fold;       // the column kernel folds q_s into the contributions (box_finish_node)
     double ca, cb;  // weights of the reference state and of the stage in the update (same for all items)
     double gamma, g0;
     const void *D;
@@ -121,12 +122,30 @@ __global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
     const RhsArgs<T> a = elem_args<T>(B, it);
     NodeOut<T> o;
     const int l = threadIdx.x;
-    const bool act = element_rhs<N, T, false, GEO>(a, e, l, s, o);
+    // element_rhs, with the node's state kept for the fold
+    NodeIn<T> in;
+    node_gather<N, T, false, GEO>(a, e, l, in);
+    node_stage<N, T, false, GEO>(a, e, l, in, s);
+    __syncthreads();
+    const bool act = l < NP;
+    if (act) {
+        T Di[N + 1], Dj[N + 1], Dk[N + 1];
+        d_rows<N, T>(a.D, l, Di, Dj, Dk);
+        node_derive<N, T, false, GEO>(a, l, in, Di, Dj, Dk, s, o);
+    }
     __syncthreads();  // every lane has finished reading the tile
     T *st = &s[0][0];
     if (act) {
+        const int k = l / ((N + 1) * (N + 1));
+        const bool wall = it.walls && ((in.ez == 0 && k == 0) || (in.ez == it.nz - 1 && k == N));
+        if (sizeof(T) == 8 && B.fold && !wall) {  // J w (q_s + cdt R), as in k_elem_col
+            const double qv[5] = {in.rp, in.u, in.v, in.w, in.tp};
 #pragma unroll
-        for (int v = 0; v < 5; ++v) st[l * 5 + v] = o.Jw * o.R[v];
+            for (int v = 0; v < 5; ++v) st[l * 5 + v] = o.Jw * fma((T)it.cdt, o.R[v], (T)qv[v]);
+        } else {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) st[l * 5 + v] = o.Jw * o.R[v];
+        }
     }
     __syncthreads();
     store_contributions<N, T>(it, e, l, st);
@@ -165,8 +184,10 @@ __global__ __launch_bounds__((col_threads<N, T>())) void k_elem_col(Batch B)
     const int e0 = g0 - it.eoff;  // first element of the workgroup in the item
     const int t = threadIdx.x, q = t / PP, c = t % PP, i = c % P, j = c / P;
     const bool act = q < EB && e0 + q < it.ne;
-    // per node of the column: 1/rho and rho'/rho (formed in FP64), zeta
-    // derivatives of the 8 tile fields
+    // per node of the column: 1/rho and rho'/rho (formed in FP64; in FP64
+    // rho' itself is kept and rho'/rho formed where it is used, the same
+    // product), zeta derivatives of the 8 tile fields
+    constexpr bool F64 = sizeof(T) == 8;
     T irho[P], buoy[P], dz[8][P];
     double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
     int ez = 0;
@@ -197,7 +218,7 @@ __global__ __launch_bounds__((col_threads<N, T>())) void k_elem_col(Batch B)
             const double pp = pb * eos_rel(dl / (rb * tb), a.gamma, a.eos);
             const double ir = 1.0 / rho;
             irho[k] = (T)ir;
-            buoy[k] = (T)(rp * ir);
+            buoy[k] = F64 ? (T)rp : (T)(rp * ir);
             col[0][k] = (T)(rho * u);
             col[1][k] = (T)(rho * v);
             col[2][k] = (T)(rho * w);
@@ -260,14 +281,23 @@ __global__ __launch_bounds__((col_threads<N, T>())) void k_elem_col(Batch B)
             };
             auto adv = [&](int f) -> T { return Uc[0] * dd[f][0] + Uc[1] * dd[f][1] + Uc[2] * dd[f][2]; };
             const T gz = (T)(-a.g0);
+            const T bk = F64 ? buoy[k] * irho[k] : buoy[k];
             T R[5];
             R[0] = -(cart(0, 0) + cart(1, 1) + cart(2, 2));
             R[1] = -adv(3) - cart(7, 0) * irho[k];
             R[2] = -adv(4) - cart(7, 1) * irho[k];
-            R[3] = -adv(5) - cart(7, 2) * irho[k] + buoy[k] * gz;
+            R[3] = -adv(5) - cart(7, 2) * irho[k] + bk * gz;
             R[4] = -adv(6);
+            // J w R, or J w (q_s + cdt R) away from the walls when folding
+            const bool wall = it.walls && ((ez == 0 && k == 0) || (ez == a.nz - 1 && k == N));
+            if (F64 && B.fold && !wall) {
+                const T qv[5] = {buoy[k], uu, vv, ww, s[q][6][l]};
 #pragma unroll
-            for (int v = 0; v < 5; ++v) res[k][v] = mx[9] * R[v];
+                for (int v = 0; v < 5; ++v) res[k][v] = mx[9] * fma((T)it.cdt, R[v], qv[v]);
+            } else {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) res[k][v] = mx[9] * R[v];
+            }
         }
     }
     __syncthreads();  // tiles read
@@ -445,6 +475,7 @@ __global__ void k_fin_batch(Batch B)
     b.walls = it.walls;
     b.ni = it.ni;
     b.nj = it.nj;
+    b.fold = B.fold;
     box_finish_node<N, SEG, T, PLAIN>(p, b, (const T *)it.ev, sx, ey, kbase == 0 ? (int)ez : it.nz - 1, threadIdx.x,
                                       kbase, klayers, StageCoef{B.ca, B.cb, it.cdt}, it.qn, it.qs, it.qout);
 }
@@ -472,6 +503,10 @@ int32_t run_chunk(const StepItem *items, int n, int phase, hipStream_t s)
     const bool recompute = items[0].mesh->metric_mode == NUMA_METRIC_RECOMPUTE;
     const bool col = recompute && col_ok;
     const int eb = col ? col_eb<N, T>() : 1;
+    // FP64 update that uses q_s (b != 0): the column and one-node-per-lane
+    // element kernels fold q_s into the contributions (the streaming one,
+    // which runs at its register limit, does not)
+    B.fold = (std::is_same<T, double>::value && B.cb != 0.0 && !(recompute && kind == 1)) ? 1 : 0;
     int64_t eo = 0, bo = 0;
     for (int k = 0; k < n; ++k) {
         const Mesh &m = *items[k].mesh;

@@ -402,11 +402,20 @@ __device__ inline void noflux(const PointArgs &p, int64_t I, double &r1, double 
 // q_out = a q_ref + b y (y itself when a = 0 and b = 1); with b = 0 the update
 // is q_ref a + cdt R (the explicit leap-frog step: q_s is not used).  The
 // contractions are written out (fma) so that every kernel that updates a state
-// rounds it the same way.
+// from a summed R rounds it the same way (the box's FP64 stages form q_s +
+// cdt R per copy instead: see box_finish_node).
 __device__ inline double rk_update(const StageCoef &c, double qref, double qs, double r)
 {
     if (c.b == 0.0) return fma(c.cdt, r, c.a * qref);
     const double y = fma(c.cdt, r, qs);
+    if (c.a == 0.0 && c.b == 1.0) return y;
+    return fma(c.b, y, c.a * qref);
+}
+
+// The same update when the element kernel has already formed y = q_s + cdt R
+// inside its contributions (b != 0; see box_finish_node's fold).
+__device__ inline double rk_update_folded(const StageCoef &c, double qref, double y)
+{
     if (c.a == 0.0 && c.b == 1.0) return y;
     return fma(c.b, y, c.a * qref);
 }
@@ -422,9 +431,15 @@ __device__ inline double rk_update(const StageCoef &c, double qref, double qs, d
 // (ez = nz - 1).  Indices are 32-bit: the mesh keeps n_local, n_unique < 2^31.
 // PLAIN: the output is the summed, mass-weighted and projected value itself
 // (the filter's DSS); qs and qn are not read.
+// fold: away from the walls the contributions are J w (q_s + cdt R) (the
+// element kernel has the stage state of its nodes at hand), so their mass-
+// weighted sum is y = q_s + cdt R itself, since the mass is the sum of the
+// copies' J w, and q_s is not read there; wall nodes carry J w R, as the
+// no-flux projection acts on R alone.
 struct BoxFin {
     int nx, ny, nz, walls;
     int ni, nj;
+    int fold;
 };
 
 template <int N, int SEG, typename T, bool PLAIN = false>
@@ -473,11 +488,13 @@ __device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin
     const double *qsi = qs + I, *qni = qn + I;
     double *qoi = qout + I;
     const double mi = p.Minv[I];
+    const bool wall = b.walls && ((ez == 0 && kl == 0) || kl == N);
+    const bool folded = !PLAIN && b.fold && !wall;
     double qsv[5] = {0, 0, 0, 0, 0}, qnv[5] = {0, 0, 0, 0, 0};
     if (!PLAIN)
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            qsv[v] = qsi[v * p.nu];
+            qsv[v] = folded ? 0.0 : qsi[v * p.nu];
             qnv[v] = sc.a == 0.0 ? 0.0 : qni[v * p.nu];
         }
     // copies of one z layer: the up to four (y, x) copies are loaded together
@@ -509,6 +526,11 @@ __device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) r[v] *= mi;
+    if (folded) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qoi[v * p.nu] = rk_update_folded(sc, qnv[v], r[v]);
+        return;
+    }
     noflux(p, I, r[1], r[2], r[3]);
 #pragma unroll
     for (int v = 0; v < 5; ++v) qoi[v * p.nu] = PLAIN ? r[v] : rk_update(sc, qnv[v], qsv[v], r[v]);

@@ -259,7 +259,14 @@ def test_step_equals_composition(torch_cuda, box4):
     qf = q0.clone()
     g.step(qf, 0.05, 1)
     a, b = p.host(qf), p.host(q3)
-    assert_groups(a - p.host(q0), b - p.host(q0), TOL64, "fused vs composed")
+    # The fused FP64 step folds q_s into the element contributions away from
+    # the walls (J w (q_s + cdt R), summed and multiplied by M^-1), so the two
+    # agree to rounding of the state rather than of the increment: the states
+    # within the FP64 bar, and within ~100 ulps of each group's largest value.
+    assert_groups(a, b, TOL64, "fused vs composed")
+    e = group_err(a, b)
+    print("fused vs composed, state", {k: "%.1e" % v for k, v in e.items()}, flush=True)
+    assert max(e.values()) <= 1e-14
 
 
 def test_step_resume_and_determinism_bitwise(torch_cuda, box4):
