@@ -388,7 +388,7 @@ static int32_t run_stage(numa_mesh_t m, int32_t prec, const numa::StageCoef &c, 
 {
     int32_t rc;
     if ((rc = mark(m, m->ev_elem, true, s))) return rc;
-    if ((rc = numa::launch_stage_elements(*m, prec, qs, s))) return rc;
+    if ((rc = numa::launch_stage_elements(*m, prec, c, qs, s))) return rc;
     if ((rc = mark(m, m->ev_elem, false, s))) return rc;
     if ((rc = mark(m, m->ev_fin, true, s))) return rc;
     if ((rc = numa::launch_stage_finish(*m, prec, c, qn, qs, qout, s))) return rc;

@@ -89,8 +89,11 @@ struct ShellFin {
     int64_t layer;    // elements of one layer times (N+1)^3
 };
 
+// fold: the contributions away from the bottom and top layers are
+// J w (q_s + cdt R) (k_rhs), so M^-1 times their sum is y = q_s + cdt R and
+// q_s is not read there (as in box_finish_node)
 template <int N, typename T, bool PLAIN = false>
-__global__ void k_shell_finish(PointArgs p, ShellFin sf, const T *ev, StageCoef c, const double *qn,
+__global__ void k_shell_finish(PointArgs p, ShellFin sf, const T *ev, StageCoef c, int fold, const double *qn,
                                const double *qs, double *qout)
 {
     constexpr int P = N + 1, PP = P * P;
@@ -101,16 +104,17 @@ __global__ void k_shell_finish(PointArgs p, ShellFin sf, const T *ev, StageCoef 
     const int32_t h = I - (int32_t)(gk * sf.fnh.d);
     const double *qsi = qs + I, *qni = qn + I;
     const double mi = p.Minv[I];
+    const int top = sf.nz * N;
+    const bool folded = !PLAIN && fold && gk != 0 && gk != (uint32_t)top;
     double qsv[5] = {0, 0, 0, 0, 0}, qnv[5] = {0, 0, 0, 0, 0};
     if (!PLAIN)
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            qsv[v] = qsi[v * p.nu];
+            qsv[v] = folded ? 0.0 : qsi[v * p.nu];
             qnv[v] = c.a == 0.0 ? 0.0 : qni[v * p.nu];
         }
     // radial copies: (layer, local k)
     int ez[2], kz[2], nzc = 1;
-    const int top = sf.nz * N;
     if (gk == (uint32_t)top) {
         ez[0] = sf.nz - 1;
         kz[0] = N;
@@ -144,8 +148,13 @@ __global__ void k_shell_finish(PointArgs p, ShellFin sf, const T *ev, StageCoef 
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) r[v] *= mi;
-    noflux(p, I, r[1], r[2], r[3]);
     double *qoi = qout + I;
+    if (folded) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) qoi[v * p.nu] = rk_update_folded(c, qnv[v], r[v]);
+        return;
+    }
+    noflux(p, I, r[1], r[2], r[3]);
 #pragma unroll
     for (int v = 0; v < 5; ++v) qoi[v * p.nu] = PLAIN ? r[v] : rk_update(c, qnv[v], qsv[v], r[v]);
 }
@@ -154,7 +163,7 @@ inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs
 
 template <typename T, bool PLAIN = false>
 void launch_shell_finish_t(Mesh &m, const T *ev, const StageCoef &c, const double *qn, const double *qs,
-                           double *qout, hipStream_t s)
+                           double *qout, hipStream_t s, int fold = 0)
 {
     ShellFin sf;
     sf.hoff = m.dv.hoff;
@@ -164,14 +173,14 @@ void launch_shell_finish_t(Mesh &m, const T *ev, const StageCoef &c, const doubl
     sf.layer = 6 * (int64_t)m.d.ne[0] * m.d.ne[0] * m.np;
     const dim3 grid(nblocks(m.nu, 256)), block(256);
     switch (m.N) {
-    case 1: hipLaunchKernelGGL((k_shell_finish<1, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, qn, qs, qout); break;
-    case 2: hipLaunchKernelGGL((k_shell_finish<2, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, qn, qs, qout); break;
-    case 3: hipLaunchKernelGGL((k_shell_finish<3, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, qn, qs, qout); break;
-    case 4: hipLaunchKernelGGL((k_shell_finish<4, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, qn, qs, qout); break;
-    case 5: hipLaunchKernelGGL((k_shell_finish<5, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, qn, qs, qout); break;
-    case 6: hipLaunchKernelGGL((k_shell_finish<6, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, qn, qs, qout); break;
-    case 7: hipLaunchKernelGGL((k_shell_finish<7, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, qn, qs, qout); break;
-    default: hipLaunchKernelGGL((k_shell_finish<8, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, qn, qs, qout); break;
+    case 1: hipLaunchKernelGGL((k_shell_finish<1, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, fold, qn, qs, qout); break;
+    case 2: hipLaunchKernelGGL((k_shell_finish<2, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, fold, qn, qs, qout); break;
+    case 3: hipLaunchKernelGGL((k_shell_finish<3, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, fold, qn, qs, qout); break;
+    case 4: hipLaunchKernelGGL((k_shell_finish<4, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, fold, qn, qs, qout); break;
+    case 5: hipLaunchKernelGGL((k_shell_finish<5, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, fold, qn, qs, qout); break;
+    case 6: hipLaunchKernelGGL((k_shell_finish<6, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, fold, qn, qs, qout); break;
+    case 7: hipLaunchKernelGGL((k_shell_finish<7, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, fold, qn, qs, qout); break;
+    default: hipLaunchKernelGGL((k_shell_finish<8, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, fold, qn, qs, qout); break;
     }
 }
 
@@ -215,7 +224,7 @@ int32_t launch_stage_finish(Mesh &m, int32_t prec, const StageCoef &c, const dou
         if (prec == NUMA_PREC_MIXED)
             launch_shell_finish_t<float>(m, m.dv.ev32, c, qn, qs, qout, s);
         else
-            launch_shell_finish_t<double>(m, m.dv.ev64, c, qn, qs, qout, s);
+            launch_shell_finish_t<double>(m, m.dv.ev64, c, qn, qs, qout, s, shell_folds(m, prec, c) ? 1 : 0);
         NUMA_HIP(hipGetLastError());
         return NUMA_OK;
     }

@@ -72,6 +72,8 @@ struct RhsArgs {
     const double *xi, *w, *Dd;  // FP64 GLL nodes, weights, derivative matrix
     BoxMetric bm;               // box: constants of the recomputed metric
     double eos[kEosTerms];      // coefficients of the binomial series of (1 + x)^gamma - 1
+    double cdt;                 // shell stage (fold != 0): the stage's cdt
+    int fold;                   // shell stage: J w (q_s + cdt R) away from the walls (k_shell_finish)
 };
 
 // Metric of a box element: stored per node (the general path), or recomputed

@@ -185,7 +185,13 @@ struct StepItem {
 bool box_batchable(const Mesh &m);
 int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int phase, hipStream_t s);
 
-int32_t launch_stage_elements(Mesh &m, int32_t prec, const double *qs, hipStream_t s);
+int32_t launch_stage_elements(Mesh &m, int32_t prec, const StageCoef &c, const double *qs, hipStream_t s);
+// the shell's FP64 stages that use q_s (b != 0) fold it into the node-major
+// contributions away from the bottom and top layers (k_rhs, k_shell_finish)
+inline bool shell_folds(const Mesh &m, int32_t prec, const StageCoef &c)
+{
+    return m.d.kind == NUMA_MESH_SHELL && prec != NUMA_PREC_MIXED && c.b != 0.0;
+}
 int32_t launch_stage_finish(Mesh &m, int32_t prec, const StageCoef &c, const double *qn, const double *qs,
                             double *qout, hipStream_t s);
 

@@ -33,14 +33,33 @@ __global__ __launch_bounds__(block_threads<N>()) void k_rhs(RhsArgs<T> a, TO *ou
     const int64_t e = xcd_remap(blockIdx.x, gridDim.x);
     const int l = threadIdx.x;
     NodeOut<T> o;
-    const bool act = element_rhs<N, T, SHELL, GEO>(a, e, l, s, o);
     if constexpr (NM) {
         static_assert(sizeof(TO) == sizeof(T), "node-major output is staged in the tile");
+        // element_rhs, with the node's state kept for the fold
+        NodeIn<T> in;
+        node_gather<N, T, SHELL, GEO>(a, e, l, in);
+        node_stage<N, T, SHELL, GEO>(a, e, l, in, s);
+        __syncthreads();
+        const bool act = l < NP;
+        if (act) {
+            T Di[N + 1], Dj[N + 1], Dk[N + 1];
+            d_rows<N, T>(a.D, l, Di, Dj, Dk);
+            node_derive<N, T, SHELL, GEO>(a, l, in, Di, Dj, Dk, s, o);
+        }
         __syncthreads();  // every lane has finished reading the tile
         TO *st = (TO *)&s[0][0];
         if (act) {
+            // J w R, or J w (q_s + cdt R) away from the bottom and top layers
+            const int ez = (int)fdiv((uint32_t)e, a.feh), k = l / ((N + 1) * (N + 1));
+            const bool wall = (ez == 0 && k == 0) || (ez == a.nz - 1 && k == N);
+            if (sizeof(T) == 8 && a.fold && !wall) {
+                const double qv[5] = {in.rp, in.u, in.v, in.w, in.tp};
 #pragma unroll
-            for (int v = 0; v < 5; ++v) st[l * 5 + v] = (TO)(o.Jw * o.R[v]);
+                for (int v = 0; v < 5; ++v) st[l * 5 + v] = (TO)(o.Jw * fma((T)a.cdt, o.R[v], (T)qv[v]));
+            } else {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) st[l * 5 + v] = (TO)(o.Jw * o.R[v]);
+            }
         }
         __syncthreads();
         TO *dst = out + e * (NP * 5);
@@ -50,6 +69,7 @@ __global__ __launch_bounds__(block_threads<N>()) void k_rhs(RhsArgs<T> a, TO *ou
             if (t < NP * 5) dst[t] = st[t];
         }
     } else {
+        const bool act = element_rhs<N, T, SHELL, GEO>(a, e, l, s, o);
         if (!act) return;
         TO *p = out + e * NP + l;
 #pragma unroll
@@ -81,9 +101,12 @@ void launch_n(Mesh &m, const RhsArgs<T> &a, TO *out, bool node_major, hipStream_
 }
 
 template <typename T, typename TO>
-void launch_t(Mesh &m, const T *met, const T *D, const double *q, TO *out, bool node_major, hipStream_t s)
+void launch_t(Mesh &m, const T *met, const T *D, const double *q, TO *out, bool node_major, hipStream_t s,
+              double cdt = 0.0, int fold = 0)
 {
     RhsArgs<T> a;
+    a.cdt = cdt;
+    a.fold = fold;
     a.G = m.dv.G;
     a.q = q;
     a.ref = m.dv.ref;
@@ -139,14 +162,14 @@ int32_t launch_rhs(Mesh &m, int32_t prec, const double *q, double *evec, hipStre
 
 // element half of a fused stage: contributions into the workspace E-vector
 // (FP32 on the mixed path)
-int32_t launch_stage_elements(Mesh &m, int32_t prec, const double *qs, hipStream_t s)
+int32_t launch_stage_elements(Mesh &m, int32_t prec, const StageCoef &c, const double *qs, hipStream_t s)
 {
     // the shell's finish reads node-major contributions, the generic one element-major
     const bool nm = m.d.kind == NUMA_MESH_SHELL;
     if (prec == NUMA_PREC_MIXED)
         launch_t<float, float>(m, m.dv.met32, m.dv.D32, qs, m.dv.ev32, nm, s);
     else
-        launch_t<double, double>(m, m.dv.met, m.dv.D64, qs, m.dv.ev64, nm, s);
+        launch_t<double, double>(m, m.dv.met, m.dv.D64, qs, m.dv.ev64, nm, s, c.cdt, shell_folds(m, prec, c) ? 1 : 0);
     NUMA_HIP(hipGetLastError());
     return NUMA_OK;
 }
