@@ -515,7 +515,7 @@ int32_t run_chunk(const StepItem *items, int n, int phase, hipStream_t s)
         it.qout = items[k].qout;
         it.qn = items[k].qn;
         it.ref = m.dv.ref;
-        it.Minv = m.dv.Minv;
+        it.Minv = stage_minv(m);
         it.nrm = m.dv.nrm;
         it.met = std::is_same<T, float>::value ? (const void *)m.dv.met32 : (const void *)m.dv.met;
         it.ev = items[k].ev;
@@ -577,7 +577,7 @@ int32_t run_plain_finish(const Mesh &m, const double *ev, double *q, hipStream_t
     B.cb = 1.0;
     BatchItem &it = B.it[0];
     it.qout = q;
-    it.Minv = m.dv.Minv;
+    it.Minv = stage_minv(m);  // the box filter's J w follows the metric mode
     it.nrm = m.dv.nrm;
     it.ev = (void *)ev;
     it.nu = m.nu;

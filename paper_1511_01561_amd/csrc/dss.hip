@@ -165,6 +165,8 @@ template <typename T, bool PLAIN = false>
 void launch_shell_finish_t(Mesh &m, const T *ev, const StageCoef &c, const double *qn, const double *qs,
                            double *qout, hipStream_t s, int fold = 0)
 {
+    PointArgs p = point_args(m);
+    if (!PLAIN) p.Minv = stage_minv(m);  // the shell filter takes the stored J w
     ShellFin sf;
     sf.hoff = m.dv.hoff;
     sf.hidx = m.dv.hidx;
@@ -173,22 +175,25 @@ void launch_shell_finish_t(Mesh &m, const T *ev, const StageCoef &c, const doubl
     sf.layer = 6 * (int64_t)m.d.ne[0] * m.d.ne[0] * m.np;
     const dim3 grid(nblocks(m.nu, 256)), block(256);
     switch (m.N) {
-    case 1: hipLaunchKernelGGL((k_shell_finish<1, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, fold, qn, qs, qout); break;
-    case 2: hipLaunchKernelGGL((k_shell_finish<2, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, fold, qn, qs, qout); break;
-    case 3: hipLaunchKernelGGL((k_shell_finish<3, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, fold, qn, qs, qout); break;
-    case 4: hipLaunchKernelGGL((k_shell_finish<4, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, fold, qn, qs, qout); break;
-    case 5: hipLaunchKernelGGL((k_shell_finish<5, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, fold, qn, qs, qout); break;
-    case 6: hipLaunchKernelGGL((k_shell_finish<6, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, fold, qn, qs, qout); break;
-    case 7: hipLaunchKernelGGL((k_shell_finish<7, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, fold, qn, qs, qout); break;
-    default: hipLaunchKernelGGL((k_shell_finish<8, T, PLAIN>), grid, block, 0, s, point_args(m), sf, ev, c, fold, qn, qs, qout); break;
+    case 1: hipLaunchKernelGGL((k_shell_finish<1, T, PLAIN>), grid, block, 0, s, p, sf, ev, c, fold, qn, qs, qout); break;
+    case 2: hipLaunchKernelGGL((k_shell_finish<2, T, PLAIN>), grid, block, 0, s, p, sf, ev, c, fold, qn, qs, qout); break;
+    case 3: hipLaunchKernelGGL((k_shell_finish<3, T, PLAIN>), grid, block, 0, s, p, sf, ev, c, fold, qn, qs, qout); break;
+    case 4: hipLaunchKernelGGL((k_shell_finish<4, T, PLAIN>), grid, block, 0, s, p, sf, ev, c, fold, qn, qs, qout); break;
+    case 5: hipLaunchKernelGGL((k_shell_finish<5, T, PLAIN>), grid, block, 0, s, p, sf, ev, c, fold, qn, qs, qout); break;
+    case 6: hipLaunchKernelGGL((k_shell_finish<6, T, PLAIN>), grid, block, 0, s, p, sf, ev, c, fold, qn, qs, qout); break;
+    case 7: hipLaunchKernelGGL((k_shell_finish<7, T, PLAIN>), grid, block, 0, s, p, sf, ev, c, fold, qn, qs, qout); break;
+    default: hipLaunchKernelGGL((k_shell_finish<8, T, PLAIN>), grid, block, 0, s, p, sf, ev, c, fold, qn, qs, qout); break;
     }
 }
 
 }  // namespace
 
-int32_t launch_dss(Mesh &m, int32_t nvar, const double *cin, double *out, int32_t flags, hipStream_t s)
+int32_t launch_dss(Mesh &m, int32_t nvar, const double *cin, double *out, int32_t flags, hipStream_t s,
+                   const double *minv)
 {
-    hipLaunchKernelGGL(k_dss, dim3(nblocks(m.nu, 256)), dim3(256), 0, s, point_args(m), nvar, cin, out, flags);
+    PointArgs p = point_args(m);
+    if (minv) p.Minv = minv;
+    hipLaunchKernelGGL(k_dss, dim3(nblocks(m.nu, 256)), dim3(256), 0, s, p, nvar, cin, out, flags);
     NUMA_HIP(hipGetLastError());
     return NUMA_OK;
 }
@@ -228,12 +233,14 @@ int32_t launch_stage_finish(Mesh &m, int32_t prec, const StageCoef &c, const dou
         NUMA_HIP(hipGetLastError());
         return NUMA_OK;
     }
+    PointArgs p = point_args(m);
+    p.Minv = stage_minv(m);
     if (prec == NUMA_PREC_MIXED)
-        hipLaunchKernelGGL(k_stage_finish<float>, dim3(nblocks(m.nu, 256)), dim3(256), 0, s, point_args(m), m.dv.own,
-                           m.dv.toff, m.dv.tidx, m.dv.ev32, c, qn, qs, qout);
+        hipLaunchKernelGGL(k_stage_finish<float>, dim3(nblocks(m.nu, 256)), dim3(256), 0, s, p, m.dv.own, m.dv.toff,
+                           m.dv.tidx, m.dv.ev32, c, qn, qs, qout);
     else
-        hipLaunchKernelGGL(k_stage_finish<double>, dim3(nblocks(m.nu, 256)), dim3(256), 0, s, point_args(m), m.dv.own,
-                           m.dv.toff, m.dv.tidx, m.dv.ev64, c, qn, qs, qout);
+        hipLaunchKernelGGL(k_stage_finish<double>, dim3(nblocks(m.nu, 256)), dim3(256), 0, s, p, m.dv.own, m.dv.toff,
+                           m.dv.tidx, m.dv.ev64, c, qn, qs, qout);
     NUMA_HIP(hipGetLastError());
     return NUMA_OK;
 }

@@ -254,7 +254,7 @@ int32_t launch_filter(Mesh &m, double order, int32_t cutoff, double *q, hipStrea
     NUMA_HIP(hipGetLastError());
     if (shell) return launch_shell_plain_finish(m, m.dv.ev64, q, s);
     if (nm) return launch_box_plain_finish(m, m.dv.ev64, q, s);
-    return launch_dss(m, 5, m.dv.ev64, q, NUMA_DSS_MASS | NUMA_DSS_NOFLUX, s);
+    return launch_dss(m, 5, m.dv.ev64, q, NUMA_DSS_MASS | NUMA_DSS_NOFLUX, s, stage_minv(m));
 }
 
 }  // namespace numa

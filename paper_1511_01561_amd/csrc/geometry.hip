@@ -227,6 +227,32 @@ __global__ void k_mass(GeoParams g, const int32_t *off, const int32_t *idx, cons
     Minv[I] = 1.0 / s;
 }
 
+// Inverse mass of the recomputed metric: per unique node, the sum over its
+// copies (ascending, as k_mass) of the J w that the recomputed-metric element
+// kernels form, the same products: box c0 w_k (column factor c0 of the
+// element's (i, j) column), shell (column factor 9) x (layer factor 2).
+__global__ void k_mass_recomputed(GeoParams g, const int32_t *off, const int32_t *idx, const double *hcol,
+                                  const double *scol, const double *slay, double *MinvR)
+{
+    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= g.nu) return;
+    const int PP = g.P * g.P;
+    double s = 0.0;
+    for (int32_t c = off[I]; c < off[I + 1]; ++c) {
+        const int64_t cc = idx[c];
+        const int64_t e = cc / g.np;
+        const int l = (int)(cc - e * g.np), ij = l % PP, k = l / PP;
+        if (g.kind == NUMA_MESH_BOX) {
+            const int64_t ex = e % g.nex, ey = (e / g.nex) % g.ney;
+            s += hcol[(ex + g.nex * ey) * (4 * PP) + ij] * g.w[k];
+        } else {
+            const int64_t neh = 6 * (int64_t)g.nex * g.nex, eh = e % neh, ez = e / neh;
+            s += scol[eh * (13 * PP) + 9 * PP + ij] * slay[4 * (ez * g.P + k) + 2];
+        }
+    }
+    MinvR[I] = 1.0 / s;
+}
+
 __global__ void k_unique_coords(GeoParams g, const int32_t *hlat, double *xu)
 {
     int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -526,6 +552,8 @@ int32_t launch_geometry(Mesh &m, hipStream_t s)
         hipLaunchKernelGGL(k_shell_layers, dim3(nblocks((int64_t)g.nez * m.P, bs)), dim3(bs), 0, s, g, m.ph.g0,
                            v.slay);
     }
+    hipLaunchKernelGGL(k_mass_recomputed, dim3(nblocks(m.nu, bs)), dim3(bs), 0, s, g, v.off, v.idx, v.hcol, v.scol,
+                       v.slay, v.MinvR);
     NUMA_HIP(hipGetLastError());
     int hbad = 0;
     NUMA_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));

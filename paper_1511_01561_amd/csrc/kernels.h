@@ -369,6 +369,15 @@ struct PointArgs {
     int walls;
 };
 
+// The inverse mass that matches the J w of the mesh's element kernels: with
+// the recomputed metric they form J w from the column (and layer) factors,
+// and the stages, and the box filter, which takes J w the same way, divide by
+// the sum of those (MinvR); otherwise by the sum of the stored J w.
+inline const double *stage_minv(const Mesh &m)
+{
+    return m.metric_mode == NUMA_METRIC_RECOMPUTE ? m.dv.MinvR : m.dv.Minv;
+}
+
 inline PointArgs point_args(const Mesh &m)
 {
     PointArgs p;
@@ -437,7 +446,10 @@ __device__ inline double rk_update_folded(const StageCoef &c, double qref, doubl
 // element kernel has the stage state of its nodes at hand), so their mass-
 // weighted sum is y = q_s + cdt R itself, since the mass is the sum of the
 // copies' J w, and q_s is not read there; wall nodes carry J w R, as the
-// no-flux projection acts on R alone.
+// no-flux projection acts on R alone.  The mass must then sum the same J w
+// as the contributions: with the recomputed metric p.Minv is MinvR (the
+// stored isoparametric J w differs from c0 w_k by ~1e-14, which the fold
+// would apply to the state at every stage).
 struct BoxFin {
     int nx, ny, nz, walls;
     int ni, nj;

@@ -288,6 +288,7 @@ uint64_t layout_workspace(Mesh &m, int32_t prec_mask, char *base)
     v.ref = (double *)take(24ull * m.nu);
     v.M = (double *)take(8ull * m.nu);
     v.Minv = (double *)take(8ull * m.nu);
+    v.MinvR = (double *)take(8ull * m.nu);
     if (m.d.kind == NUMA_MESH_SHELL) v.grav = (double *)take(24ull * m.nu);
     v.nrm = (double *)take(48ull * m.nh);
     v.xu = (double *)take(24ull * m.nu);

@@ -79,6 +79,8 @@ struct DeviceView {
     double *ref = nullptr;     // [3][n_unique] rho_bar, theta_bar, p_bar
     double *M = nullptr;       // [n_unique]
     double *Minv = nullptr;    // [n_unique]
+    double *MinvR = nullptr;   // [n_unique] 1 / (sum of the copies' recomputed J w): the mass of the
+                               // recomputed metric's kernels (box: c0 w_k; shell: column x layer factor)
     double *grav = nullptr;    // shell: [3][n_unique]
     double *nrm = nullptr;     // [2][3][n_horiz] bottom and top wall normals
     double *xu = nullptr;      // [3][n_unique] unique coordinates
@@ -149,7 +151,9 @@ int32_t launch_geometry(Mesh &m, hipStream_t s);
 int32_t launch_export(Mesh &m, int32_t what, void *out, hipStream_t s);
 int32_t launch_init_state(Mesh &m, const numa_ic &ic, const double *noise, double *q, hipStream_t s);
 int32_t launch_rhs(Mesh &m, int32_t prec, const double *q, double *evec, hipStream_t s);
-int32_t launch_dss(Mesh &m, int32_t nvar, const double *cin, double *out, int32_t flags, hipStream_t s);
+// minv: the inverse mass applied with NUMA_DSS_MASS (null: the stored metric's M^-1)
+int32_t launch_dss(Mesh &m, int32_t nvar, const double *cin, double *out, int32_t flags, hipStream_t s,
+                   const double *minv = nullptr);
 void filter_sigma(int N, double order, int32_t cutoff, double *sigma);
 void filter_matrix(int N, const double *xi, const double *w, double order, int32_t cutoff, double *F);
 int32_t launch_filter(Mesh &m, double order, int32_t cutoff, double *q, hipStream_t s);

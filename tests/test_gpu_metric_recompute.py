@@ -220,3 +220,27 @@ def test_full_size_largest_order(torch_cuda, oracle_mod):
     e = group_err(p.host(qm) - q0, qo - q0)
     print("N=8 full-size mixed increment", {k: "%.1e" % v for k, v in e.items()})
     assert max(e.values()) < 1e-4
+
+
+@pytest.mark.parametrize("which", ["box4", "box8", "shell4"])
+def test_folded_stages_keep_the_state_at_zero_dt(torch_cuda, which):
+    """FP64 stages fold q_s into the contributions (J w (q_s + cdt R)); with
+    dt = 0 a step returns M^-1 sum(J w q_s), which is q_s to rounding only if
+    the mass is formed from the same J w as the contributions.  With the
+    recomputed metric that is J w from the column (and layer) factors, not
+    the stored isoparametric J w, which differs from it by ~1e-14 and would
+    scale the state by that much at every stage (60 stages here: 1e-13 at
+    N = 4, 2e-13 at N = 8 against ~3e-15 with the consistent mass)."""
+    from paper_1511_01561_amd import numa
+    from test_gpu_parity import small_shell
+    wl = {"box4": terrain_box(4), "box8": terrain_box(8), "shell4": small_shell(4)}[which]
+    for metric in (numa.METRIC_STORED, numa.METRIC_RECOMPUTE):
+        g = numa.Mesh(wl["mesh"], wl["phys"], prec_mask=1)
+        g.set_metric(metric)
+        q = g.init_state(wl["ic"], inputs.device_noise(g.n_unique, 5) if which != "shell4" else None)
+        q0 = q.clone()
+        g.step(q, 0.0, 20)
+        a, b = q.cpu().numpy(), q0.cpu().numpy()
+        e = group_err(a, b)
+        print(which, "metric", metric, {k: "%.1e" % v for k, v in e.items()}, flush=True)
+        assert max(e.values()) <= 2e-14, (which, metric, e)
