@@ -219,9 +219,12 @@ int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn,
  * element kernel writes every element-local node's contribution J w R
  * (node-major: a copy's five values together); the finish kernel sums the
  * copies of each unique node, applies M^-1, the wall projection and the
- * update.  Uses the workspace scratch; equals the composition of numa_rhs,
- * numa_dss and numa_rk_stage up to rounding (the copies may be summed in
- * another order).
+ * update.  In FP64 (box and shell; not the generic box path) the contribution
+ * away from the walls is J w (q_s + c dt R), so that the finish need not read
+ * q_s there; with the recomputed metric M is then the sum of the recomputed
+ * J w.  Uses the workspace scratch; equals the composition of numa_rhs,
+ * numa_dss and numa_rk_stage up to rounding of the state (the copies may be
+ * summed in another order, and q_s enters through the weighted sum).
  * With a filter set on the mesh (numa_mesh_set_filter) every step ends with
  * numa_filter (Code example 1: the filter follows the stages).
  * The stream must not run other work on q or the workspace meanwhile. */
