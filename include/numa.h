@@ -219,7 +219,8 @@ int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn,
  * element kernel writes every element-local node's contribution J w R
  * (node-major: a copy's five values together); the finish kernel sums the
  * copies of each unique node, applies M^-1, the wall projection and the
- * update.  In FP64 (box and shell; not the generic box path) the contribution
+ * update.  In FP64 (box and shell; not the generic box path, nor the box at
+ * N = 5, 6 with the recomputed metric) the contribution
  * away from the walls is J w (q_s + c dt R), so that the finish need not read
  * q_s there; with the recomputed metric M is then the sum of the recomputed
  * J w.  Uses the workspace scratch; equals the composition of numa_rhs,
