@@ -512,8 +512,8 @@ __device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin
             qnv[v] = sc.a == 0.0 ? 0.0 : qni[v * p.nu];
         }
     // copies of one z layer: the up to four (y, x) copies are loaded together
-    // (absent ones re-read the first copy and count zero), so a node waits
-    // for one round trip per z layer instead of one per copy
+    // (absent ones are not loaded and count zero), so a node waits for one
+    // round trip per z layer instead of one per copy
     if (nxc == 1) { cx[1] = cx[0]; lx[1] = lx[0]; }
     if (nyc == 1) { cy[1] = cy[0]; ly[1] = ly[0]; }
     double r[5] = {0, 0, 0, 0, 0};
@@ -526,8 +526,13 @@ __device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin
                 const int32_t e = cx[x] + b.nx * (cy[y] + b.ny * cz[z]);
                 const int32_t cc = e * NP + lx[x] + P * (ly[y] + P * lz[z]);
                 const T *src = ev + (int64_t)cc * 5;  // node-major [n_local][5]
+                if (y < nyc && x < nxc) {
 #pragma unroll
-                for (int v = 0; v < 5; ++v) c[2 * y + x][v] = src[v];
+                    for (int v = 0; v < 5; ++v) c[2 * y + x][v] = src[v];
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) c[2 * y + x][v] = (T)0;
+                }
             }
 #pragma unroll
         for (int y = 0; y < 2; ++y)
