@@ -80,7 +80,8 @@ __global__ void k_stage_finish(PointArgs p, const int32_t *own, const int32_t *t
 // bottom layer (hoff/hidx, 1 to 4, ascending) times its radial copies (local
 // k = 0 of layer gk/N and k = N of the layer below on a layer boundary, else
 // one).  The contributions are node-major [n_local][5]; the up to four
-// horizontal copies of one radial copy are loaded together.  PLAIN: the
+// horizontal copies of one radial copy are loaded together (absent ones are
+// not loaded).  PLAIN: the
 // output is the summed, mass-weighted, projected value (the filter's DSS).
 struct ShellFin {
     const int32_t *hoff, *hidx;
@@ -138,8 +139,13 @@ __global__ void k_shell_finish(PointArgs p, ShellFin sf, const T *ev, StageCoef 
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const T *src = ev + (base + hc[q]) * 5;
+            if (q < hn) {  // absent copies are not loaded
 #pragma unroll
-            for (int v = 0; v < 5; ++v) c[q][v] = src[v];
+                for (int v = 0; v < 5; ++v) c[q][v] = src[v];
+            } else {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) c[q][v] = (T)0;
+            }
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
