@@ -142,8 +142,10 @@ int32_t numa_mesh_attach_workspace(numa_mesh_t m, void *dev_ptr, uint64_t bytes,
  * computes element-local coordinates, the metric terms and J w by derivative
  * contractions of the coordinates (isoparametric), the mass matrix
  * M_I = sum_e w_ijk J^e (Eq. (discstrongform)) and its inverse, the reference
- * state, gravity, wall normals and (box) the column factors of the
- * recomputed metric, into the workspace.  Asynchronous. */
+ * state, gravity, wall normals, the column (and, shell, layer) factors of
+ * the recomputed metric and the inverse of the mass summed from the
+ * recomputed J w (used by the stages in NUMA_METRIC_RECOMPUTE mode), into
+ * the workspace.  Asynchronous. */
 int32_t numa_geometry(numa_mesh_t m, const numa_phys *ph, void *stream);
 
 /* Metric terms of the element kernels (numa_rhs, numa_step, numa_step_batch).
