@@ -172,9 +172,13 @@ constexpr int col_eb()
 }
 template <int N, typename T>
 constexpr int col_threads() { return ((col_eb<N, T>() * (N + 1) * (N + 1) + 63) / 64) * 64; }
+// workgroups per CU the column kernel is compiled for: in FP32 at N = 4 the
+// tile (40 KB) lets four share a CU if the registers fit 4 waves per SIMD
+template <int N, typename T>
+constexpr int col_blocks() { return (sizeof(T) == 4 && N == 4) ? 4 : 1; }
 
 template <int N, typename T>
-__global__ __launch_bounds__((col_threads<N, T>())) void k_elem_col(Batch B)
+__global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T>())) void k_elem_col(Batch B)
 {
     constexpr int P = N + 1, PP = P * P, NP = PP * P, EB = col_eb<N, T>(), BT = col_threads<N, T>();
     __shared__ T s[EB][8][NP];
