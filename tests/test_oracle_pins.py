@@ -218,6 +218,157 @@ def test_shell_mass_converges_to_volume(oracle_mod):
 
 
 # --------------------------------------------------------------------------
+# Terrain-following box geometry (Sec. "Spatial Discretization": isoparametric
+# hexahedra; Eq. (derivatives): the metric terms).  Everything the pins below
+# compare with is computed here from the map itself, with GLL nodes taken as
+# numpy's roots of P'_N, never from the oracle's arrays.
+# --------------------------------------------------------------------------
+TERRAIN = dict(nx=4, ny=4, nz=3, N=4, Lx=4.0e4, Ly=3.0e4, H=6.0e3, h0=500.0)
+
+
+def _numpy_gll_nodes(N):
+    inner = np.sort(npleg.Legendre.basis(N).deriv().roots().real)
+    return np.concatenate([[-1.0], inner, [1.0]])
+
+
+def _terrain(x, y, t=TERRAIN):
+    """h(x, y) of the map and its gradient"""
+    kx, ky = 2 * math.pi / t["Lx"], 2 * math.pi / t["Ly"]
+    h = t["h0"] * np.sin(kx * x) * np.sin(ky * y)
+    return h, t["h0"] * kx * np.cos(kx * x) * np.sin(ky * y), t["h0"] * ky * np.sin(kx * x) * np.cos(ky * y)
+
+
+def _terrain_unique_coords(t=TERRAIN):
+    """unique-node coordinates of the terrain box in canonical order
+    (x fastest; x, y periodic, so the lattice stops one point short of Lx, Ly):
+    x = Lx (ex + (1 + xi_i)/2)/nx and likewise y, z; z' = z + h(x, y)(1 - z/H)"""
+    N, nx, ny, nz = t["N"], t["nx"], t["ny"], t["nz"]
+    xi = _numpy_gll_nodes(N)
+
+    def axis(n, L, closed):
+        c = np.arange(n * N + (1 if closed else 0))
+        e = np.minimum(c // N, n - 1)
+        return L * (e + (1 + xi[c - N * e]) / 2) / n
+
+    ax, ay, az = axis(nx, t["Lx"], False), axis(ny, t["Ly"], False), axis(nz, t["H"], True)
+    z, y, x = np.meshgrid(az, ay, ax, indexing="ij")
+    x, y, z = x.ravel(), y.ravel(), z.ravel()
+    h = _terrain(x, y, t)[0]
+    return x, y, z + h * (1 - z / t["H"])
+
+
+def _terrain_box(oracle_mod, phys=None, N=None):
+    t = TERRAIN
+    return oracle_mod.OracleMesh(0, N or t["N"], (t["nx"], t["ny"], t["nz"]), (1, 1, 0), (t["Lx"], t["Ly"], t["H"]),
+                                 t["h0"], phys or PHYS)
+
+
+def test_terrain_coordinates_follow_the_map(oracle_mod):
+    m = _terrain_box(oracle_mod)
+    x, y, z = _terrain_unique_coords()
+    xu = m.get("xu")
+    assert xu.shape[1] == x.size
+    np.testing.assert_allclose(xu[0], x, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(xu[1], y, rtol=0, atol=1e-9)
+    np.testing.assert_allclose(xu[2], z, rtol=0, atol=1e-9)
+    # the terrain is really there: the bottom layer is not flat
+    assert np.ptp(xu[2][:m.n_horiz]) > 1.9 * TERRAIN["h0"]
+
+
+def _seam_free_mask(m, t=TERRAIN):
+    """element-local mask of the elements that do not touch the periodic seam:
+    there a field linear in the wrapped unique coordinates is not linear in the
+    element's own coordinates"""
+    e = np.arange(m.n_elem)
+    ok = (e % t["nx"] < t["nx"] - 1) & ((e // t["nx"]) % t["ny"] < t["ny"] - 1)
+    return np.repeat(ok, m.np)
+
+
+def test_terrain_linear_theta_is_advected_exactly(oracle_mod):
+    """theta' linear in the physical coordinates is in the isoparametric
+    element's interpolation space, so the chain rule through the terrain
+    metric (zeta_x, zeta_y from z_xi, z_eta) gives its exact gradient at every
+    node: with constant u, g0 = 0 and rho' = -rho_bar theta'/(theta_bar + theta')
+    (p' = 0), R_theta' = -u.grad(theta') = -(u b + v c + w d)."""
+    t = TERRAIN
+    m = _terrain_box(oracle_mod, phys=dict(PHYS, g0=0.0))
+    x, y, z = _terrain_unique_coords()
+    b, c, d = 0.3 / t["Lx"], -0.2 / t["Ly"], 0.4 / t["H"]
+    tp = 0.1 + b * x + c * y + d * z
+    u, v, w = 3.0, -2.0, 0.5
+    rb, tb, _ = m.get("ref")
+    q = np.stack([-rb * tp / (tb + tp), np.full_like(tp, u), np.full_like(tp, v), np.full_like(tp, w), tp])
+    R = m.rhs(q) / m.get("metric")[9]
+    mask = _seam_free_mask(m)
+    exact = -(u * b + v * c + w * d)
+    assert np.max(np.abs(R[4][mask] - exact)) < 1e-12 * abs(exact)
+    # the same field differentiated along z only would be off by the terrain slope
+    assert abs(exact + w * d) > 0.5 * abs(exact)
+
+
+def test_terrain_linear_velocity_is_differentiated_exactly(oracle_mod):
+    """u, v, w linear in the physical coordinates, rho' = theta' = 0, g0 = 0
+    (constant rho_bar): R_u = -(u.grad)u and R_rho' = -rho_bar div(u) exactly,
+    with every entry of the velocity gradient non-zero, so that each metric
+    term (xi_x, eta_y, zeta_x, zeta_y, zeta_z) enters."""
+    t = TERRAIN
+    m = _terrain_box(oracle_mod, phys=dict(PHYS, g0=0.0))
+    x, y, z = _terrain_unique_coords()
+    G = np.array([[0.7 / t["Lx"], -0.4 / t["Ly"], 0.9 / t["H"]],
+                  [0.3 / t["Lx"], 0.5 / t["Ly"], -0.6 / t["H"]],
+                  [-0.2 / t["Lx"], 0.8 / t["Ly"], 0.35 / t["H"]]])  # G[a, c] = d u_a / d x_c
+    u0 = np.array([2.0, -1.5, 0.4])
+    X = np.stack([x, y, z])
+    vel = u0[:, None] + G @ X
+    q = np.zeros((5, m.n_unique))
+    q[1:4] = vel
+    R = m.rhs(q) / m.get("metric")[9]
+    mask = _seam_free_mask(m)
+    Gm = m.get("gather").ravel()[mask]
+    rb = m.get("ref")[0][Gm]
+    assert np.ptp(rb) == 0.0  # g0 = 0: constant reference density
+    exact_u = -(G @ vel)  # -(u.grad) u_a = -sum_c u_c G[a, c]
+    for a in range(3):
+        ex = exact_u[a][Gm]
+        assert np.max(np.abs(R[1 + a][mask] - ex)) < 1e-12 * np.max(np.abs(ex)), a
+    ex0 = -rb * np.trace(G)
+    assert np.max(np.abs(R[0][mask] - ex0)) < 1e-12 * np.max(np.abs(ex0))
+
+
+def test_terrain_bottom_normal_is_the_analytic_terrain_normal(oracle_mod):
+    """bottom wall: n = (-h_x, -h_y, 1)/|.| of the map's terrain; top: +z"""
+    m = _terrain_box(oracle_mod)
+    x, y, _ = _terrain_unique_coords()
+    nrm, isb = m.get("normals"), m.get("isbnd").astype(bool)
+    nh = m.n_horiz
+    _, hx, hy = _terrain(x[:nh], y[:nh])
+    s = np.sqrt(hx * hx + hy * hy + 1.0)
+    np.testing.assert_allclose(nrm[:, :nh], np.stack([-hx / s, -hy / s, 1.0 / s]), rtol=0, atol=1e-13)
+    np.testing.assert_allclose(nrm[:, -nh:], np.tile([[0.0], [0.0], [1.0]], (1, nh)), rtol=0, atol=0)
+    assert isb[:nh].all() and isb[-nh:].all() and not isb[nh:-nh].any()
+    assert np.max(np.abs(nrm[0, :nh])) > 0.05  # the slope is resolved, not negligible
+
+
+def test_terrain_bottom_normal_matches_grad_zeta(oracle_mod):
+    """The bottom surface of the isoparametric mesh has normal grad(zeta)/|.|
+    (zeta = -1 there), taken from the oracle's metric; it converges
+    spectrally in N to the wall normal the no-flux projection uses."""
+    errs = []
+    for N in (2, 4, 6, 8):
+        m = _terrain_box(oracle_mod, N=N)
+        met, G = m.get("metric"), m.get("gather").ravel()
+        nrm = m.get("normals")
+        P = N + 1
+        k = (np.arange(m.n_local) % m.np) // (P * P)
+        bottom = (k == 0) & (G < m.n_horiz)
+        gz = met[6:9][:, bottom]
+        gz = gz / np.sqrt((gz ** 2).sum(0))
+        errs.append(np.max(np.abs(gz - nrm[:, G[bottom]])))
+    assert errs[3] < errs[2] < errs[1] < errs[0]
+    assert errs[3] < 1e-6
+
+
+# --------------------------------------------------------------------------
 # Reference state: hydrostatic balance and the equation of state
 # --------------------------------------------------------------------------
 def test_isentropic_reference_is_hydrostatic(oracle_mod):
