@@ -233,6 +233,20 @@ int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn,
  * The stream must not run other work on q or the workspace meanwhile. */
 int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double *q, void *stream);
 
+/* The right-hand side of the time loop as numa_step's fused stage computes
+ * it (Code example 1: create_rhs, then DSS and multiplication with the
+ * inverse mass matrix; Eq. (discstrongform) with the DSS weights of the text
+ * after Eq. (derivatives)): r [5][n_unique] (device, FP64) = M^-1 times the
+ * sum over the copies of each unique node of J w R, with the wall-normal part
+ * of components 1..3 removed at the no-flux walls.  It runs the same element
+ * and finish kernels as numa_step (the kernel choice by order, metric mode and
+ * precision; the copies summed in the same order; M^-1 of the same J w), as a
+ * stage whose update is the identity on R, so no kernel folds a state into the
+ * contributions.  Equals numa_dss(numa_rhs(q), NUMA_DSS_MASS | NUMA_DSS_NOFLUX)
+ * up to rounding.  prec as for numa_rhs.  r may alias q.  Uses the workspace
+ * scratch like numa_step (calls on one mesh on different streams race). */
+int32_t numa_stage_rhs(numa_mesh_t m, int32_t prec, const double *q, double *r, void *stream);
+
 /* 1D-IMEX (Sec. "Time Discretization": implicit corrections along the vertical
  * columns after an explicit leap-frog step; Code example 1: IMEX corrections
  * per vertical column), nsteps steps on the pair (qprev = q^{n-1},

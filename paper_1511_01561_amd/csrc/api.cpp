@@ -486,6 +486,28 @@ int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double
     return NUMA_OK;
 }
 
+int32_t numa_stage_rhs(numa_mesh_t m, int32_t prec, const double *q, double *r, void *stream)
+{
+    int32_t rc = need_ready(m, "numa_stage_rhs");
+    if (rc) return rc;
+    if ((rc = check_prec(m, prec, "numa_stage_rhs"))) return rc;
+    if (!q || !r) {
+        set_error("numa_stage_rhs: null argument");
+        return NUMA_EINVAL;
+    }
+    hipStream_t s = as_stream(stream);
+    // a stage whose update is q_out = 0 q_ref + 1 R (b = 0: no q_s term, so no
+    // kernel folds q_s into the contributions): the summed, mass-weighted,
+    // projected right-hand side itself
+    const numa::StageCoef c{0.0, 0.0, 1.0};
+    if (numa::box_batchable(*m)) {
+        void *ev = prec == NUMA_PREC_MIXED ? (void *)m->dv.ev32 : (void *)m->dv.ev64;
+        numa::StepItem it = {m, q, q, r, ev, c};
+        return run_batch_stage(&it, 1, prec, s);
+    }
+    return run_stage(m, prec, c, q, q, r, s);
+}
+
 int32_t numa_imex_step(numa_mesh_t m, int32_t prec, double dt, double ra, int32_t nsteps, double *qprev,
                        double *qcur, void *stream)
 {

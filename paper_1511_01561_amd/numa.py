@@ -28,7 +28,7 @@ EXPORTED = ["numa_last_error", "numa_gll", "numa_mesh_create", "numa_mesh_destro
             "numa_rk_stage", "numa_step", "numa_profile", "numa_profile_read", "numa_step_scratch_bytes",
             "numa_step_batch", "numa_batch_capture", "numa_graph_launch", "numa_graph_destroy",
             "numa_mesh_set_metric", "numa_filter", "numa_filter_matrix", "numa_mesh_set_filter",
-            "numa_mesh_set_integrator", "numa_imex_step"]
+            "numa_mesh_set_integrator", "numa_imex_step", "numa_stage_rhs"]
 
 
 class numa_mesh_desc(ct.Structure):
@@ -89,6 +89,7 @@ def lib():
         "numa_mesh_set_integrator": (I32, [P, I32]),
         "numa_imex_step": (I32, [P, I32, D, D, I32, P, P, P]),
         "numa_step": (I32, [P, I32, D, I32, P, P]),
+        "numa_stage_rhs": (I32, [P, I32, P, P, P]),
         "numa_profile": (I32, [P, I32]),
         "numa_profile_read": (I32, [P, P]),
         "numa_step_scratch_bytes": (I32, [P, I32, ct.POINTER(ct.c_uint64)]),
@@ -216,6 +217,13 @@ class Mesh:
         if out is None:
             out = self._empty(5, self.n_local)
         check(lib().numa_rhs(self._h, prec, _ptr(q), _ptr(out), _stream(stream)))
+        return out
+
+    def stage_rhs(self, q, prec=PREC_FP64, out=None, stream=None):
+        """M^-1 DSS(J w R) with the wall projection, by numa_step's stage kernels."""
+        if out is None:
+            out = self._empty(5, self.n_unique)
+        check(lib().numa_stage_rhs(self._h, prec, _ptr(q), _ptr(out), _stream(stream)))
         return out
 
     def dss(self, c_elem, flags=DSS_MASS, out=None, stream=None):

@@ -3,13 +3,13 @@ and the shell: the explicit leap-frog stage, the per-line vertical solve (the
 library eliminates rho' and theta' and solves a band system for the vertical
 velocity; the oracle solves each line's full system densely) and the
 Robert-Asselin filter.  FP64 states within 1e-12 relative
-max-norm per variable group; the mixed-precision explicit stage within 1e-4
+max-norm per variable group; the mixed-precision explicit stage within 1e-5
 of the increment."""
 import numpy as np
 import pytest
 
 from paper_1511_01561_amd import inputs
-from test_gpu_parity import TOL64, Pair, assert_groups, group_err, small_shell
+from test_gpu_parity import TOL64, TOLMIX, Pair, assert_groups, group_err, small_shell
 
 pytestmark = pytest.mark.gpu
 
@@ -79,7 +79,7 @@ def test_imex_mixed_precision_explicit_stage(torch_cuda, oracle_mod):
     q0, (_, ob), (_, gb) = imex_case(p, 0.1, 0.05, 2, 30, prec=numa.PREC_MIXED)
     e = group_err(gb - q0, ob - q0)
     print("imex mixed increment", {k: "%.1e" % v for k, v in e.items()}, flush=True)
-    assert max(e.values()) <= 1e-4
+    assert max(e.values()) <= TOLMIX
 
 
 def test_imex_stable_beyond_the_vertical_acoustic_limit(torch_cuda, oracle_mod):

@@ -177,7 +177,7 @@ def test_step_parity_all_orders_recomputed_metric(torch_cuda, oracle_mod, N, ne,
     p.g.step(qm, 0.05, 2, prec=numa.PREC_MIXED)
     e = group_err(p.host(qm) - q0, qo - q0)
     print("recomputed mixed 2-step increment", {k: "%.1e" % v for k, v in e.items()})
-    assert max(e.values()) < 1e-4
+    assert max(e.values()) <= TOLMIX
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -219,7 +219,7 @@ def test_full_size_largest_order(torch_cuda, oracle_mod):
     p.g.step(qm, 0.05, 1, prec=numa.PREC_MIXED)
     e = group_err(p.host(qm) - q0, qo - q0)
     print("N=8 full-size mixed increment", {k: "%.1e" % v for k, v in e.items()})
-    assert max(e.values()) < 1e-4
+    assert max(e.values()) <= TOLMIX
 
 
 @pytest.mark.parametrize("which", ["box4", "box8", "shell4"])

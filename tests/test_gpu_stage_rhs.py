@@ -1,0 +1,141 @@
+"""The right-hand side as the benchmark's stage kernels compute it, against
+the oracle.
+
+numa_stage_rhs runs numa_step's own element and finish kernels (the column
+kernels k_elem_col / k_elem_stream with the recomputed metric, k_elem_batch
+with the stored metric or FP64 at N = 7, 8; the box finish k_fin_batch; the
+generic and shell finishes elsewhere) as a stage whose update is the identity
+on R.  Its output is M^-1 DSS(J w R) with the wall projection, which the
+oracle computes as dss(rhs(q), MASS | NOFLUX) (Eq. (discstrongform), Eq.
+(derivatives), Code example 1).  Tolerances: FP64 1e-12 and mixed precision
+1e-5, relative max-norm per variable group.
+"""
+import numpy as np
+import pytest
+
+from paper_1511_01561_amd import inputs
+from test_gpu_parity import TOL64, TOLMIX, Pair, assert_groups, group_err, small_shell, torch_cuda  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def _box(N, ne=(4, 3, 3), perz=False):
+    return inputs.box_workload(*ne, N, 12e3, 9e3, 6e3, terrain=400.0, bubble_centre=(6e3, 4.5e3, 2e3),
+                               bubble_radius=2.5e3, periodic_z=perz)
+
+
+def _check(p, q, metric, what, tol_mixed=TOLMIX, Ro=None):
+    from paper_1511_01561_amd import numa
+    p.g.set_metric(metric)
+    if Ro is None:
+        Ro = p.o.dss(p.o.rhs(q), 3)
+    qd = p.dev(q)
+    R64 = p.host(p.g.stage_rhs(qd, prec=numa.PREC_FP64))
+    assert_groups(R64, Ro, TOL64, "%s fp64" % what)
+    Rmx = p.host(p.g.stage_rhs(qd, prec=numa.PREC_MIXED))
+    assert_groups(Rmx, Ro, tol_mixed, "%s mixed" % what)
+    return R64, Ro
+
+
+@pytest.mark.parametrize("N", range(1, 9))
+@pytest.mark.parametrize("metric", ["recompute", "stored"])
+def test_stage_rhs_orders(torch_cuda, oracle_mod, N, metric):
+    """Every order on a 4 x 3 x 3 terrain box with walls: several element
+    workgroups of the column kernels with a partly empty last one, the
+    top-wall layer of the finish; a random state (every term of R)."""
+    from paper_1511_01561_amd import numa
+    p = Pair(_box(N), oracle_mod)
+    q = inputs.random_state(p.nu, seed=10 + N)
+    mode = numa.METRIC_RECOMPUTE if metric == "recompute" else numa.METRIC_STORED
+    _check(p, q, mode, "stage rhs N=%d %s" % (N, metric))
+
+
+@pytest.mark.parametrize("N,ne,perz", [(4, (8, 4, 2), True), (3, (5, 2, 2), False), (6, (6, 2, 2), False)])
+def test_stage_rhs_periodic_z_and_generic_finish(torch_cuda, oracle_mod, N, ne, perz):
+    """Periodic z (no walls; the z-wrapped copies in the finish), and boxes
+    whose nx is not a multiple of the finish segment (the generic finish)."""
+    from paper_1511_01561_amd import numa
+    p = Pair(_box(N, ne, perz), oracle_mod)
+    q = inputs.random_state(p.nu, seed=30 + N)
+    Ro = p.o.dss(p.o.rhs(q), 3)
+    for mode in (numa.METRIC_RECOMPUTE, numa.METRIC_STORED):
+        _check(p, q, mode, Ro=Ro, what="stage rhs N=%d ne=%s perz=%d metric=%d" % (N, ne, perz, mode))
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_stage_rhs_shell(torch_cuda, oracle_mod, N):
+    """The shell's stage kernels: R_rho' of a random state is not cancelled,
+    so the plain group norm applies."""
+    from paper_1511_01561_amd import numa
+    p = Pair(small_shell(N), oracle_mod)
+    q = inputs.random_state(p.nu, seed=50 + N)
+    for mode in (numa.METRIC_RECOMPUTE, numa.METRIC_STORED):
+        _check(p, q, mode, "shell stage rhs N=%d metric=%d" % (N, mode))
+
+
+def test_stage_rhs_equals_rhs_then_dss(torch_cuda, oracle_mod):
+    """The stage kernels and the unfused numa_rhs + numa_dss agree."""
+    from paper_1511_01561_amd import numa
+    p = Pair(_box(4), oracle_mod)
+    qd = p.dev(inputs.random_state(p.nu, seed=7))
+    for mode in (numa.METRIC_RECOMPUTE, numa.METRIC_STORED):
+        p.g.set_metric(mode)
+        a = p.host(p.g.stage_rhs(qd))
+        b = p.host(p.g.dss(p.g.rhs(qd), numa.DSS_MASS | numa.DSS_NOFLUX))
+        assert_groups(a, b, 1e-13, "stage rhs vs rhs+dss metric=%d" % mode)
+
+
+def test_stage_rhs_may_alias_its_input(torch_cuda, oracle_mod):
+    from paper_1511_01561_amd import numa
+    p = Pair(_box(4), oracle_mod)
+    q = inputs.random_state(p.nu, seed=8)
+    p.g.set_metric(numa.METRIC_RECOMPUTE)
+    ref = p.host(p.g.stage_rhs(p.dev(q)))
+    qd = p.dev(q)
+    p.g.stage_rhs(qd, out=qd)
+    assert np.array_equal(p.host(qd), ref)
+
+
+def test_stage_rhs_refuses_bad_arguments(torch_cuda, oracle_mod):
+    from paper_1511_01561_amd import numa
+    import ctypes as ct
+    p = Pair(_box(2), oracle_mod, prec_mask=1)
+    qd = p.dev(inputs.random_state(p.nu, seed=1))
+    with pytest.raises(numa.NumaError):
+        p.g.stage_rhs(qd, prec=numa.PREC_MIXED)  # no mixed workspace
+    assert numa.lib().numa_stage_rhs(p.g._h, 0, None, ct.c_void_p(qd.data_ptr()), None) == -1
+    assert numa.lib().numa_stage_rhs(None, 0, ct.c_void_p(qd.data_ptr()), ct.c_void_p(qd.data_ptr()), None) == -1
+
+
+# ------------------------------------------------- full one-GPU workload size
+@pytest.mark.parametrize("N", [4, 8])
+def test_stage_rhs_full_size(torch_cuda, oracle_mod, N):
+    """The 64 x 64 x 16 terrain box of the benchmark at N = 4 and N = 8, in
+    the launch configuration the benchmark times, on its initial state
+    (bubble and noise) and on a random state."""
+    from paper_1511_01561_amd import numa
+    p = Pair(inputs.gpu_box(N), oracle_mod)
+    q_ic = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 0))
+    for name, q in (("ic", q_ic), ("random", inputs.random_state(p.nu, seed=N))):
+        Ro = p.o.dss(p.o.rhs(q), 3)
+        for mode in (numa.METRIC_RECOMPUTE, numa.METRIC_STORED):
+            _check(p, q, mode, "full N=%d %s metric=%d" % (N, name, mode), Ro=Ro)
+    del p
+    import torch
+    torch.cuda.empty_cache()
+
+
+def test_stage_rhs_full_size_mixed_error_report(torch_cuda, oracle_mod):
+    """The mixed-precision error of R per group on the benchmark state, and
+    of the state after one step (the increment), printed for the record and
+    held to the mixed tolerance."""
+    from paper_1511_01561_amd import numa
+    p = Pair(inputs.gpu_box(4), oracle_mod)
+    q0 = p.o.init_state(p.wl["ic"], inputs.noise(p.nu, 0))
+    p.g.set_metric(numa.METRIC_RECOMPUTE)
+    qo = p.o.step(q0, 0.05, 1)
+    qm = p.dev(q0)
+    p.g.step(qm, 0.05, 1, prec=numa.PREC_MIXED)
+    e = group_err(p.host(qm) - q0, qo - q0)
+    print("full mixed 1-step increment", {k: "%.2e" % v for k, v in e.items()}, flush=True)
+    assert max(e.values()) <= TOLMIX
