@@ -53,6 +53,10 @@ extern "C" {
 #define NUMA_METRIC_STORED 0     /* metric terms and J w read per element-local node */
 #define NUMA_METRIC_RECOMPUTE 1  /* box: recomputed in the element kernel every stage */
 
+#define NUMA_STAGE_GATHER 0  /* element kernel writes J w R per copy; a finish kernel gathers the copies */
+#define NUMA_STAGE_BLOCK 1   /* one kernel per block of element columns sums the copies in LDS */
+#define NUMA_STAGE_COLOUR 2  /* 8 colour passes add J w R into a unique-node accumulator */
+
 #define NUMA_RK_SSP33 0      /* three-stage third-order SSP Runge-Kutta (Shu-Osher) */
 #define NUMA_RK_SSP53 1      /* five-stage third-order SSP Runge-Kutta (Spiteri-Ruuth) */
 
@@ -163,6 +167,35 @@ int32_t numa_geometry(numa_mesh_t m, const numa_phys *ph, void *stream);
  * g0 (a/r)^2 (the gather map and the gravity array are not read either).
  * Host only. */
 int32_t numa_mesh_set_metric(numa_mesh_t m, int32_t mode);
+
+/* How a fused stage of numa_step, numa_step_batch and numa_stage_rhs sums the
+ * element contributions at the unique nodes (the DSS of the text after
+ * Eq. (derivatives), inside the time loop of Code example 1).  Box meshes
+ * with the recomputed metric; every mode gives the same sums up to their
+ * order (parity with the oracle within 1e-12 either way), and every mode is
+ * deterministic.
+ * NUMA_STAGE_GATHER (default): the element kernel writes J w R of every
+ *   element-local node (node-major), the finish kernel gathers the copies of
+ *   each unique node in a fixed order; every mesh.
+ * NUMA_STAGE_BLOCK: a workgroup owns a block of element columns and walks
+ *   its element layers upwards, summing the copies in LDS and finishing the
+ *   nodes whose copies all lie in the block; it recomputes the western
+ *   neighbour element's east face itself, so x block faces are not shared,
+ *   and writes partial sums only on its y faces (and its z faces between
+ *   blocks), which a second kernel adds.  Meshes with walls, N = 2..4, nx a
+ *   multiple of 4 (N = 4) or 8, ny even; the stage's input and output
+ *   states must differ (numa_stage_rhs: r != q).
+ * NUMA_STAGE_COLOUR: the elements are coloured by the parity of
+ *   (ex, ey, ez); one launch per colour adds J w R with a plain read-modify-
+ *   write into an FP64 accumulator [5][n_unique] in the workspace scratch (no
+ *   two elements of a colour share a node: no atomics), the colours in a
+ *   fixed order; a pointwise kernel then applies M^-1, the wall projection
+ *   and the update (the paper's scheme of re-ordering elements so that
+ *   concurrent threads never update the same node, Sec. "OpenMP").  N <= 4,
+ *   nx, ny, nz even.
+ * Meshes or stages a mode does not cover run NUMA_STAGE_GATHER.  NUMA_EINVAL
+ * for an unknown mode.  Host only. */
+int32_t numa_mesh_set_stage(numa_mesh_t m, int32_t mode);
 
 /* Copy an internal field (NUMA_FIELD_*) to a caller device buffer. */
 int32_t numa_export(numa_mesh_t m, int32_t what, void *dev_out, void *stream);

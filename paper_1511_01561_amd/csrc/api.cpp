@@ -193,6 +193,20 @@ int32_t numa_mesh_set_metric(numa_mesh_t m, int32_t mode)
     return NUMA_OK;
 }
 
+int32_t numa_mesh_set_stage(numa_mesh_t m, int32_t mode)
+{
+    if (!m) {
+        set_error("numa_mesh_set_stage: null mesh handle");
+        return NUMA_EINVAL;
+    }
+    if (mode != NUMA_STAGE_GATHER && mode != NUMA_STAGE_BLOCK && mode != NUMA_STAGE_COLOUR) {
+        set_error("numa_mesh_set_stage: unknown mode %d", mode);
+        return NUMA_EINVAL;
+    }
+    m->stage_mode = mode;
+    return NUMA_OK;
+}
+
 int32_t numa_geometry(numa_mesh_t m, const numa_phys *ph, void *stream)
 {
     if (!m || !ph) {
@@ -411,9 +425,11 @@ struct StagePlan {
     int in, ref, out;
     double a, b, beta;
 };
-// SSP-RK3 (Shu-Osher): (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3), beta = b
+// SSP-RK3 (Shu-Osher): (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3), beta = b.
+// No stage writes its own input: the fused block stage finishes nodes while
+// other workgroups still gather the input state.
 static const StagePlan kSsp33[3] = {
-    {0, 0, 1, 0.0, 1.0, 1.0}, {1, 0, 1, 0.75, 0.25, 0.25}, {1, 0, 0, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0}};
+    {0, 0, 1, 0.0, 1.0, 1.0}, {1, 0, 2, 0.75, 0.25, 0.25}, {2, 0, 0, 1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0}};
 // Five-stage third-order SSP Runge-Kutta (Spiteri and Ruuth, SIAM J. Numer.
 // Anal. 40(2), 2002), the paper's explicit scheme class (Sec. "Time
 // Discretization": five stages, third order):
@@ -468,7 +484,7 @@ int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double
     int ns;
     const StagePlan *plan = stage_plan(m->integrator, &ns);
     const bool batched = numa::box_batchable(*m);
-    void *ev = prec == NUMA_PREC_MIXED ? (void *)m->dv.ev32 : (void *)m->dv.ev64;
+    void *ev = m->dv.ev64;  // FP64-sized: element contributions of either precision, or an FP64 accumulator
     for (int n = 0; n < nsteps; ++n) {
         for (int k = 0; k < ns; ++k) {
             const StagePlan &p = plan[k];
@@ -495,13 +511,17 @@ int32_t numa_stage_rhs(numa_mesh_t m, int32_t prec, const double *q, double *r, 
         set_error("numa_stage_rhs: null argument");
         return NUMA_EINVAL;
     }
+    if (q == r) {
+        set_error("numa_stage_rhs: r must not alias q");
+        return NUMA_EINVAL;
+    }
     hipStream_t s = as_stream(stream);
     // a stage whose update is q_out = 0 q_ref + 1 R (b = 0: no q_s term, so no
     // kernel folds q_s into the contributions): the summed, mass-weighted,
     // projected right-hand side itself
     const numa::StageCoef c{0.0, 0.0, 1.0};
     if (numa::box_batchable(*m)) {
-        void *ev = prec == NUMA_PREC_MIXED ? (void *)m->dv.ev32 : (void *)m->dv.ev64;
+        void *ev = m->dv.ev64;  // FP64-sized: element contributions of either precision, or an FP64 accumulator
         numa::StepItem it = {m, q, q, r, ev, c};
         return run_batch_stage(&it, 1, prec, s);
     }
@@ -542,7 +562,7 @@ int32_t numa_imex_step(numa_mesh_t m, int32_t prec, double dt, double ra, int32_
         m->imex_ok = true;
     }
     const numa::StageCoef c{1.0, 0.0, 2.0 * dt};  // q* = q^{n-1} + 2 dt L(q^n)
-    void *ev = prec == NUMA_PREC_MIXED ? (void *)m->dv.ev32 : (void *)m->dv.ev64;
+    void *ev = m->dv.ev64;  // FP64-sized: element contributions of either precision, or an FP64 accumulator
     for (int n = 0; n < nsteps; ++n) {
         if (numa::box_batchable(*m)) {
             numa::StepItem it = {m, qprev, qcur, m->dv.qs, ev, c};
@@ -558,12 +578,19 @@ int32_t numa_imex_step(numa_mesh_t m, int32_t prec, double dt, double ra, int32_
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
-// batch-item scratch: stage state, contributions, and for SSP-RK(5,3) the
-// second stage state
+// the contribution scratch of a batch item: element contributions of the
+// precision, the fused block stage's partial sums, or the colour passes' FP64
+// accumulator [5][n_unique]
+static uint64_t contribution_bytes(const Mesh &m, int32_t prec)
+{
+    const uint64_t ev = (prec == NUMA_PREC_MIXED ? 20ull : 40ull) * m.nl, acc = 40ull * m.nu;
+    return align256(ev > acc ? ev : acc);
+}
+
+// batch-item scratch: stage state, contributions, second stage state
 static uint64_t scratch_bytes(const Mesh &m, int32_t prec)
 {
-    return align256(40ull * m.nu) + align256((prec == NUMA_PREC_MIXED ? 20ull : 40ull) * m.nl) +
-           (m.integrator == NUMA_RK_SSP53 ? align256(40ull * m.nu) : 0);
+    return align256(40ull * m.nu) + contribution_bytes(m, prec) + align256(40ull * m.nu);
 }
 
 int32_t numa_step_scratch_bytes(numa_mesh_t m, int32_t prec, uint64_t *bytes)
@@ -636,7 +663,7 @@ int32_t numa_step_batch(const numa_batch_item *items, int32_t n, int32_t prec, i
     for (int32_t k = 0; k < n; ++k) {
         const Mesh *m = items[k].mesh;
         char *scr = static_cast<char *>(items[k].scratch);
-        const uint64_t evb = align256((prec == NUMA_PREC_MIXED ? 20ull : 40ull) * m->nl);
+        const uint64_t evb = contribution_bytes(*m, prec);
         double *buf[3] = {items[k].q, reinterpret_cast<double *>(scr),
                           reinterpret_cast<double *>(scr + align256(40ull * m->nu) + evb)};
         void *ev = scr + align256(40ull * m->nu);

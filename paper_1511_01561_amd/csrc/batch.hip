@@ -8,6 +8,8 @@
 // (numa_step) runs through the same kernels with one item.
 #include "kernels.h"
 
+#include <vector>
+
 namespace numa {
 namespace {
 
@@ -28,7 +30,7 @@ struct BatchItem {
     int nz, walls;
     int ne;               // elements
     int mblk;             // finish blocks of the main layers: (nx/SEG) ny nz
-    FastDiv fx, fy, fseg;  // division by nx, ny and nx/SEG
+    FastDiv fx, fy, fseg;  // division by nx, ny and nx/SEG (colour passes: fseg by nx/2, fy by ny/2)
     double cdt;            // (beta / b) dt of the stage update
     double theta0;         // the box reference is isentropic: theta_bar = theta0 everywhere
     BoxMetric bm;          // constants of the recomputed metric
@@ -177,8 +179,13 @@ constexpr int col_threads() { return ((col_eb<N, T>() * (N + 1) * (N + 1) + 63) 
 template <int N, typename T>
 constexpr int col_blocks() { return (sizeof(T) == 4 && N == 4) ? 4 : 1; }
 
-template <int N, typename T>
-__global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T>())) void k_elem_col(Batch B)
+// MODE 0: write J w R node-major for the finish kernel (NUMA_STAGE_GATHER);
+// MODE 1: one colour pass of NUMA_STAGE_COLOUR: the workgroup's elements are
+// the elements of colour `colour` (parity of ex, ey, ez), EB consecutive ones
+// along x, and every lane adds its nodes' J w R to the FP64 accumulator with
+// a plain read-modify-write (no other element of the colour has the node).
+template <int N, typename T, int MODE = 0>
+__global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T>())) void k_elem_col(Batch B, int colour)
 {
     constexpr int P = N + 1, PP = P * P, NP = PP * P, EB = col_eb<N, T>(), BT = col_threads<N, T>();
     __shared__ T s[EB][8][NP];
@@ -194,9 +201,18 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T>())) void k
     constexpr bool F64 = sizeof(T) == 8;
     T irho[P], buoy[P], dz[8][P];
     double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
-    int ez = 0;
+    int ez = 0, base = 0;
+    const int layer = a.ni * a.nj;
     if (act) {
-        const BoxElem be = box_elem((uint32_t)(e0 + q), a.fx, a.fy);
+        BoxElem be;
+        if constexpr (MODE == 1) {
+            const uint32_t ec = (uint32_t)(e0 + q), t1 = fdiv(ec, it.fseg), t2 = fdiv(t1, it.fy);
+            be.ex = 2 * (int)(ec - t1 * it.fseg.d) + (colour & 1);
+            be.ey = 2 * (int)(t1 - t2 * it.fy.d) + ((colour >> 1) & 1);
+            be.ez = 2 * (int)t2 + (colour >> 2);
+        } else {
+            be = box_elem((uint32_t)(e0 + q), a.fx, a.fy);
+        }
         ez = be.ez;
         const double *cp = a.hcol + (int64_t)(be.ex + a.nx * be.ey) * (4 * PP) + c;
         c0 = cp[0];
@@ -206,7 +222,7 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T>())) void k
         int gi = be.ex * N + i, gj = be.ey * N + j;
         if (gi == a.ni) gi = 0;
         if (gj == a.nj) gj = 0;
-        const int base = gi + a.ni * gj, layer = a.ni * a.nj;
+        base = gi + a.ni * gj;
         T col[8][P];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
@@ -304,6 +320,20 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T>())) void k
             }
         }
     }
+    if constexpr (MODE == 1) {
+        if (act) {
+            double *acc = (double *)it.ev;
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                int gk = ez * N + k;
+                if (gk == a.nk) gk = 0;
+                const int32_t I = base + layer * gk;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) acc[I + v * a.nu] += (double)res[k][v];
+            }
+        }
+        return;  // every lane: no barrier follows
+    }
     __syncthreads();  // tiles read
     T *st = &s[0][0][0];
     if (act) {
@@ -317,6 +347,56 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T>())) void k
     const int ne = it.ne - e0 < EB ? it.ne - e0 : EB;
     T *out = (T *)it.ev + (int64_t)e0 * (NP * 5);
     store_run<T>(out, st, ne * NP * 5, t, BT);
+}
+
+// NUMA_STAGE_COLOUR: zero the accumulator [5][nu] of every item (a kernel,
+// not a memset: the stage may be captured in a graph)
+__global__ void k_colour_zero(Batch B)
+{
+    const int g = (int)blockIdx.x;
+    const BatchItem &it = B.it[batch_item(B, g, true)];
+    const int64_t I = (int64_t)(g - it.boff) * 256 + threadIdx.x;
+    if (I >= it.nu) return;
+    double *acc = (double *)it.ev;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) acc[I + v * it.nu] = 0.0;
+}
+
+// NUMA_STAGE_COLOUR: M^-1, wall projection and stage update of every unique
+// node from the accumulated sum (the tail of box_finish_node)
+__global__ void k_colour_finish(Batch B)
+{
+    const int g = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const BatchItem &it = B.it[batch_item(B, g, true)];
+    const int64_t I = (int64_t)(g - it.boff) * 256 + threadIdx.x;
+    if (I >= it.nu) return;
+    const double *acc = (const double *)it.ev;
+    const StageCoef sc{B.ca, B.cb, it.cdt};
+    const double mi = it.Minv[I];
+    const bool wall = it.walls && (I < it.nh || I >= it.nu - it.nh);
+    double r[5], qnv[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+        r[v] = acc[I + v * it.nu] * mi;
+        qnv[v] = sc.a == 0.0 ? 0.0 : it.qn[I + v * it.nu];
+    }
+    if (B.fold && !wall) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) it.qout[I + v * it.nu] = rk_update_folded(sc, qnv[v], r[v]);
+        return;
+    }
+    PointArgs p;
+    p.off = nullptr;
+    p.idx = nullptr;
+    p.Minv = it.Minv;
+    p.nrm = it.nrm;
+    p.nl = 0;
+    p.nu = it.nu;
+    p.nh = it.nh;
+    p.walls = it.walls;
+    noflux(p, I, r[1], r[2], r[3]);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) it.qout[I + v * it.nu] = rk_update(sc, qnv[v], it.qs[I + v * it.nu], r[v]);
 }
 
 // Streaming variant of the column kernel: after the tile is built the lane
@@ -485,7 +565,7 @@ __global__ void k_fin_batch(Batch B)
 }
 
 template <int N, typename T>
-int32_t run_chunk(const StepItem *items, int n, int phase, hipStream_t s)
+int32_t run_chunk(const StepItem *items, int n, int phase, hipStream_t s, bool colour)
 {
     constexpr int SEG = seg_for<N>();
     Batch B;
@@ -542,20 +622,42 @@ int32_t run_chunk(const StepItem *items, int n, int phase, hipStream_t s)
         it.ne = (int)m.ne;
         it.eoff = (int)eo;
         it.boff = (int)bo;
-        eo += (m.ne + eb - 1) / eb * eb;
-        bo += mblk + (m.walls ? (int64_t)(m.d.ne[0] / SEG) * m.d.ne[1] : 0);
+        if (colour) {  // a colour pass covers ne/8 elements; the pointwise kernels 256 nodes per block
+            it.ne = (int)(m.ne / 8);
+            it.fseg = fast_div((uint32_t)(m.d.ne[0] / 2));
+            it.fy = fast_div((uint32_t)(m.d.ne[1] / 2));
+            eo += (it.ne + eb - 1) / eb * eb;
+            bo += (m.nu + 255) / 256;
+        } else {
+            eo += (m.ne + eb - 1) / eb * eb;
+            bo += mblk + (m.walls ? (int64_t)(m.d.ne[0] / SEG) * m.d.ne[1] : 0);
+        }
     }
     if (eo >= (int64_t(1) << 31) || bo >= (int64_t(1) << 31)) {
         set_error("batch: more than 2^31 - 1 elements in one launch");
         return NUMA_EUNSUPPORTED;
     }
     for (int k = n; k < kMaxBatch; ++k) B.it[k] = BatchItem{};
+    if (colour) {
+        if constexpr (kind == 0) {
+            if (phase == 0) {
+                hipLaunchKernelGGL(k_colour_zero, dim3((unsigned)bo), dim3(256), 0, s, B);
+                for (int c = 0; c < 8; ++c)
+                    hipLaunchKernelGGL((k_elem_col<N, T, 1>), dim3((unsigned)(eo / eb)), dim3(col_threads<N, T>()), 0, s,
+                                       B, c);
+            } else {
+                hipLaunchKernelGGL(k_colour_finish, dim3((unsigned)bo), dim3(256), 0, s, B);
+            }
+            NUMA_HIP(hipGetLastError());
+            return NUMA_OK;
+        }
+    }
     if (phase == 0) {
         if (!recompute) {
             hipLaunchKernelGGL((k_elem_batch<N, T, kMetricStored>), dim3((unsigned)eo), dim3(block_threads<N>()), 0, s,
                                B);
         } else if constexpr (kind == 0) {
-            hipLaunchKernelGGL((k_elem_col<N, T>), dim3((unsigned)(eo / eb)), dim3(col_threads<N, T>()), 0, s, B);
+            hipLaunchKernelGGL((k_elem_col<N, T>), dim3((unsigned)(eo / eb)), dim3(col_threads<N, T>()), 0, s, B, 0);
         } else if constexpr (kind == 1) {
             hipLaunchKernelGGL((k_elem_stream<N, T>), dim3((unsigned)(eo / eb)), dim3(col_threads<N, T>()), 0, s, B);
         } else {
@@ -604,20 +706,20 @@ int32_t run_plain_finish(const Mesh &m, const double *ev, double *q, hipStream_t
 }
 
 template <typename T>
-int32_t run_stage_t(const StepItem *items, int n, int phase, hipStream_t s)
+int32_t run_stage_t(const StepItem *items, int n, int phase, hipStream_t s, bool colour)
 {
     for (int c0 = 0; c0 < n; c0 += kMaxBatch) {
         const int c = n - c0 < kMaxBatch ? n - c0 : kMaxBatch;
         int32_t rc;
         switch (items[0].mesh->N) {
-        case 1: rc = run_chunk<1, T>(items + c0, c, phase, s); break;
-        case 2: rc = run_chunk<2, T>(items + c0, c, phase, s); break;
-        case 3: rc = run_chunk<3, T>(items + c0, c, phase, s); break;
-        case 4: rc = run_chunk<4, T>(items + c0, c, phase, s); break;
-        case 5: rc = run_chunk<5, T>(items + c0, c, phase, s); break;
-        case 6: rc = run_chunk<6, T>(items + c0, c, phase, s); break;
-        case 7: rc = run_chunk<7, T>(items + c0, c, phase, s); break;
-        default: rc = run_chunk<8, T>(items + c0, c, phase, s); break;
+        case 1: rc = run_chunk<1, T>(items + c0, c, phase, s, colour); break;
+        case 2: rc = run_chunk<2, T>(items + c0, c, phase, s, colour); break;
+        case 3: rc = run_chunk<3, T>(items + c0, c, phase, s, colour); break;
+        case 4: rc = run_chunk<4, T>(items + c0, c, phase, s, colour); break;
+        case 5: rc = run_chunk<5, T>(items + c0, c, phase, s, colour); break;
+        case 6: rc = run_chunk<6, T>(items + c0, c, phase, s, colour); break;
+        case 7: rc = run_chunk<7, T>(items + c0, c, phase, s, colour); break;
+        default: rc = run_chunk<8, T>(items + c0, c, phase, s, colour); break;
         }
         if (rc) return rc;
     }
@@ -657,10 +759,28 @@ int32_t launch_box_plain_finish(const Mesh &m, const double *ev, double *q, hipS
     }
 }
 
+bool colour_ok(const Mesh &m)
+{
+    return m.stage_mode == NUMA_STAGE_COLOUR && m.d.kind == NUMA_MESH_BOX && m.metric_mode == NUMA_METRIC_RECOMPUTE &&
+           m.N <= 4 && m.d.ne[0] % 2 == 0 && m.d.ne[1] % 2 == 0 && m.d.ne[2] % 2 == 0;
+}
+
 int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int phase, hipStream_t s)
 {
-    if (prec == NUMA_PREC_MIXED) return run_stage_t<float>(items, n, phase, s);
-    return run_stage_t<double>(items, n, phase, s);
+    // items the fused block kernels take (pencil.hip), the colour passes, the rest
+    std::vector<StepItem> pen, col, rest;
+    for (int k = 0; k < n; ++k)
+        (pencil_stage_ok(items[k], prec) ? pen : colour_ok(*items[k].mesh) ? col : rest).push_back(items[k]);
+    int32_t rc = NUMA_OK;
+    if (!pen.empty() && (rc = launch_pencil_stage(pen.data(), (int)pen.size(), prec, phase, s))) return rc;
+    for (int g = 0; g < 2; ++g) {
+        const std::vector<StepItem> &v = g == 0 ? col : rest;
+        if (v.empty()) continue;
+        rc = prec == NUMA_PREC_MIXED ? run_stage_t<float>(v.data(), (int)v.size(), phase, s, g == 0)
+                                     : run_stage_t<double>(v.data(), (int)v.size(), phase, s, g == 0);
+        if (rc) return rc;
+    }
+    return NUMA_OK;
 }
 
 }  // namespace numa

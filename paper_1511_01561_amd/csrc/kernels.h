@@ -26,6 +26,10 @@ struct BoxMetric {
 // expm1(gamma log1p(x)).  This is the pressure perturbation of the equation of
 // state p = p0 (R rho theta / p0)^gamma about the reference, without cancellation.
 constexpr int kEosTerms = 10;
+// The rarely taken branch is a separate function: inlined, the constants of
+// log1p and expm1 would be hoisted out of the kernels' loops and held in
+// registers for the whole kernel.
+__device__ __noinline__ double eos_rel_large(double x, double gamma) { return expm1(gamma * log1p(x)); }
 __device__ __forceinline__ double eos_rel(double x, double gamma, const double *c)
 {
     if (fabs(x) < 0.015625) {
@@ -34,7 +38,7 @@ __device__ __forceinline__ double eos_rel(double x, double gamma, const double *
         for (int k = kEosTerms - 2; k >= 0; --k) r = r * x + c[k];
         return r * x;
     }
-    return expm1(gamma * log1p(x));
+    return eos_rel_large(x, gamma);
 }
 
 // host: constants of the recomputed metric of a box mesh

@@ -127,6 +127,7 @@ struct Mesh {
     DeviceView dv;
     bool uploaded = false, geom = false;
     int metric_mode = 0;  // NUMA_METRIC_STORED or NUMA_METRIC_RECOMPUTE (box)
+    int stage_mode = 0;   // NUMA_STAGE_GATHER, NUMA_STAGE_BLOCK or NUMA_STAGE_COLOUR (box)
     int integrator = 0;         // NUMA_RK_SSP33 or NUMA_RK_SSP53
     double imex_dt = 0.0;       // dt of the IMEX factors in the workspace (valid when imex_ok)
     bool imex_ok = false;
@@ -188,6 +189,17 @@ struct StepItem {
 // kernels; phase 0 launches the element kernels, phase 1 the finish kernels.
 bool box_batchable(const Mesh &m);
 int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int phase, hipStream_t s);
+
+// The fused block stage (pencil.hip): box meshes with walls, recomputed
+// metric, N = 2..4, nx and ny multiples of the block; phase 0 launches the
+// block kernel, phase 1 the kernel of the nodes shared between blocks.  The
+// stage's input and output states must be distinct.
+bool pencil_ok(const Mesh &m, int32_t prec);
+inline bool pencil_stage_ok(const StepItem &it, int32_t prec)
+{
+    return it.qs != it.qout && pencil_ok(*it.mesh, prec);
+}
+int32_t launch_pencil_stage(const StepItem *items, int n, int32_t prec, int phase, hipStream_t s);
 
 int32_t launch_stage_elements(Mesh &m, int32_t prec, const StageCoef &c, const double *qs, hipStream_t s);
 // the shell's FP64 stages that use q_s (b != 0) fold it into the node-major

@@ -19,6 +19,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 DSS_MASS, DSS_NOFLUX = 1, 2
 METRIC_STORED, METRIC_RECOMPUTE = 0, 1
 RK_SSP33, RK_SSP53 = 0, 1
+STAGE_GATHER, STAGE_BLOCK, STAGE_COLOUR = 0, 1, 2
 WS_IMEX = 4
 FIELD_MASS, FIELD_REF, FIELD_COORDS, FIELD_METRIC, FIELD_GRAVITY, FIELD_LOCAL_COORDS = range(6)
 
@@ -28,7 +29,7 @@ EXPORTED = ["numa_last_error", "numa_gll", "numa_mesh_create", "numa_mesh_destro
             "numa_rk_stage", "numa_step", "numa_profile", "numa_profile_read", "numa_step_scratch_bytes",
             "numa_step_batch", "numa_batch_capture", "numa_graph_launch", "numa_graph_destroy",
             "numa_mesh_set_metric", "numa_filter", "numa_filter_matrix", "numa_mesh_set_filter",
-            "numa_mesh_set_integrator", "numa_imex_step", "numa_stage_rhs"]
+            "numa_mesh_set_integrator", "numa_imex_step", "numa_stage_rhs", "numa_mesh_set_stage"]
 
 
 class numa_mesh_desc(ct.Structure):
@@ -98,6 +99,7 @@ def lib():
         "numa_graph_launch": (I32, [P, P]),
         "numa_graph_destroy": (I32, [P]),
         "numa_mesh_set_metric": (I32, [P, I32]),
+        "numa_mesh_set_stage": (I32, [P, I32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -263,6 +265,10 @@ class Mesh:
     def set_metric(self, mode: int):
         """METRIC_STORED or METRIC_RECOMPUTE (box meshes)."""
         check(lib().numa_mesh_set_metric(self._h, mode))
+
+    def set_stage(self, mode: int):
+        """STAGE_GATHER (default), STAGE_BLOCK or STAGE_COLOUR: how a fused stage sums the copies."""
+        check(lib().numa_mesh_set_stage(self._h, mode))
 
     def profile(self, enable: bool):
         check(lib().numa_profile(self._h, 1 if enable else 0))

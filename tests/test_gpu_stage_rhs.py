@@ -85,15 +85,15 @@ def test_stage_rhs_equals_rhs_then_dss(torch_cuda, oracle_mod):
         assert_groups(a, b, 1e-13, "stage rhs vs rhs+dss metric=%d" % mode)
 
 
-def test_stage_rhs_may_alias_its_input(torch_cuda, oracle_mod):
+def test_stage_rhs_refuses_aliasing(torch_cuda, oracle_mod):
+    """The fused stage finishes nodes while other workgroups still read the
+    input state, so r must not alias q."""
     from paper_1511_01561_amd import numa
-    p = Pair(_box(4), oracle_mod)
-    q = inputs.random_state(p.nu, seed=8)
+    p = Pair(_box(4, (8, 4, 2)), oracle_mod)
+    qd = p.dev(inputs.random_state(p.nu, seed=8))
     p.g.set_metric(numa.METRIC_RECOMPUTE)
-    ref = p.host(p.g.stage_rhs(p.dev(q)))
-    qd = p.dev(q)
-    p.g.stage_rhs(qd, out=qd)
-    assert np.array_equal(p.host(qd), ref)
+    with pytest.raises(numa.NumaError):
+        p.g.stage_rhs(qd, out=qd)
 
 
 def test_stage_rhs_refuses_bad_arguments(torch_cuda, oracle_mod):
