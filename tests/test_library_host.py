@@ -237,9 +237,15 @@ def test_integrator_setting_and_scratch_size(L):
         assert L.numa_step_scratch_bytes(h, 0, ct.byref(a)) == 0
         assert L.numa_mesh_set_integrator(h, numa.RK_SSP53) == 0
         assert L.numa_step_scratch_bytes(h, 0, ct.byref(b)) == 0
-        nu = ct.c_int64()
-        assert L.numa_mesh_info(h, None, None, ct.byref(nu), None, None) == 0
-        assert b.value - a.value == (40 * nu.value + 255) // 256 * 256    # the second stage state
+        nu, nl = ct.c_int64(), ct.c_int64()
+        assert L.numa_mesh_info(h, None, ct.byref(nl), ct.byref(nu), None, None) == 0
+        # both integrators keep two stage states (no stage writes its own input)
+        # beside the contributions (FP64 element-local, or an FP64 unique-node sum)
+        r = lambda x: (x + 255) // 256 * 256
+        assert a.value == b.value == 2 * r(40 * nu.value) + r(max(40 * nl.value, 40 * nu.value))
+        m = ct.c_uint64()
+        assert L.numa_step_scratch_bytes(h, 1, ct.byref(m)) == 0
+        assert m.value == 2 * r(40 * nu.value) + r(max(20 * nl.value, 40 * nu.value))
         assert L.numa_mesh_set_integrator(h, 2) == -1 and L.numa_mesh_set_integrator(h, -1) == -1
         assert L.numa_mesh_set_integrator(None, 0) == -1
         assert L.numa_mesh_set_integrator(h, numa.RK_SSP33) == 0
