@@ -69,6 +69,18 @@ def finish_bytes(nu, nl, n_wall, prec):
     return nu * (8 + 40 * 2.0 / 3.0 + 40) + qs_nodes * 40 + nl * contrib + n_wall * 24
 
 
+def stage_bytes(nu, ncol_nodes, prec):
+    """Algorithmic HBM bytes of one fused stage (right-hand side, DSS, M^-1,
+    update) with the metric recomputed every stage: per unique node the state
+    read (5 x 8 B), q^n read in two of the three stages (5 x 8 x 2/3 B), the new
+    state written (5 x 8 B), the reference rho_bar, theta_bar, p_bar (3 x 8 B)
+    and M^-1 (8 B, or 4 B in mixed precision); plus the column factors of the
+    metric (4 x 8 B per element column node (i, j)), read once.  Element-local
+    intermediates (the contributions' round trip) are not algorithmic."""
+    minv = 4 if prec == "mixed" else 8
+    return nu * (40 + 40 * 2.0 / 3.0 + 40 + 24 + minv) + 32 * ncol_nodes
+
+
 def load_traffic(kernel, workload):
     """HBM bytes per launch measured by rocprofv3 counters (FETCH_SIZE +
     WRITE_SIZE, calibrated on a copy kernel), if taken on the current source."""
@@ -82,29 +94,56 @@ def load_traffic(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(wl, budget_s=15.0):
-    """Time the FP64 oracle (OpenMP over elements / unique nodes) on this host
-    for whole SSP-RK3 steps of the same workload until ~budget_s has elapsed."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(wl, steps=100, budget_s=45.0):
+    """Time the FP64 oracle (OpenMP over elements / unique nodes) on this host:
+    up to `steps` SSP-RK3 steps of the same workload with all threads (stopping
+    early after budget_s), then one step on one thread.  Returns the record and
+    the oracle states after the first and after the last step (accuracy of the
+    GPU results)."""
     import numpy as np
     import oracle
     from paper_1511_01561_amd import inputs
     mm = wl["mesh"]
     t0 = time.perf_counter()
     om = oracle.OracleMesh(mm["kind"], mm["N"], mm["ne"], mm["periodic"], mm["extent"], mm["h0"], wl["phys"])
-    q = om.init_state(wl["ic"], inputs.noise(om.n_unique, 0))
+    q0 = om.init_state(wl["ic"], inputs.noise(om.n_unique, 0))
     _log("oracle setup %.1f s" % (time.perf_counter() - t0))
-    steps, el = 0, 0.0
-    while el < budget_s and steps < 100:
+    nthreads = oracle.num_threads()
+    q, q1, per = q0, None, []
+    while len(per) < steps and sum(per) < budget_s:
         t = time.perf_counter()
         q = om.step(q, 0.05, 1)
-        el += time.perf_counter() - t
-        steps += 1
-        _log("oracle step %d: %.2f s" % (steps, el))
+        per.append(time.perf_counter() - t)
+        if q1 is None:
+            q1 = q.copy()
+        if len(per) % 10 == 0:
+            _log("oracle step %d: %.2f s" % (len(per), sum(per)))
     assert np.isfinite(q).all()
-    return dict(value=om.n_unique * 3 * steps / el, unit="grid-point RHS updates/s",
-                cores=oracle.num_threads(), kind="oracle",
-                sample="%d SSP-RK3 step(s) of the full 64x64x16 N=4 box, FP64, %d OpenMP threads, %.1f s"
-                       % (steps, oracle.num_threads(), el))
+    oracle.set_threads(1)
+    t = time.perf_counter()
+    om.step(q0, 0.05, 1)
+    one = time.perf_counter() - t
+    oracle.set_threads(nthreads)
+    _log("oracle: %d steps on %d threads, median %.3f s/step; 1 thread %.2f s/step" % (len(per), nthreads,
+                                                                                    float(np.median(per)), one))
+    el = sum(per)
+    rec = dict(value=om.n_unique * 3 * len(per) / el, unit="grid-point RHS updates/s", cores=nthreads, kind="oracle",
+               sample="%d SSP-RK3 steps of the full 64x64x16 N=4 box (the timed workload), FP64, %d OpenMP threads, "
+                      "%.1f s" % (len(per), nthreads, el),
+               steps=len(per), median_s_per_step=float(np.median(per)),
+               one_thread_s_per_step=one, one_thread_value=om.n_unique * 3 / one, cpu_model=cpu_model())
+    return rec, q0, q1, q, len(per)
 
 
 def serving(n_req, budget_gb, precs, loads=(0.5, 0.8), seed=0):
@@ -331,7 +370,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--small", action="store_true", help="4x4x4 box instead of the one-GPU workload")
     ap.add_argument("--sweep", action="store_true", help="order sweep and shell instead of the bench line")
-    ap.add_argument("--serve-requests", type=int, default=100, help="requests per serving run (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=1000, help="requests per serving run (0: skip)")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this size (HBM counter calibration)")
@@ -416,15 +455,75 @@ def main():
     mixed = recomp.get("mixed")
     if mixed is not None:
         mixed["dtype"] = "f32 contractions / f64 state"
-    # roofline of the dominant kernel of the headline path
-    el, fin = head["element_kernel"], head["finish_kernel"]
-    dom_name, dom = (("k_elem_col<4,double> (recomputed metric)", el) if el["avg_launch_us"] >= fin["avg_launch_us"]
-                     else ("k_fin_batch<4,4,double>", fin))
-    traffic = load_traffic("element" if dom is el else "finish", workload)
-    roofline = dict(kernel=dom_name, bound="hbm", achieved=dom["achieved_GBs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=dom["achieved_GBs"] / HBM_PEAK_GBS, traffic=traffic,
-                    algorithmic_bytes=dom["algorithmic_bytes"], avg_launch_us=dom["avg_launch_us"],
-                    other_kernel=(fin if dom is el else el))
+
+    # achievable rate: a plain device copy (1 GiB each way), timed with events
+    src = torch.ones((1 << 30) // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_GBs = 5 * 2 * (1 << 30) / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    _log("device copy: %.0f GB/s" % copy_GBs)
+
+    # roofline of the whole fused stage (element kernel + finish kernel): the
+    # algorithmic bytes of a stage over the two kernels' average durations
+    ncol = mm["ne"][0] * mm["ne"][1] * (mm["N"] + 1) ** 2
+
+    def stage_roofline(r, prec):
+        el, fin = r["element_kernel"], r["finish_kernel"]
+        st_us = el["avg_launch_us"] + fin["avg_launch_us"]
+        algo = stage_bytes(g.n_unique, ncol, prec)
+        ach = algo / (st_us * 1e-6) / 1e9
+        return dict(kernel="fused SSP-RK3 stage: k_elem_col<4,%s> + k_fin_batch<4,4,%s> (recomputed metric, gather DSS)"
+                    % (("double",) * 2 if prec == "fp64" else ("float",) * 2),
+                    bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                    algorithmic_bytes=algo, stage_us=st_us, copy_GBs=copy_GBs, copy_frac=ach / copy_GBs,
+                    contribution_round_trip_bytes=2 * (40 if prec == "fp64" else 20) * g.n_local,
+                    element_kernel=el, finish_kernel=fin)
+
+    roofline = stage_roofline(head, "fp64")
+    te, tf = load_traffic("element", workload), load_traffic("finish", workload)
+    roofline["traffic"] = te + tf if te is not None and tf is not None else None
+    roofline["traffic_by_kernel"] = {"element": te, "finish": tf}
+    if mixed is not None:
+        mixed["roofline"] = stage_roofline(mixed, "mixed")
+    _log("stage: %.1f us, %.0f GB/s algorithmic = %.3f of 8 TB/s, %.3f of the copy rate"
+         % (roofline["stage_us"], roofline["achieved"], roofline["frac"], roofline["copy_frac"]))
+
+    # the three DSS schedules of a stage on the same mesh (numa_mesh_set_stage)
+    g.set_metric(numa.METRIC_RECOMPUTE)
+    modes = {}
+    for mode, mname in ((numa.STAGE_BLOCK, "block"), (numa.STAGE_COLOUR, "colour")):
+        g.set_stage(mode)
+        modes[mname] = {}
+        for prec, name in ((numa.PREC_FP64, "fp64"), (numa.PREC_MIXED, "mixed")):
+            if name == "mixed" and args.no_mixed:
+                continue
+            gpu_s, wall_s = timed_steps(prec)
+            modes[mname][name] = {"ms_per_step": 1e3 * wall_s / args.steps}
+        _log("stage mode %s: %s" % (mname, {k: "%.3f ms" % v["ms_per_step"] for k, v in modes[mname].items()}))
+    g.set_stage(numa.STAGE_GATHER)
+    modes["gather"] = {k: {"ms_per_step": v["ms_per_step"]} for k, v in recomp.items() if k in ("fp64", "mixed")}
+
+    # accuracy: FP64 and mixed states after 1 and after the oracle's steps
+    # (100 unless the CPU budget stopped it earlier)
+    def states(n):
+        out = {}
+        for prec, name in ((numa.PREC_FP64, "fp64"), (numa.PREC_MIXED, "mixed")):
+            if name == "mixed" and args.no_mixed:
+                continue
+            q = q0.clone()
+            g.step(q, dt, n, prec=prec)
+            out[name] = q.cpu().numpy()
+        return out
+
+    acc_states = {1: states(1), 100: states(100)}
+    q0h = q0.cpu().numpy()
     g.set_metric(numa.METRIC_RECOMPUTE)
     filt = filter_leg(g, q0, dt, args.steps, stream, workload)
     rk53 = rk53_leg(g, q0, dt, args.steps, stream)
@@ -444,17 +543,34 @@ def main():
         _log("copy probe: 3 x %d MiB device copies" % args.copy_probe)
         del src, dst
 
+    n_elem, n_unique, n_local = g.n_elem, g.n_unique, g.n_local
     serve = None
     if args.serve_requests > 0:
-        del q0
+        del q0, g
         torch.cuda.empty_cache()
         precs = [(numa.PREC_FP64, "fp64")] + ([] if args.no_mixed else [(numa.PREC_MIXED, "mixed")])
         serve = serving(args.serve_requests, args.serve_budget_gb, precs)
 
     cpu = None
+    accuracy = {}
+    for n, st in acc_states.items():
+        if "mixed" in st:
+            accuracy["mixed_vs_fp64_state_%d" % n] = group_err(st["mixed"], st["fp64"])
+            accuracy["mixed_vs_fp64_increment_%d" % n] = group_err(st["mixed"] - q0h, st["fp64"] - q0h)
     if not args.no_cpu:
-        cpu = cpu_baseline(wl)
+        cpu, _, o1, on, nsteps = cpu_baseline(wl)
         _log("cpu oracle: %.3e updates/s" % cpu["value"])
+        accuracy["fp64_vs_oracle_state_1"] = group_err(acc_states[1]["fp64"], o1)
+        accuracy["fp64_vs_oracle_increment_1"] = group_err(acc_states[1]["fp64"] - q0h, o1 - q0h)
+        if "mixed" in acc_states[1]:
+            accuracy["mixed_vs_oracle_increment_1"] = group_err(acc_states[1]["mixed"] - q0h, o1 - q0h)
+        if nsteps == 100:
+            accuracy["fp64_vs_oracle_state_100"] = group_err(acc_states[100]["fp64"], on)
+            if "mixed" in acc_states[100]:
+                accuracy["mixed_vs_oracle_state_100"] = group_err(acc_states[100]["mixed"], on)
+    accuracy["norm"] = "max|a - b| / max|b| per variable group (rho'; u, v, w; theta')"
+    _log("accuracy: %s" % {k: ({g: "%.1e" % e for g, e in v.items()} if isinstance(v, dict) else v)
+                           for k, v in accuracy.items()})
 
     out = {
         "metric": "grid-point RHS updates/s",
@@ -469,12 +585,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": workload, "elements": g.n_elem, "order": mm["N"], "unique_nodes": g.n_unique,
-                   "local_nodes": g.n_local, "dt": dt, "integrator": "SSP-RK3", "metric": "recomputed each stage",
+        "config": {"workload": workload, "elements": n_elem, "order": mm["N"], "unique_nodes": n_unique,
+                   "local_nodes": n_local, "dt": dt, "integrator": "SSP-RK3", "metric": "recomputed each stage",
                    "parallelism": "single GPU"},
         "mixed": mixed,
         "stored_metric": stored,
         "roofline": roofline,
+        "accuracy": accuracy,
+        "stage_modes": modes,
         "filter": filt,
         "ssp53": rk53,
         "imex": imex,

@@ -77,6 +77,7 @@ def lib():
         L.or_step_rk53.argtypes = [P, ct.c_double, ct.c_int, P]
         L.or_imex_V.argtypes = [P, P, P]
         L.or_imex_step.argtypes = [P, ct.c_double, ct.c_double, ct.c_int, P, P, P, ct.c_int]
+        L.or_set_threads.argtypes = [ct.c_int]
         _lib = L
     return _lib
 
@@ -286,3 +287,8 @@ def rk53_combine(i: int, dt: float, U: np.ndarray, L: np.ndarray) -> np.ndarray:
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (timing only)."""
+    lib().or_set_threads(int(n))

@@ -1305,3 +1305,14 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* threads of the parallel loops from now on (timing only; results do not
+ * depend on the thread count) */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
