@@ -149,7 +149,14 @@ int32_t numa_mesh_attach_workspace(numa_mesh_t m, void *dev_ptr, uint64_t bytes,
  * state, gravity, wall normals, the column (and, shell, layer) factors of
  * the recomputed metric and the inverse of the mass summed from the
  * recomputed J w (used by the stages in NUMA_METRIC_RECOMPUTE mode), into
- * the workspace.  Asynchronous. */
+ * the workspace.  The hydrostatic reference state is computed here from ph
+ * (not passed in): the box's isentropic profile with theta0 = ph->T0, or the
+ * shell's isothermal one at T = ph->T0 with g = g0 (a/r)^2 (the paper's
+ * equation set is cited, not stated: a reading), with p_bar re-evaluated from
+ * the equation of state at every node; numa_export(NUMA_FIELD_REF) returns it.
+ * Asynchronous.  NUMA_EINVAL for invalid constants (R, cp, p0, T0 > 0,
+ * cp > R, g0 >= 0) or a box top at or above the isentropic model top;
+ * NUMA_ENOMEM without a workspace. */
 int32_t numa_geometry(numa_mesh_t m, const numa_phys *ph, void *stream);
 
 /* Metric terms of the element kernels (numa_rhs, numa_step, numa_step_batch).
@@ -214,10 +221,17 @@ int32_t numa_init_state(numa_mesh_t m, const numa_ic *ic, const double *noise, d
  * q and c_elem must not overlap. */
 int32_t numa_rhs(numa_mesh_t m, int32_t prec, const double *q, double *c_elem, void *stream);
 
-/* Direct stiffness summation of an element-local field c_elem [nvar][n_local]
- * into out [nvar][n_unique]: the sum over the copies of each unique node, in
- * ascending element-local order; NUMA_DSS_MASS divides by M; NUMA_DSS_NOFLUX
- * (nvar == 5) removes the wall-normal part of components 1..3. */
+/* Direct stiffness summation (the text after Eq. (derivatives): the element
+ * contributions are summed at the shared grid points and weighted by the
+ * element volumes, i.e. divided by the diagonal mass M_I = sum_e w_ijk J^e of
+ * Eq. (discstrongform); Code example 1: DSS and multiplication with the
+ * inverse mass matrix) of an element-local field c_elem [nvar][n_local]
+ * (device) into out [nvar][n_unique] (device): the sum over the copies of
+ * each unique node, in ascending element-local order; NUMA_DSS_MASS divides
+ * by M; NUMA_DSS_NOFLUX (nvar == 5) removes the wall-normal part of
+ * components 1..3 (the no-flux walls, a reading: the paper states no
+ * boundary condition).  c_elem and out must not overlap.  NUMA_EINVAL for a
+ * null pointer, nvar < 1, unknown flags or NOFLUX with nvar != 5. */
 int32_t numa_dss(numa_mesh_t m, int32_t nvar, const double *c_elem, double *out, int32_t flags,
                  void *stream);
 
@@ -242,13 +256,20 @@ int32_t numa_filter(numa_mesh_t m, double filter_order, int32_t cutoff, double *
  * F[i * (order + 1) + m], host memory, (order + 1)^2 doubles.  Host only. */
 int32_t numa_filter_matrix(int32_t order, double filter_order, int32_t cutoff, double *F);
 
-/* SSP-RK3 stage s in 0..2 (Shu-Osher form), pointwise over [5][n_unique]:
- * qout = a_s qn + b_s (qs + dt r), (a, b) = (0, 1), (3/4, 1/4), (1/3, 2/3).
- * qout may alias qs or qn; qn is not read for s = 0. */
+/* One explicit Runge-Kutta stage update ("update q" of Code example 1;
+ * Sec. "Time Discretization": the fully explicit scheme is a Runge-Kutta
+ * method whose coefficients the text does not give; the reading used here is
+ * SSP-RK3 in Shu-Osher form): stage s in 0..2, pointwise over [5][n_unique]
+ * (device), qout = a_s qn + b_s (qs + dt r), (a, b) = (0, 1), (3/4, 1/4),
+ * (1/3, 2/3); r is the DSS-ed right-hand side (numa_dss with
+ * NUMA_DSS_MASS | NUMA_DSS_NOFLUX of numa_rhs).  qout may alias qs or qn; qn
+ * is not read for s = 0.  NUMA_EINVAL for a null pointer or s outside 0..2. */
 int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn, const double *qs,
                       const double *r, double *qout, void *stream);
 
-/* nsteps Runge-Kutta steps in place on q [5][n_unique] (device) with the mesh's
+/* The time loop of Code example 1 (per stage: create_rhs, DSS and the
+ * multiplication with the inverse mass matrix, update q; Sec. "Time
+ * Discretization"): nsteps Runge-Kutta steps in place on q [5][n_unique] (device) with the mesh's
  * integrator (numa_mesh_set_integrator; SSP-RK3 unless set), each stage being
  * rhs -> DSS (mass, no-flux) -> stage update, fused into two kernels: the
  * element kernel writes every element-local node's contribution J w R
