@@ -160,25 +160,29 @@ def serving(n_req, budget_gb, precs, loads=(0.5, 0.8), seed=0):
                         steps=r["steps"]) for r in inputs.serving_requests(n_req, s, rate)]
 
     out = {"requests": n_req, "budget_gb": budget_gb, "steps_per_request": 50,
+           "budget_covers": "request states, scratch and flags, and every geometry workspace (LRU eviction of idle ones)",
            "mix": "box {8^3, 16^3, 32x32x8, 64x64x16} x N {3,4,5,6}, uniform"}
     for prec, name in precs:
         ex = GpuExecutor(prec=prec)
         srv = Server(ex, budget_bytes=int(budget_gb * 2 ** 30))
         b2b = make(1.0, seed)
-        srv.prewarm(b2b)
+        srv.prewarm(b2b, fraction=0.7)
+        rec0 = {"geometry_gb_prewarmed": srv.geom_bytes / 2 ** 30}
         st = srv.run(b2b, realtime=False)
         cap = n_req / st.wall
-        rec = {"capacity_req_per_s": cap, "throughput_updates_per_s": st.updates / st.wall,
-               "back_to_back_wall_s": st.wall, "max_active": st.max_active}
+        rec = dict(rec0, capacity_req_per_s=cap, throughput_updates_per_s=st.updates / st.wall,
+                   back_to_back_wall_s=st.wall, max_active=st.max_active, peak_gb=st.peak_bytes / 2 ** 30,
+                   failed=st.failed)
         _log("serving %s: capacity %.2f req/s, %.3e updates/s, max %d active" % (name, cap, st.updates / st.wall,
                                                                                 st.max_active))
         for load in loads:
             reqs = make(load * cap, seed + 1)
-            srv.prewarm(reqs)
+            srv.prewarm(reqs, fraction=0.7)
             st = srv.run(reqs, realtime=True)
             rec["load_%.1f" % load] = {"rate_req_per_s": load * cap, "p50_s": st.percentile(50),
                                        "p99_s": st.percentile(99), "throughput_updates_per_s": st.updates / st.wall,
-                                       "max_active": st.max_active, "peak_gb": st.peak_bytes / 2 ** 30}
+                                       "max_active": st.max_active, "peak_gb": st.peak_bytes / 2 ** 30,
+                                       "failed": st.failed}
             _log("serving %s at %.1f C: p50 %.3f s, p99 %.3f s" % (name, load, st.percentile(50), st.percentile(99)))
         ex.drop_graphs()
         out[name] = rec
@@ -371,7 +375,8 @@ def main():
     ap.add_argument("--small", action="store_true", help="4x4x4 box instead of the one-GPU workload")
     ap.add_argument("--sweep", action="store_true", help="order sweep and shell instead of the bench line")
     ap.add_argument("--serve-requests", type=int, default=1000, help="requests per serving run (0: skip)")
-    ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=28.0,
+                    help="device memory for geometry and requests (admission binds below it)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()

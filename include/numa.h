@@ -376,6 +376,8 @@ typedef struct numa_batch_item {
     void *scratch;
     uint64_t scratch_bytes;  /* size of scratch: at least numa_step_scratch_bytes() */
     double dt;
+    int32_t *nonfinite;      /* device, or NULL: set to 1 (never cleared) when a stage
+                                writes a non-finite value into the item's state */
 } numa_batch_item;
 
 int32_t numa_step_scratch_bytes(numa_mesh_t m, int32_t prec, uint64_t *bytes);

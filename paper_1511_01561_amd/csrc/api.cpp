@@ -669,7 +669,8 @@ int32_t numa_step_batch(const numa_batch_item *items, int32_t n, int32_t prec, i
         void *ev = scr + align256(40ull * m->nu);
         for (int j = 0; j < ns; ++j) {
             const StagePlan &p = plan[j];
-            st[(size_t)j * n + k] = {m, buf[p.ref], buf[p.in], buf[p.out], ev, stage_coef(p, items[k].dt)};
+            st[(size_t)j * n + k] = {m, buf[p.ref], buf[p.in], buf[p.out], ev, stage_coef(p, items[k].dt),
+                                     items[k].nonfinite};
         }
     }
     for (int32_t step = 0; step < nsteps; ++step) {

@@ -25,7 +25,8 @@ struct BatchItem {
     const void *met;      // [ne][10][np] of T
     void *ev;             // [nl][5] of T: contributions of this stage, node-major
     const double *hcol;   // column factors of the recomputed metric
-    int64_t nu, nh;
+    int32_t *flag;        // non-finite flag of the item's state, or null
+    int nu, nh;           // unique nodes, per level (meshes are limited to 32-bit indices)
     int ni, nj, nkw;      // lattice extents; nkw: extent in z when periodic, else -1
     int nz, walls;
     int ne;               // elements
@@ -380,9 +381,11 @@ __global__ void k_colour_finish(Batch B)
         r[v] = acc[I + v * it.nu] * mi;
         qnv[v] = sc.a == 0.0 ? 0.0 : it.qn[I + v * it.nu];
     }
+    double o[5];
     if (B.fold && !wall) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) it.qout[I + v * it.nu] = rk_update_folded(sc, qnv[v], r[v]);
+        for (int v = 0; v < 5; ++v) it.qout[I + v * it.nu] = o[v] = rk_update_folded(sc, qnv[v], r[v]);
+        flag_nonfinite(it.flag, o, 5);
         return;
     }
     PointArgs p;
@@ -396,7 +399,8 @@ __global__ void k_colour_finish(Batch B)
     p.walls = it.walls;
     noflux(p, I, r[1], r[2], r[3]);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) it.qout[I + v * it.nu] = rk_update(sc, qnv[v], it.qs[I + v * it.nu], r[v]);
+    for (int v = 0; v < 5; ++v) it.qout[I + v * it.nu] = o[v] = rk_update(sc, qnv[v], it.qs[I + v * it.nu], r[v]);
+    flag_nonfinite(it.flag, o, 5);
 }
 
 // Streaming variant of the column kernel: after the tile is built the lane
@@ -561,7 +565,8 @@ __global__ void k_fin_batch(Batch B)
     b.nj = it.nj;
     b.fold = B.fold;
     box_finish_node<N, SEG, T, PLAIN>(p, b, (const T *)it.ev, sx, ey, kbase == 0 ? (int)ez : it.nz - 1, threadIdx.x,
-                                      kbase, klayers, StageCoef{B.ca, B.cb, it.cdt}, it.qn, it.qs, it.qout);
+                                      kbase, klayers, StageCoef{B.ca, B.cb, it.cdt}, it.qn, it.qs, it.qout,
+                                      PLAIN ? nullptr : it.flag);
 }
 
 template <int N, typename T>
@@ -604,8 +609,9 @@ int32_t run_chunk(const StepItem *items, int n, int phase, hipStream_t s, bool c
         it.met = std::is_same<T, float>::value ? (const void *)m.dv.met32 : (const void *)m.dv.met;
         it.ev = items[k].ev;
         it.hcol = m.dv.hcol;
-        it.nu = m.nu;
-        it.nh = m.nh;
+        it.flag = items[k].flag;
+        it.nu = (int)m.nu;
+        it.nh = (int)m.nh;
         it.ni = (int)m.ni;
         it.nj = (int)m.nj;
         it.nkw = m.d.periodic[2] ? (int)m.nk : -1;
@@ -686,8 +692,9 @@ int32_t run_plain_finish(const Mesh &m, const double *ev, double *q, hipStream_t
     it.Minv = stage_minv(m);  // the box filter's J w follows the metric mode
     it.nrm = m.dv.nrm;
     it.ev = (void *)ev;
-    it.nu = m.nu;
-    it.nh = m.nh;
+    it.flag = nullptr;
+    it.nu = (int)m.nu;
+    it.nh = (int)m.nh;
     it.ni = (int)m.ni;
     it.nj = (int)m.nj;
     it.nz = m.d.ne[2];

@@ -413,6 +413,16 @@ __device__ inline void noflux(const PointArgs &p, int64_t I, double &r1, double 
     r3 -= dn * n2;
 }
 
+// Sets *flag (when given) if any of the n values is not finite: a plain store
+// of 1 by every such lane, the flag is never cleared here.
+__device__ __forceinline__ void flag_nonfinite(int32_t *flag, const double *v, int n)
+{
+    if (!flag) return;
+    bool bad = false;
+    for (int k = 0; k < n; ++k) bad |= !isfinite(v[k]);
+    if (bad) *flag = 1;
+}
+
 // Runge-Kutta stage update (Shu-Osher form, StageCoef): y = q_s + cdt R, then
 // q_out = a q_ref + b y (y itself when a = 0 and b = 1); with b = 0 the update
 // is q_ref a + cdt R (the explicit leap-frog step: q_s is not used).  The
@@ -463,7 +473,8 @@ struct BoxFin {
 template <int N, int SEG, typename T, bool PLAIN = false>
 __device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin &b, const T *ev, int sx, int ey,
                                                 int ez, int lane, int kbase, int klayers, const StageCoef &sc,
-                                                const double *qn, const double *qs, double *qout)
+                                                const double *qn, const double *qs, double *qout,
+                                                int32_t *flag = nullptr)
 {
     constexpr int P = N + 1, NP = P * P * P, W = SEG * N;
     if (lane >= W * N * klayers) return;
@@ -549,14 +560,18 @@ __device__ __forceinline__ void box_finish_node(const PointArgs &p, const BoxFin
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) r[v] *= mi;
+    double o[5];
     if (folded) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) qoi[v * p.nu] = rk_update_folded(sc, qnv[v], r[v]);
-        return;
-    }
-    noflux(p, I, r[1], r[2], r[3]);
+        for (int v = 0; v < 5; ++v) o[v] = rk_update_folded(sc, qnv[v], r[v]);
+    } else {
+        noflux(p, I, r[1], r[2], r[3]);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) qoi[v * p.nu] = PLAIN ? r[v] : rk_update(sc, qnv[v], qsv[v], r[v]);
+        for (int v = 0; v < 5; ++v) o[v] = PLAIN ? r[v] : rk_update(sc, qnv[v], qsv[v], r[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) qoi[v * p.nu] = o[v];
+    flag_nonfinite(flag, o, 5);
 }
 
 // Copy n values staged in LDS (st) to out with 16-byte stores: the leading values until out is 16-byte aligned one by one, then

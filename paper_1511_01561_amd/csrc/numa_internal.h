@@ -183,6 +183,7 @@ struct StepItem {
     double *qout;
     void *ev;
     StageCoef c;
+    int32_t *flag = nullptr;  // device: set to 1 when the stage writes a non-finite value
 };
 
 // Box meshes whose x extent fits the finish block's segment take the batched

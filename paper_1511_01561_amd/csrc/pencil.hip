@@ -62,6 +62,7 @@ struct PenItem {
     const double *ref, *Minv, *nrm, *hcol;
     double *py;        // partial sums on the y block faces [nby][2][nbz][WZ+1][ni][5]
     double *pz;        // partial sums on the z block faces [nbz][2][nj][ni][5]
+    int32_t *flag;     // non-finite flag of the item's state, or null
     int64_t nu, nh;
     int ni, nj, nk;    // lattice extents (nk = nz N + 1 levels)
     int nx, ny, nz;
@@ -104,9 +105,11 @@ __device__ __forceinline__ void pen_finish(const PenItem &it, const PenBatch &B,
     for (int v = 0; v < 5; ++v) qnv[v] = sc.a == 0.0 ? 0.0 : it.qn[I + v * it.nu];
 #pragma unroll
     for (int v = 0; v < 5; ++v) r[v] *= mi;
+    double o[5];
     if (B.fold && !wall) {
 #pragma unroll
-        for (int v = 0; v < 5; ++v) it.qout[I + v * it.nu] = rk_update_folded(sc, qnv[v], r[v]);
+        for (int v = 0; v < 5; ++v) it.qout[I + v * it.nu] = o[v] = rk_update_folded(sc, qnv[v], r[v]);
+        flag_nonfinite(it.flag, o, 5);
         return;
     }
     PointArgs p;
@@ -120,7 +123,8 @@ __device__ __forceinline__ void pen_finish(const PenItem &it, const PenBatch &B,
     p.walls = 1;
     noflux(p, I, r[1], r[2], r[3]);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) it.qout[I + v * it.nu] = rk_update(sc, qnv[v], it.qs[I + v * it.nu], r[v]);
+    for (int v = 0; v < 5; ++v) it.qout[I + v * it.nu] = o[v] = rk_update(sc, qnv[v], it.qs[I + v * it.nu], r[v]);
+    flag_nonfinite(it.flag, o, 5);
 }
 
 // workgroups per CU the block kernel is compiled for: two at N = 4 (the
@@ -541,9 +545,10 @@ __global__ __launch_bounds__(pen_threads<N>(), (pen_min_blocks<N, T>())) void k_
                     const StageCoef sc{B.ca, B.cb, it.cdt};
 #pragma unroll
                     for (int v = 0; v < 5; ++v) r[v] *= fm[kk];
+                    double o[5];
                     if (B.fold && !wall) {
 #pragma unroll
-                        for (int v = 0; v < 5; ++v) it.qout[I + v * it.nu] = rk_update_folded(sc, fn[kk][v], r[v]);
+                        for (int v = 0; v < 5; ++v) it.qout[I + v * it.nu] = o[v] = rk_update_folded(sc, fn[kk][v], r[v]);
                     } else {
                         if (wall) {
                             const double n0 = gk == 0 ? nb[0] : nt[0], n1 = gk == 0 ? nb[1] : nt[1],
@@ -554,8 +559,9 @@ __global__ __launch_bounds__(pen_threads<N>(), (pen_min_blocks<N, T>())) void k_
                             r[3] -= dn * n2;
                         }
 #pragma unroll
-                        for (int v = 0; v < 5; ++v) it.qout[I + v * it.nu] = rk_update(sc, fn[kk][v], fs[kk][v], r[v]);
+                        for (int v = 0; v < 5; ++v) it.qout[I + v * it.nu] = o[v] = rk_update(sc, fn[kk][v], fs[kk][v], r[v]);
                     }
+                    flag_nonfinite(it.flag, o, 5);
                 }
             }
         }
@@ -677,6 +683,7 @@ int32_t pen_chunk(const StepItem *items, int n, int phase, hipStream_t s)
         it.nrm = m.dv.nrm;
         it.hcol = m.dv.hcol;
         it.py = (double *)items[k].ev;
+        it.flag = items[k].flag;
         it.nu = m.nu;
         it.nh = m.nh;
         it.ni = (int)m.ni;

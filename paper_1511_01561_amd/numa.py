@@ -49,7 +49,7 @@ class numa_ic(ct.Structure):
 
 class numa_batch_item(ct.Structure):
     _fields_ = [("mesh", ct.c_void_p), ("q", ct.c_void_p), ("scratch", ct.c_void_p), ("scratch_bytes", ct.c_uint64),
-                ("dt", ct.c_double)]
+                ("dt", ct.c_double), ("nonfinite", ct.c_void_p)]
 
 
 class NumaError(RuntimeError):
@@ -142,18 +142,40 @@ def _ptr(t):
     return ct.c_void_p(t.data_ptr())
 
 
+def _desc(mesh: dict):
+    d = numa_mesh_desc()
+    d.kind = int(mesh["kind"]); d.order = int(mesh["N"])
+    for a in range(3):
+        d.ne[a] = int(mesh["ne"][a]); d.periodic[a] = int(mesh["periodic"][a])
+        d.extent[a] = float(mesh["extent"][a])
+    d.terrain_amp = float(mesh.get("h0", 0.0))
+    return d
+
+
+def mesh_sizes(mesh: dict, prec_mask: int, prec: int):
+    """Host only: (device workspace bytes, unique nodes, batch scratch bytes of
+    one item in precision prec) of a mesh description, without building it on
+    the device."""
+    d = _desc(mesh)
+    h = ct.c_void_p()
+    check(lib().numa_mesh_create(ct.byref(d), ct.byref(h)))
+    try:
+        nb, sb, nu = ct.c_uint64(), ct.c_uint64(), ct.c_int64()
+        check(lib().numa_mesh_workspace_bytes(h, prec_mask, ct.byref(nb)))
+        check(lib().numa_step_scratch_bytes(h, prec, ct.byref(sb)))
+        check(lib().numa_mesh_info(h, None, None, ct.byref(nu), None, None))
+        return nb.value, nu.value, sb.value
+    finally:
+        lib().numa_mesh_destroy(h)
+
+
 class Mesh:
     """A mesh handle with its device workspace (a torch uint8 tensor)."""
 
     def __init__(self, mesh: dict, phys: dict, prec_mask: int = 3, device="cuda:0", stream=None):
         import torch
         self.device = torch.device(device)
-        d = numa_mesh_desc()
-        d.kind = int(mesh["kind"]); d.order = int(mesh["N"])
-        for a in range(3):
-            d.ne[a] = int(mesh["ne"][a]); d.periodic[a] = int(mesh["periodic"][a])
-            d.extent[a] = float(mesh["extent"][a])
-        d.terrain_amp = float(mesh.get("h0", 0.0))
+        d = _desc(mesh)
         self._desc = d
         h = ct.c_void_p()
         check(lib().numa_mesh_create(ct.byref(d), ct.byref(h)))
@@ -301,20 +323,24 @@ def alloc_scratch(mesh: Mesh, prec: int):
 
 
 def _items(items):
-    """items: sequence of (mesh, q, scratch, dt)"""
+    """items: sequence of (mesh, q, scratch, dt) or (mesh, q, scratch, dt, flag),
+    flag a device int32 tensor element (a view of one element) or None"""
     arr = (numa_batch_item * len(items))()
-    for k, (m, q, scr, dt) in enumerate(items):
+    for k, it in enumerate(items):
+        m, q, scr, dt = it[:4]
+        flag = it[4] if len(it) > 4 else None
         arr[k].mesh = m._h.value if isinstance(m._h, ct.c_void_p) else m._h
         arr[k].q = q.data_ptr()
         arr[k].scratch = scr.data_ptr()
         arr[k].scratch_bytes = scr.numel() * scr.element_size()
         arr[k].dt = float(dt)
+        arr[k].nonfinite = flag.data_ptr() if flag is not None else None
     return arr
 
 
 def step_batch(items, nsteps: int, prec: int = PREC_FP64, stream=None):
-    """Advance every (mesh, q, scratch, dt) item by nsteps steps in batched
-    launches (same order, metric mode and integrator, box meshes)."""
+    """Advance every (mesh, q, scratch, dt[, flag]) item by nsteps steps in
+    batched launches (same order, metric mode and integrator, box meshes)."""
     arr = _items(items)
     check(lib().numa_step_batch(arr, len(items), prec, int(nsteps), _stream(stream)))
 

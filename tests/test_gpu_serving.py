@@ -136,8 +136,10 @@ def test_serving_results_same_alone_and_in_the_mix(torch_cuda, prec):
         wl = box(n, N, 30 + i, nz=max(2, n // 2))
         reqs.append(Request(id=i, arrival=0.0, workload=wl, noise_seed=500 + i, steps=4 + (i % 3)))
     ex = GpuExecutor(prec=prec)
-    # budget for about three of the larger requests at once, so admission binds
-    budget = 3 * ex.request_bytes(reqs[-1], ex.geometry(reqs[-1]))
+    # every geometry, and room for about three of the larger requests at once,
+    # so admission binds
+    geoms = {r.key: ex.sizes(r)[0] for r in reqs}
+    budget = sum(geoms.values()) + 3 * ex.sizes(reqs[-1])[1]
     srv = Server(ex, budget_bytes=budget, keep_states=True)
     srv.prewarm(reqs)
     st = srv.run(reqs, realtime=False)
@@ -177,3 +179,64 @@ def test_serving_mixed_integrators_and_filters(torch_cuda):
         assert torch.equal(q, r.state), r.id
     ex.drop_graphs()
 
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_nonfinite_request_retires_alone(torch_cuda, prec):
+    """A request whose state is not finite (a NaN bubble amplitude) is retired
+    as failed after its first iteration, through the per-request flag the
+    stage kernels set; the requests batched with it finish with their
+    results bitwise equal to their runs alone."""
+    from paper_1511_01561_amd.serve import GpuExecutor, Request, Server
+    torch = torch_cuda
+    reqs = []
+    for i, (n, N) in enumerate([(8, 4), (4, 4), (8, 3), (4, 4)]):
+        wl = box(n, N, 80 + i, nz=max(2, n // 2))
+        if i == 1:
+            wl["ic"]["amp"] = float("nan")
+        reqs.append(Request(id=i, arrival=0.0, workload=wl, noise_seed=900 + i, steps=5))
+    ex = GpuExecutor(prec=prec)
+    srv = Server(ex, budget_bytes=1 << 34, keep_states=True)
+    srv.prewarm(reqs)
+    st = srv.run(reqs, realtime=False)
+    assert st.failed == 1 and reqs[1].failed and len(st.latencies) == 3
+    assert reqs[1].done < reqs[0].done
+    for r in reqs:
+        if r.failed:
+            continue
+        g = ex.geometry(r)
+        q = g.init_state(r.workload["ic"], inputs.device_noise(g.n_unique, r.noise_seed))
+        g.step(q, 0.05, r.steps, prec=prec)
+        torch.cuda.synchronize()
+        assert torch.equal(q, r.state), r.id
+    ex.drop_graphs()
+
+
+def test_admission_counts_geometry_and_evicts_idle_geometry(torch_cuda):
+    """The budget covers geometry workspaces too: with room for one geometry
+    and one request at a time, requests of two mesh shapes run one after the
+    other, the idle geometry evicted in between, and every result is the
+    request's run alone."""
+    from paper_1511_01561_amd.serve import GpuExecutor, Request, Server
+    torch = torch_cuda
+    reqs = []
+    for i in range(4):  # two mesh shapes of the same size (terrain 500 m and 300 m), alternating
+        wl = box(8, 4, 120 + i, nz=2)
+        if i % 2:
+            wl["mesh"]["h0"] = 300.0
+        reqs.append(Request(id=i, arrival=0.0, workload=wl, noise_seed=950 + i, steps=3))
+    ex = GpuExecutor(prec=0)
+    sizes = [ex.sizes(r) for r in reqs]
+    assert len({r.key for r in reqs}) == 2
+    budget = max(g + q for g, q in sizes) + 4096  # one geometry and one request
+    srv = Server(ex, budget_bytes=budget, keep_states=True)
+    st = srv.run(reqs, realtime=False)
+    assert len(st.latencies) == 4 and st.peak_bytes <= budget and st.max_active == 1
+    assert len(srv.geoms) == 1
+    for r in reqs:
+        g = ex.geometry(r)
+        q = g.init_state(r.workload["ic"], inputs.device_noise(g.n_unique, r.noise_seed))
+        g.step(q, 0.05, r.steps)
+        torch.cuda.synchronize()
+        assert torch.equal(q, r.state), r.id
+    ex.drop_graphs()
