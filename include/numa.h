@@ -383,6 +383,31 @@ typedef struct numa_batch_item {
 int32_t numa_step_scratch_bytes(numa_mesh_t m, int32_t prec, uint64_t *bytes);
 int32_t numa_step_batch(const numa_batch_item *items, int32_t n, int32_t prec, int32_t nsteps, void *stream);
 
+/* ---- Batched steps without device allocation ----
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * numa_step_batch with each item's scratch taken from a static device array
+ * of the library, NUMA_NOALLOC_SCRATCH_BYTES on each GPU it runs on (held
+ * from the first call there until the process ends), instead of a caller
+ * buffer.  Items, precision, step count and results are as numa_step_batch's
+ * (the same kernels: bitwise the same results), except that every item's
+ * scratch must be NULL and its scratch_bytes 0.  The items' scratch lies one
+ * after another in the array, numa_step_scratch_bytes() each: NUMA_ENOMEM
+ * when the sum exceeds NUMA_NOALLOC_SCRATCH_BYTES; NUMA_EINVAL for more than
+ * NUMA_NOALLOC_MAX_ITEMS items or a mesh that is profiling.  No device or
+ * host allocation.  Runs on the current device; the first call on a device
+ * looks up the array's address there, and a call with nsteps = 0 does only
+ * that (items are not read): make one before capturing the call into a graph.
+ * Nothing in the array needs to start at zero (every stage writes its
+ * scratch before reading it).  All calls on one GPU share its array, which
+ * keeps the last call's contents: calls that overlap in time on one GPU
+ * (other streams, host threads, or graph replays) race and give wrong
+ * results.  The meshes' workspaces (geometry, the filter's scratch) remain
+ * the caller's, attached beforehand. */
+#define NUMA_NOALLOC_SCRATCH_BYTES (128ull << 20)
+#define NUMA_NOALLOC_MAX_ITEMS 64
+int32_t numa_step_batch_noalloc(const numa_batch_item *items, int32_t n, int32_t prec, int32_t nsteps, void *stream);
+
 /* Capture numa_step_batch(items, n, prec, nsteps) on a non-default stream into
  * a HIP graph (no memory operations inside); numa_graph_launch replays it on
  * any stream with the same arguments (the same device buffers), so membership

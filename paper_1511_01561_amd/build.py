@@ -17,7 +17,8 @@ ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libnuma.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["api.cpp", "mesh.cpp", "geometry.hip", "rhs.hip", "dss.hip", "batch.hip", "pencil.hip", "filter.hip", "imex.hip"]
+SOURCES = ["api.cpp", "mesh.cpp", "geometry.hip", "rhs.hip", "dss.hip", "batch.hip", "pencil.hip", "filter.hip", "imex.hip",
+           "noalloc.hip"]
 
 ARCH = "gfx950"
 CFLAGS = [

@@ -603,7 +603,12 @@ int32_t numa_step_scratch_bytes(numa_mesh_t m, int32_t prec, uint64_t *bytes)
     return NUMA_OK;
 }
 
-static int32_t check_batch(const numa_batch_item *items, int32_t n, int32_t prec, const char *fn)
+}  // extern "C"
+
+// own_scratch: the items bring their scratch (numa_step_batch), else the
+// library supplies it, the items' scratch fields must be empty and no mesh
+// may be profiling (that creates events)
+int32_t numa::check_batch(const numa_batch_item *items, int32_t n, int32_t prec, bool own_scratch, const char *fn)
 {
     if (!items || n < 1) {
         set_error("%s: no items", fn);
@@ -630,17 +635,29 @@ static int32_t check_batch(const numa_batch_item *items, int32_t n, int32_t prec
             set_error("%s: item %d uses another integrator than item 0 (one integrator per batch)", fn, k);
             return NUMA_EINVAL;
         }
-        if (!items[k].q || !items[k].scratch || reinterpret_cast<uintptr_t>(items[k].scratch) % 256) {
-            set_error("%s: item %d: null state or scratch not 256-byte aligned", fn, k);
+        if (!items[k].q) {
+            set_error("%s: item %d: null state", fn, k);
             return NUMA_EINVAL;
         }
-        if (items[k].scratch_bytes < scratch_bytes(*m, prec)) {
+        if (!own_scratch) {
+            if (items[k].scratch || items[k].scratch_bytes) {
+                set_error("%s: item %d: the library supplies the scratch; pass NULL and 0", fn, k);
+                return NUMA_EINVAL;
+            }
+            if (m->profiling) {  // the profile creates events as it goes
+                set_error("%s: item %d: disable numa_profile on the items' meshes first", fn, k);
+                return NUMA_EINVAL;
+            }
+        } else if (!items[k].scratch || reinterpret_cast<uintptr_t>(items[k].scratch) % 256) {
+            set_error("%s: item %d: null scratch or scratch not 256-byte aligned", fn, k);
+            return NUMA_EINVAL;
+        } else if (items[k].scratch_bytes < scratch_bytes(*m, prec)) {
             set_error("%s: item %d: scratch of %llu bytes, the item needs %llu", fn, k,
                       (unsigned long long)items[k].scratch_bytes, (unsigned long long)scratch_bytes(*m, prec));
             return NUMA_ENOMEM;
         }
         for (int32_t j = 0; j < k; ++j)
-            if (items[j].q == items[k].q || items[j].scratch == items[k].scratch) {
+            if (items[j].q == items[k].q || (own_scratch && items[j].scratch == items[k].scratch)) {
                 set_error("%s: items %d and %d share a state or a scratch buffer", fn, j, k);
                 return NUMA_EINVAL;
             }
@@ -648,21 +665,33 @@ static int32_t check_batch(const numa_batch_item *items, int32_t n, int32_t prec
     return NUMA_OK;
 }
 
-int32_t numa_step_batch(const numa_batch_item *items, int32_t n, int32_t prec, int32_t nsteps, void *stream)
+uint64_t numa::batch_pool_bytes(const numa_batch_item *items, int32_t n, int32_t prec)
 {
-    int32_t rc = check_batch(items, n, prec, "numa_step_batch");
-    if (rc) return rc;
-    if (nsteps < 0) {
-        set_error("numa_step_batch: negative step count");
-        return NUMA_EINVAL;
-    }
-    hipStream_t s = as_stream(stream);
+    uint64_t total = 0;
+    for (int32_t k = 0; k < n; ++k) total += scratch_bytes(*items[k].mesh, prec);
+    return total;
+}
+
+int numa::batch_stages(const numa_batch_item *items)
+{
+    int ns;
+    (void)stage_plan(items[0].mesh->integrator, &ns);
+    return ns;
+}
+
+// nsteps steps of a checked batch.  pool: null when each item brings its
+// scratch, else the items' scratch lies one after another in pool (each
+// numa_step_scratch_bytes, a multiple of 256).  st: room for the stages of
+// the integrator times n stage items.
+int32_t numa::run_step_batch(const numa_batch_item *items, int32_t n, int32_t prec, int32_t nsteps, char *pool,
+                             StepItem *st, hipStream_t s)
+{
     int ns;
     const StagePlan *plan = stage_plan(items[0].mesh->integrator, &ns);
-    std::vector<numa::StepItem> st((size_t)ns * n);
     for (int32_t k = 0; k < n; ++k) {
         const Mesh *m = items[k].mesh;
-        char *scr = static_cast<char *>(items[k].scratch);
+        char *scr = pool ? pool : static_cast<char *>(items[k].scratch);
+        if (pool) pool += scratch_bytes(*m, prec);
         const uint64_t evb = contribution_bytes(*m, prec);
         double *buf[3] = {items[k].q, reinterpret_cast<double *>(scr),
                           reinterpret_cast<double *>(scr + align256(40ull * m->nu) + evb)};
@@ -673,6 +702,7 @@ int32_t numa_step_batch(const numa_batch_item *items, int32_t n, int32_t prec, i
                                      items[k].nonfinite};
         }
     }
+    int32_t rc;
     for (int32_t step = 0; step < nsteps; ++step) {
         for (int j = 0; j < ns; ++j)
             if ((rc = run_batch_stage(&st[(size_t)j * n], n, prec, s))) return rc;
@@ -680,6 +710,20 @@ int32_t numa_step_batch(const numa_batch_item *items, int32_t n, int32_t prec, i
             if ((rc = run_filter(items[k].mesh, items[k].q, s))) return rc;
     }
     return NUMA_OK;
+}
+
+extern "C" {
+
+int32_t numa_step_batch(const numa_batch_item *items, int32_t n, int32_t prec, int32_t nsteps, void *stream)
+{
+    int32_t rc = numa::check_batch(items, n, prec, true, "numa_step_batch");
+    if (rc) return rc;
+    if (nsteps < 0) {
+        set_error("numa_step_batch: negative step count");
+        return NUMA_EINVAL;
+    }
+    std::vector<numa::StepItem> st((size_t)numa::batch_stages(items) * n);
+    return numa::run_step_batch(items, n, prec, nsteps, nullptr, st.data(), as_stream(stream));
 }
 
 int32_t numa_batch_capture(const numa_batch_item *items, int32_t n, int32_t prec, int32_t nsteps, void *stream,
@@ -690,7 +734,7 @@ int32_t numa_batch_capture(const numa_batch_item *items, int32_t n, int32_t prec
         return NUMA_EINVAL;
     }
     *out = nullptr;
-    int32_t rc = check_batch(items, n, prec, "numa_batch_capture");
+    int32_t rc = numa::check_batch(items, n, prec, true, "numa_batch_capture");
     if (rc) return rc;
     if (!stream) {
         set_error("numa_batch_capture: capture needs a non-default stream");

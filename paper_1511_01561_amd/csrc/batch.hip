@@ -774,18 +774,25 @@ bool colour_ok(const Mesh &m)
 
 int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int phase, hipStream_t s)
 {
-    // items the fused block kernels take (pencil.hip), the colour passes, the rest
-    std::vector<StepItem> pen, col, rest;
-    for (int k = 0; k < n; ++k)
-        (pencil_stage_ok(items[k], prec) ? pen : colour_ok(*items[k].mesh) ? col : rest).push_back(items[k]);
-    int32_t rc = NUMA_OK;
-    if (!pen.empty() && (rc = launch_pencil_stage(pen.data(), (int)pen.size(), prec, phase, s))) return rc;
-    for (int g = 0; g < 2; ++g) {
-        const std::vector<StepItem> &v = g == 0 ? col : rest;
-        if (v.empty()) continue;
-        rc = prec == NUMA_PREC_MIXED ? run_stage_t<float>(v.data(), (int)v.size(), phase, s, g == 0)
-                                     : run_stage_t<double>(v.data(), (int)v.size(), phase, s, g == 0);
-        if (rc) return rc;
+    // items the fused block kernels take (pencil.hip), the colour passes, the
+    // rest; partitioned in chunks on the stack, with no host allocation
+    constexpr int kChunk = 4 * kMaxBatch;
+    StepItem part[3][kChunk];
+    for (int c0 = 0; c0 < n; c0 += kChunk) {
+        const int cn = n - c0 < kChunk ? n - c0 : kChunk;
+        int cnt[3] = {0, 0, 0};
+        for (int k = c0; k < c0 + cn; ++k) {
+            const int g = pencil_stage_ok(items[k], prec) ? 0 : colour_ok(*items[k].mesh) ? 1 : 2;
+            part[g][cnt[g]++] = items[k];
+        }
+        int32_t rc;
+        if (cnt[0] && (rc = launch_pencil_stage(part[0], cnt[0], prec, phase, s))) return rc;
+        for (int g = 1; g < 3; ++g) {
+            if (!cnt[g]) continue;
+            rc = prec == NUMA_PREC_MIXED ? run_stage_t<float>(part[g], cnt[g], phase, s, g == 1)
+                                         : run_stage_t<double>(part[g], cnt[g], phase, s, g == 1);
+            if (rc) return rc;
+        }
     }
     return NUMA_OK;
 }

@@ -191,6 +191,17 @@ struct StepItem {
 bool box_batchable(const Mesh &m);
 int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int phase, hipStream_t s);
 
+// Batched steps (api.cpp), shared by numa_step_batch and the no-allocation
+// variant: argument checks (own_scratch: each item brings its scratch, else
+// the library supplies it), the scratch the items need laid out one after
+// another, the stages of the items' integrator, and the run itself (pool:
+// null for the items' own scratch; st: stages x n stage items).
+int32_t check_batch(const numa_batch_item *items, int32_t n, int32_t prec, bool own_scratch, const char *fn);
+uint64_t batch_pool_bytes(const numa_batch_item *items, int32_t n, int32_t prec);
+int batch_stages(const numa_batch_item *items);
+int32_t run_step_batch(const numa_batch_item *items, int32_t n, int32_t prec, int32_t nsteps, char *pool,
+                       StepItem *st, hipStream_t s);
+
 // The fused block stage (pencil.hip): box meshes with walls, recomputed
 // metric, N = 2..4, nx and ny multiples of the block; phase 0 launches the
 // block kernel, phase 1 the kernel of the nodes shared between blocks.  The

@@ -29,7 +29,8 @@ EXPORTED = ["numa_last_error", "numa_gll", "numa_mesh_create", "numa_mesh_destro
             "numa_rk_stage", "numa_step", "numa_profile", "numa_profile_read", "numa_step_scratch_bytes",
             "numa_step_batch", "numa_batch_capture", "numa_graph_launch", "numa_graph_destroy",
             "numa_mesh_set_metric", "numa_filter", "numa_filter_matrix", "numa_mesh_set_filter",
-            "numa_mesh_set_integrator", "numa_imex_step", "numa_stage_rhs", "numa_mesh_set_stage"]
+            "numa_mesh_set_integrator", "numa_imex_step", "numa_stage_rhs", "numa_mesh_set_stage",
+            "numa_step_batch_noalloc"]
 
 
 class numa_mesh_desc(ct.Structure):
@@ -95,6 +96,7 @@ def lib():
         "numa_profile_read": (I32, [P, P]),
         "numa_step_scratch_bytes": (I32, [P, I32, ct.POINTER(ct.c_uint64)]),
         "numa_step_batch": (I32, [ct.POINTER(numa_batch_item), I32, I32, I32, P]),
+        "numa_step_batch_noalloc": (I32, [ct.POINTER(numa_batch_item), I32, I32, I32, P]),
         "numa_batch_capture": (I32, [ct.POINTER(numa_batch_item), I32, I32, I32, P, ct.POINTER(P)]),
         "numa_graph_launch": (I32, [P, P]),
         "numa_graph_destroy": (I32, [P]),
@@ -324,15 +326,16 @@ def alloc_scratch(mesh: Mesh, prec: int):
 
 def _items(items):
     """items: sequence of (mesh, q, scratch, dt) or (mesh, q, scratch, dt, flag),
-    flag a device int32 tensor element (a view of one element) or None"""
+    scratch None for the library's own, flag a device int32 tensor element (a
+    view of one element) or None"""
     arr = (numa_batch_item * len(items))()
     for k, it in enumerate(items):
         m, q, scr, dt = it[:4]
         flag = it[4] if len(it) > 4 else None
         arr[k].mesh = m._h.value if isinstance(m._h, ct.c_void_p) else m._h
         arr[k].q = q.data_ptr()
-        arr[k].scratch = scr.data_ptr()
-        arr[k].scratch_bytes = scr.numel() * scr.element_size()
+        arr[k].scratch = scr.data_ptr() if scr is not None else None
+        arr[k].scratch_bytes = scr.numel() * scr.element_size() if scr is not None else 0
         arr[k].dt = float(dt)
         arr[k].nonfinite = flag.data_ptr() if flag is not None else None
     return arr
@@ -343,6 +346,18 @@ def step_batch(items, nsteps: int, prec: int = PREC_FP64, stream=None):
     batched launches (same order, metric mode and integrator, box meshes)."""
     arr = _items(items)
     check(lib().numa_step_batch(arr, len(items), prec, int(nsteps), _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
+NOALLOC_MAX_ITEMS = 64
+
+
+def step_batch_noalloc(items, nsteps: int, prec: int = PREC_FP64, stream=None):
+    """step_batch over (mesh, q, dt[, flag]) items whose scratch the library
+    takes from its static device array (numa_step_batch_noalloc); nsteps = 0
+    with no items only looks up the array on the current device."""
+    arr = _items([(it[0], it[1], None) + tuple(it[2:]) for it in items])
+    check(lib().numa_step_batch_noalloc(arr, len(items), prec, int(nsteps), _stream(stream)))
 
 
 class Graph:
