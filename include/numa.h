@@ -284,8 +284,20 @@ int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn,
  * summed in another order, and q_s enters through the weighted sum).
  * With a filter set on the mesh (numa_mesh_set_filter) every step ends with
  * numa_filter (Code example 1: the filter follows the stages).
- * The stream must not run other work on q or the workspace meanwhile. */
+ * The stream must not run other work on q or the workspace meanwhile.
+ * The time loop as a HIP graph: the launches of one step are captured once
+ * (on a stream of the mesh's own) and the graph is replayed nsteps times on
+ * the caller's stream; the capture is kept for the next call while the
+ * precision, dt, q and the mesh's settings (metric, stage mode, integrator,
+ * filter, workspace, geometry) are unchanged, and redone otherwise.  Direct
+ * launches instead while numa_profile is on, while the caller's stream is
+ * itself being captured, or after numa_mesh_set_step_graph(m, 0).  Both give
+ * bitwise the same result. */
 int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double *q, void *stream);
+
+/* numa_step's captured step on (enable != 0, the default) or off (direct
+ * launches; drops a kept capture).  Host only. */
+int32_t numa_mesh_set_step_graph(numa_mesh_t m, int32_t enable);
 
 /* The right-hand side of the time loop as numa_step's fused stage computes
  * it (Code example 1: create_rhs, then DSS and multiplication with the
@@ -297,7 +309,8 @@ int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double
  * precision; the copies summed in the same order; M^-1 of the same J w), as a
  * stage whose update is the identity on R, so no kernel folds a state into the
  * contributions.  Equals numa_dss(numa_rhs(q), NUMA_DSS_MASS | NUMA_DSS_NOFLUX)
- * up to rounding.  prec as for numa_rhs.  r may alias q.  Uses the workspace
+ * up to rounding.  prec as for numa_rhs.  r must not alias q (NUMA_EINVAL:
+ * the fused block stage finishes nodes while other workgroups still read q).  Uses the workspace
  * scratch like numa_step (calls on one mesh on different streams race). */
 int32_t numa_stage_rhs(numa_mesh_t m, int32_t prec, const double *q, double *r, void *stream);
 

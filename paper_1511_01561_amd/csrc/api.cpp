@@ -110,10 +110,21 @@ int32_t numa_mesh_create(const numa_mesh_desc *d, numa_mesh_t *out)
     return NUMA_OK;
 }
 
+static void drop_step_graph(numa_mesh_t m)
+{
+    if (m->step_exec) (void)hipGraphExecDestroy(m->step_exec);
+    if (m->step_graph) (void)hipGraphDestroy(m->step_graph);
+    m->step_exec = nullptr;
+    m->step_graph = nullptr;
+}
+
 int32_t numa_mesh_destroy(numa_mesh_t m)
 {
-    if (m)
+    if (m) {
         for (hipEvent_t e : m->ev_pool) (void)hipEventDestroy(e);
+        drop_step_graph(m);
+        if (m->cap_stream) (void)hipStreamDestroy(m->cap_stream);
+    }
     delete m;
     return NUMA_OK;
 }
@@ -170,6 +181,7 @@ int32_t numa_mesh_attach_workspace(numa_mesh_t m, void *dev_ptr, uint64_t bytes,
         return NUMA_ENOMEM;
     }
     m->ws = static_cast<char *>(dev_ptr);
+    ++m->gen;
     m->ws_bytes = bytes;
     m->prec_mask = prec_mask | 1;
     numa::layout_workspace(*m, m->prec_mask, m->ws);
@@ -190,6 +202,7 @@ int32_t numa_mesh_set_metric(numa_mesh_t m, int32_t mode)
         return NUMA_EINVAL;
     }
     m->metric_mode = mode;
+    ++m->gen;
     return NUMA_OK;
 }
 
@@ -204,6 +217,7 @@ int32_t numa_mesh_set_stage(numa_mesh_t m, int32_t mode)
         return NUMA_EINVAL;
     }
     m->stage_mode = mode;
+    ++m->gen;
     return NUMA_OK;
 }
 
@@ -229,6 +243,7 @@ int32_t numa_geometry(numa_mesh_t m, const numa_phys *ph, void *stream)
     m->gamma = ph->cp / (ph->cp - ph->R);
     int32_t rc = numa::launch_geometry(*m, as_stream(stream));
     m->geom = rc == NUMA_OK;
+    ++m->gen;
     m->imex_ok = false;  // the reference state may have changed
     return rc;
 }
@@ -332,6 +347,7 @@ int32_t numa_mesh_set_filter(numa_mesh_t m, int32_t enable, double filter_order,
     }
     if (enable && !filter_params_ok("numa_mesh_set_filter", filter_order, cutoff)) return NUMA_EINVAL;
     m->filter_on = enable != 0;
+    ++m->gen;
     m->filter_order = enable ? filter_order : 0.0;
     m->filter_cutoff = enable ? cutoff : 0;
     return NUMA_OK;
@@ -467,6 +483,66 @@ int32_t numa_mesh_set_integrator(numa_mesh_t m, int32_t integrator)
         return NUMA_EINVAL;
     }
     m->integrator = integrator;
+    ++m->gen;
+    return NUMA_OK;
+}
+
+// the launches of one step of the mesh's integrator (and its filter) on q
+static int32_t enqueue_step(numa_mesh_t m, int32_t prec, double dt, double *q, hipStream_t s)
+{
+    double *buf[3] = {q, m->dv.qs, m->dv.qs2};
+    int ns;
+    const StagePlan *plan = stage_plan(m->integrator, &ns);
+    const bool batched = numa::box_batchable(*m);
+    void *ev = m->dv.ev64;  // FP64-sized: element contributions of either precision, or an FP64 accumulator
+    int32_t rc;
+    for (int k = 0; k < ns; ++k) {
+        const StagePlan &p = plan[k];
+        const numa::StageCoef c = stage_coef(p, dt);
+        if (batched) {
+            numa::StepItem it = {m, buf[p.ref], buf[p.in], buf[p.out], ev, c};
+            rc = run_batch_stage(&it, 1, prec, s);
+        } else {
+            rc = run_stage(m, prec, c, buf[p.ref], buf[p.in], buf[p.out], s);
+        }
+        if (rc) return rc;
+    }
+    return run_filter(m, q, s);
+}
+
+// the captured step for (prec, dt, q) under the mesh's current settings,
+// recorded on the mesh's own capture stream when it is not cached
+static int32_t step_exec(numa_mesh_t m, int32_t prec, double dt, double *q, hipGraphExec_t *out)
+{
+    if (m->step_exec && m->g_prec == prec && m->g_dt == dt && m->g_q == q && m->g_gen == m->gen) {
+        *out = m->step_exec;
+        return NUMA_OK;
+    }
+    drop_step_graph(m);
+    if (!m->cap_stream) NUMA_HIP(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
+    NUMA_HIP(hipStreamBeginCapture(m->cap_stream, hipStreamCaptureModeThreadLocal));
+    int32_t rc = enqueue_step(m, prec, dt, q, m->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(m->cap_stream, &g);
+    if (rc != NUMA_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (rc == NUMA_OK) set_error("numa_step: hipStreamEndCapture failed: %s", hipGetErrorString(e));
+        return rc != NUMA_OK ? rc : NUMA_EDEVICE;
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        set_error("numa_step: hipGraphInstantiate failed: %s", hipGetErrorString(e));
+        return NUMA_EDEVICE;
+    }
+    m->step_graph = g;
+    m->step_exec = x;
+    m->g_prec = prec;
+    m->g_dt = dt;
+    m->g_q = q;
+    m->g_gen = m->gen;
+    *out = x;
     return NUMA_OK;
 }
 
@@ -479,26 +555,31 @@ int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double
         set_error("numa_step: null state or negative step count");
         return NUMA_EINVAL;
     }
+    if (nsteps == 0) return NUMA_OK;
     hipStream_t s = as_stream(stream);
-    double *buf[3] = {q, m->dv.qs, m->dv.qs2};
-    int ns;
-    const StagePlan *plan = stage_plan(m->integrator, &ns);
-    const bool batched = numa::box_batchable(*m);
-    void *ev = m->dv.ev64;  // FP64-sized: element contributions of either precision, or an FP64 accumulator
-    for (int n = 0; n < nsteps; ++n) {
-        for (int k = 0; k < ns; ++k) {
-            const StagePlan &p = plan[k];
-            const numa::StageCoef c = stage_coef(p, dt);
-            if (batched) {
-                numa::StepItem it = {m, buf[p.ref], buf[p.in], buf[p.out], ev, c};
-                rc = run_batch_stage(&it, 1, prec, s);
-            } else {
-                rc = run_stage(m, prec, c, buf[p.ref], buf[p.in], buf[p.out], s);
-            }
-            if (rc) return rc;
-        }
-        if ((rc = run_filter(m, q, s))) return rc;
+    // replay the captured step unless the caller is capturing this stream
+    // itself or the stage kernels are being timed one by one
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    NUMA_HIP(hipStreamIsCapturing(s, &cs));
+    if (m->step_graphs && !m->profiling && cs == hipStreamCaptureStatusNone) {
+        hipGraphExec_t x;
+        if ((rc = step_exec(m, prec, dt, q, &x))) return rc;
+        for (int n = 0; n < nsteps; ++n) NUMA_HIP(hipGraphLaunch(x, s));
+        return NUMA_OK;
     }
+    for (int n = 0; n < nsteps; ++n)
+        if ((rc = enqueue_step(m, prec, dt, q, s))) return rc;
+    return NUMA_OK;
+}
+
+int32_t numa_mesh_set_step_graph(numa_mesh_t m, int32_t enable)
+{
+    if (!m) {
+        set_error("numa_mesh_set_step_graph: null mesh handle");
+        return NUMA_EINVAL;
+    }
+    m->step_graphs = enable != 0;
+    if (!m->step_graphs) drop_step_graph(m);
     return NUMA_OK;
 }
 

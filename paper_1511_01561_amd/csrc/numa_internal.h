@@ -136,6 +136,18 @@ struct Mesh {
     int filter_cutoff = 0;      // modes 0..cutoff pass unchanged
     numa_phys ph{};
     double gamma = 0.0;
+    // numa_step's captured step: the launches of one step (stages, filter)
+    // recorded once on cap_stream and replayed per step; valid while the
+    // precision, dt, state and settings generation match
+    bool step_graphs = true;
+    uint64_t gen = 0;  // bumped by every call that changes what a step launches
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t step_graph = nullptr;
+    hipGraphExec_t step_exec = nullptr;
+    int32_t g_prec = -1;
+    double g_dt = 0.0;
+    const double *g_q = nullptr;
+    uint64_t g_gen = 0;
 };
 
 // Host GLL (nodes, weights, derivative matrix); returns false for bad order.

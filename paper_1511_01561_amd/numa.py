@@ -30,7 +30,7 @@ EXPORTED = ["numa_last_error", "numa_gll", "numa_mesh_create", "numa_mesh_destro
             "numa_step_batch", "numa_batch_capture", "numa_graph_launch", "numa_graph_destroy",
             "numa_mesh_set_metric", "numa_filter", "numa_filter_matrix", "numa_mesh_set_filter",
             "numa_mesh_set_integrator", "numa_imex_step", "numa_stage_rhs", "numa_mesh_set_stage",
-            "numa_step_batch_noalloc"]
+            "numa_step_batch_noalloc", "numa_mesh_set_step_graph"]
 
 
 class numa_mesh_desc(ct.Structure):
@@ -97,6 +97,7 @@ def lib():
         "numa_step_scratch_bytes": (I32, [P, I32, ct.POINTER(ct.c_uint64)]),
         "numa_step_batch": (I32, [ct.POINTER(numa_batch_item), I32, I32, I32, P]),
         "numa_step_batch_noalloc": (I32, [ct.POINTER(numa_batch_item), I32, I32, I32, P]),
+        "numa_mesh_set_step_graph": (I32, [P, I32]),
         "numa_batch_capture": (I32, [ct.POINTER(numa_batch_item), I32, I32, I32, P, ct.POINTER(P)]),
         "numa_graph_launch": (I32, [P, P]),
         "numa_graph_destroy": (I32, [P]),
@@ -289,6 +290,10 @@ class Mesh:
     def set_metric(self, mode: int):
         """METRIC_STORED or METRIC_RECOMPUTE (box meshes)."""
         check(lib().numa_mesh_set_metric(self._h, mode))
+
+    def set_step_graph(self, enable: bool):
+        """numa_step replays a captured step (default) or launches directly"""
+        check(lib().numa_mesh_set_step_graph(self._h, int(bool(enable))))
 
     def set_stage(self, mode: int):
         """STAGE_GATHER (default), STAGE_BLOCK or STAGE_COLOUR: how a fused stage sums the copies."""
