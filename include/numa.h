@@ -134,12 +134,26 @@ int32_t numa_mesh_gather_map(numa_mesh_t m, int32_t *host_out);
 /* Device workspace needed for the precisions in prec_mask (bit 0: FP64 path,
  * bit 1: mixed path) and, with bit 2 (NUMA_WS_IMEX, meshes with walls), the factors
  * of numa_imex_step's vertical line systems (8 (4N+1) n_levels n_horiz bytes).
- * The FP64 data (geometry, reference, maps, scratch) is always included. */
+ * The FP64 data (geometry, reference, maps, scratch) is always included.
+ * Bit 3 (NUMA_WS_LEAN; box meshes whose x element count fits the batched
+ * finish) asks for only what batched steps with the recomputed metric read:
+ * the reference state, M, M^-1, the recomputed metric's column factors and
+ * mass, wall normals, coordinates and the inverse map; not the gather map,
+ * the per-node metric, the first-occurrence copy lists, the contribution and
+ * stage-state scratch nor the IMEX factors (at 64x64x16, N = 4: 0.36 GB
+ * against 2.28 GB with both precisions).  On such a mesh numa_geometry forms
+ * M as the sum of the recomputed J w (the same metric, to ~1e-14), and only
+ * numa_geometry, numa_init_state, numa_export (not NUMA_FIELD_METRIC),
+ * numa_rk_stage and the batched steps (numa_step_batch, its no-allocation
+ * variant and captured graphs; recomputed metric, no filter) run on it:
+ * the others return NUMA_ENOMEM. */
 #define NUMA_WS_IMEX 4
+#define NUMA_WS_LEAN 8
 int32_t numa_mesh_workspace_bytes(numa_mesh_t m, int32_t prec_mask, uint64_t *bytes);
 
 /* Bind a caller-owned device buffer (256-byte aligned) as the workspace.
- * The buffer must outlive every call on the handle. */
+ * The buffer must outlive every call on the handle.  NUMA_EUNSUPPORTED for
+ * NUMA_WS_LEAN on a mesh the batched steps do not take. */
 int32_t numa_mesh_attach_workspace(numa_mesh_t m, void *dev_ptr, uint64_t bytes, int32_t prec_mask);
 
 /* Geometry (computed once, remark after Eq. (derivatives)): uploads the maps,

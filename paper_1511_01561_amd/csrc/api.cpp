@@ -52,6 +52,18 @@ static int32_t need_ready(numa_mesh_t m, const char *fn)
     return NUMA_OK;
 }
 
+// the entry points that read the per-node metric, the gather map or the
+// mesh's own scratch: not on a lean workspace
+static int32_t need_full(numa_mesh_t m, const char *fn)
+{
+    if (m->lean) {
+        set_error("%s: the workspace was attached lean (NUMA_WS_LEAN): only the batched steps of the recomputed "
+                  "metric run on it", fn);
+        return NUMA_ENOMEM;
+    }
+    return NUMA_OK;
+}
+
 static int32_t check_prec(numa_mesh_t m, int32_t prec, const char *fn)
 {
     if (prec != NUMA_PREC_FP64 && prec != NUMA_PREC_MIXED) {
@@ -174,6 +186,11 @@ int32_t numa_mesh_attach_workspace(numa_mesh_t m, void *dev_ptr, uint64_t bytes,
         set_error("numa_mesh_attach_workspace: workspace must be 256-byte aligned");
         return NUMA_EINVAL;
     }
+    if ((prec_mask & NUMA_WS_LEAN) && !numa::box_batchable(*m)) {
+        set_error("numa_mesh_attach_workspace: NUMA_WS_LEAN needs a box mesh whose x element count fits the "
+                  "batched finish");
+        return NUMA_EUNSUPPORTED;
+    }
     uint64_t need = numa::layout_workspace(*m, prec_mask, nullptr);
     if (bytes < need) {
         set_error("numa_mesh_attach_workspace: %llu bytes given, %llu needed", (unsigned long long)bytes,
@@ -286,6 +303,7 @@ int32_t numa_rhs(numa_mesh_t m, int32_t prec, const double *q, double *c_elem, v
 {
     int32_t rc = need_ready(m, "numa_rhs");
     if (rc) return rc;
+    if ((rc = need_full(m, "numa_rhs"))) return rc;
     if ((rc = check_prec(m, prec, "numa_rhs"))) return rc;
     if (!q || !c_elem) {
         set_error("numa_rhs: null argument");
@@ -298,6 +316,7 @@ int32_t numa_dss(numa_mesh_t m, int32_t nvar, const double *c_elem, double *out,
 {
     int32_t rc = need_ready(m, "numa_dss");
     if (rc) return rc;
+    if ((rc = need_full(m, "numa_dss"))) return rc;
     if (!c_elem || !out || nvar < 1) {
         set_error("numa_dss: null argument or nvar < 1");
         return NUMA_EINVAL;
@@ -357,6 +376,7 @@ int32_t numa_filter(numa_mesh_t m, double filter_order, int32_t cutoff, double *
 {
     int32_t rc = need_ready(m, "numa_filter");
     if (rc) return rc;
+    if ((rc = need_full(m, "numa_filter"))) return rc;
     if (!q) {
         set_error("numa_filter: null state");
         return NUMA_EINVAL;
@@ -550,6 +570,7 @@ int32_t numa_step(numa_mesh_t m, int32_t prec, double dt, int32_t nsteps, double
 {
     int32_t rc = need_ready(m, "numa_step");
     if (rc) return rc;
+    if ((rc = need_full(m, "numa_step"))) return rc;
     if ((rc = check_prec(m, prec, "numa_step"))) return rc;
     if (!q || nsteps < 0) {
         set_error("numa_step: null state or negative step count");
@@ -587,6 +608,7 @@ int32_t numa_stage_rhs(numa_mesh_t m, int32_t prec, const double *q, double *r, 
 {
     int32_t rc = need_ready(m, "numa_stage_rhs");
     if (rc) return rc;
+    if ((rc = need_full(m, "numa_stage_rhs"))) return rc;
     if ((rc = check_prec(m, prec, "numa_stage_rhs"))) return rc;
     if (!q || !r) {
         set_error("numa_stage_rhs: null argument");
@@ -614,6 +636,7 @@ int32_t numa_imex_step(numa_mesh_t m, int32_t prec, double dt, double ra, int32_
 {
     int32_t rc = need_ready(m, "numa_imex_step");
     if (rc) return rc;
+    if ((rc = need_full(m, "numa_imex_step"))) return rc;
     if ((rc = check_prec(m, prec, "numa_imex_step"))) return rc;
     if (!qprev || !qcur || qprev == qcur || nsteps < 0) {
         set_error("numa_imex_step: null or identical states, or negative step count");
@@ -711,6 +734,15 @@ int32_t numa::check_batch(const numa_batch_item *items, int32_t n, int32_t prec,
         if (m->metric_mode != items[0].mesh->metric_mode) {
             set_error("%s: item %d uses another metric mode than item 0 (one mode per batch)", fn, k);
             return NUMA_EINVAL;
+        }
+        if (m->lean && m->metric_mode != NUMA_METRIC_RECOMPUTE) {
+            set_error("%s: item %d: a lean workspace (NUMA_WS_LEAN) holds no stored metric: set "
+                      "NUMA_METRIC_RECOMPUTE", fn, k);
+            return NUMA_EINVAL;
+        }
+        if (m->lean && m->filter_on) {
+            set_error("%s: item %d: the filter needs the contribution scratch a lean workspace does not hold", fn, k);
+            return NUMA_ENOMEM;
         }
         if (m->integrator != items[0].mesh->integrator) {
             set_error("%s: item %d uses another integrator than item 0 (one integrator per batch)", fn, k);

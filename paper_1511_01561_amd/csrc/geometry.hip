@@ -253,6 +253,16 @@ __global__ void k_mass_recomputed(GeoParams g, const int32_t *off, const int32_t
     MinvR[I] = 1.0 / s;
 }
 
+// lean workspace: M and M^-1 from the recomputed J w (the stored metric is
+// not kept)
+__global__ void k_mass_from_recomputed(GeoParams g, const double *MinvR, double *M, double *Minv)
+{
+    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= g.nu) return;
+    M[I] = 1.0 / MinvR[I];
+    Minv[I] = MinvR[I];
+}
+
 __global__ void k_unique_coords(GeoParams g, const int32_t *hlat, double *xu)
 {
     int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -416,7 +426,7 @@ __device__ inline double box_terrain(const GeoParams &g, int64_t ci, int64_t cj)
     return g.h0 * sin(2.0 * kPi * xx / g.L0) * sin(2.0 * kPi * yy / g.L1);
 }
 
-__global__ void k_box_columns(GeoParams g, double *hcol)
+__global__ void k_box_columns(GeoParams g, double *hcol, int *bad)
 {
     const int PP = g.P * g.P;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -433,6 +443,7 @@ __global__ void k_box_columns(GeoParams g, double *hcol)
     const double h = box_terrain(g, ci + i, cj + j);
     const double xa = g.L0 / (2.0 * g.nex), yb = g.L1 / (2.0 * g.ney);
     const double zc = (1.0 - h / g.L2) * (g.L2 / (2.0 * g.nez));
+    if (!(zc > 0.0)) *bad = 1;  // the terrain reaches the top: no positive Jacobian
     double *o = hcol + col * 4 * PP + l;
     o[0] = xa * yb * zc * (g.w[i] * g.w[j]);
     o[PP] = 1.0 / zc;
@@ -512,7 +523,7 @@ int32_t launch_geometry(Mesh &m, hipStream_t s)
     GeoParams g = params(m);
     DeviceView &v = m.dv;
     if (!m.uploaded) {
-        NUMA_HIP(hipMemcpyAsync(v.G, m.G.data(), 4 * m.nl, hipMemcpyHostToDevice, s));
+        if (v.G) NUMA_HIP(hipMemcpyAsync(v.G, m.G.data(), 4 * m.nl, hipMemcpyHostToDevice, s));
         NUMA_HIP(hipMemcpyAsync(v.off, m.off.data(), 4 * (m.nu + 1), hipMemcpyHostToDevice, s));
         NUMA_HIP(hipMemcpyAsync(v.idx, m.idx.data(), 4 * m.nl, hipMemcpyHostToDevice, s));
         if (v.hlat) NUMA_HIP(hipMemcpyAsync(v.hlat, m.hlat.data(), 12 * m.nh, hipMemcpyHostToDevice, s));
@@ -520,9 +531,11 @@ int32_t launch_geometry(Mesh &m, hipStream_t s)
             NUMA_HIP(hipMemcpyAsync(v.hoff, m.hoff.data(), 4 * m.hoff.size(), hipMemcpyHostToDevice, s));
             NUMA_HIP(hipMemcpyAsync(v.hidx, m.hidx.data(), 4 * m.hidx.size(), hipMemcpyHostToDevice, s));
         }
-        NUMA_HIP(hipMemcpyAsync(v.own, m.own.data(), 4 * m.nu, hipMemcpyHostToDevice, s));
-        NUMA_HIP(hipMemcpyAsync(v.toff, m.toff.data(), 4 * (m.nu + 1), hipMemcpyHostToDevice, s));
-        NUMA_HIP(hipMemcpyAsync(v.tidx, m.tidx.data(), 4 * m.nl, hipMemcpyHostToDevice, s));
+        if (v.own) {
+            NUMA_HIP(hipMemcpyAsync(v.own, m.own.data(), 4 * m.nu, hipMemcpyHostToDevice, s));
+            NUMA_HIP(hipMemcpyAsync(v.toff, m.toff.data(), 4 * (m.nu + 1), hipMemcpyHostToDevice, s));
+            NUMA_HIP(hipMemcpyAsync(v.tidx, m.tidx.data(), 4 * m.nl, hipMemcpyHostToDevice, s));
+        }
         m.D32.assign(m.D, m.D + m.P * m.P);
         NUMA_HIP(hipMemcpyAsync(v.D64, m.D, 8 * m.P * m.P, hipMemcpyHostToDevice, s));
         NUMA_HIP(hipMemcpyAsync(v.D32, m.D32.data(), 4 * m.P * m.P, hipMemcpyHostToDevice, s));
@@ -533,19 +546,21 @@ int32_t launch_geometry(Mesh &m, hipStream_t s)
         m.uploaded = true;
     }
     const int bs = 256;
-    int *bad = (int *)v.qs;  // a flag in the stage-state scratch
+    int *bad = v.flag;
     NUMA_HIP(hipMemsetAsync(bad, 0, sizeof(int), s));
-    int mt = ((m.np + 63) / 64) * 64;
-    if (mt > 256) mt = 256;
-    hipLaunchKernelGGL(k_metric, dim3((unsigned)m.ne), dim3(mt), 4 * m.np * sizeof(double), s, g, v.met, v.met32,
-                       bad);
-    hipLaunchKernelGGL(k_mass, dim3(nblocks(m.nu, bs)), dim3(bs), 0, s, g, v.off, v.idx, v.met, v.M, v.Minv);
+    if (v.met) {  // not in a lean workspace: the mass then comes from the recomputed J w below
+        int mt = ((m.np + 63) / 64) * 64;
+        if (mt > 256) mt = 256;
+        hipLaunchKernelGGL(k_metric, dim3((unsigned)m.ne), dim3(mt), 4 * m.np * sizeof(double), s, g, v.met,
+                           v.met32, bad);
+        hipLaunchKernelGGL(k_mass, dim3(nblocks(m.nu, bs)), dim3(bs), 0, s, g, v.off, v.idx, v.met, v.M, v.Minv);
+    }
     hipLaunchKernelGGL(k_unique_coords, dim3(nblocks(m.nu, bs)), dim3(bs), 0, s, g, v.hlat, v.xu);
     hipLaunchKernelGGL(k_reference, dim3(nblocks(m.nu, bs)), dim3(bs), 0, s, g, m.ph, v.hlat, v.xu, v.ref, v.grav);
     hipLaunchKernelGGL(k_normals, dim3(nblocks(m.nh, bs)), dim3(bs), 0, s, g, v.hlat, v.xu, v.nrm);
     if (v.hcol)
         hipLaunchKernelGGL(k_box_columns, dim3(nblocks((int64_t)g.nex * g.ney * m.P * m.P, bs)), dim3(bs), 0, s, g,
-                           v.hcol);
+                           v.hcol, bad);
     if (v.scol) {
         hipLaunchKernelGGL(k_shell_columns, dim3(nblocks(6 * (int64_t)g.nex * g.nex * m.P * m.P, bs)), dim3(bs), 0, s,
                            g, v.G, v.scol, v.shid);
@@ -554,6 +569,8 @@ int32_t launch_geometry(Mesh &m, hipStream_t s)
     }
     hipLaunchKernelGGL(k_mass_recomputed, dim3(nblocks(m.nu, bs)), dim3(bs), 0, s, g, v.off, v.idx, v.hcol, v.scol,
                        v.slay, v.MinvR);
+    if (!v.met)
+        hipLaunchKernelGGL(k_mass_from_recomputed, dim3(nblocks(m.nu, bs)), dim3(bs), 0, s, g, v.MinvR, v.M, v.Minv);
     NUMA_HIP(hipGetLastError());
     int hbad = 0;
     NUMA_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -581,6 +598,10 @@ int32_t launch_export(Mesh &m, int32_t what, void *out, hipStream_t s)
         NUMA_HIP(hipMemcpyAsync(out, v.xu, 24 * m.nu, hipMemcpyDeviceToDevice, s));
         break;
     case NUMA_FIELD_METRIC:
+        if (!v.met) {
+            set_error("export: the per-node metric is not kept in a lean workspace (NUMA_WS_LEAN)");
+            return NUMA_ENOMEM;
+        }
         hipLaunchKernelGGL(k_export_metric, dim3(nblocks(m.nl, bs)), dim3(bs), 0, s, g, v.met, (double *)out);
         break;
     case NUMA_FIELD_GRAVITY:

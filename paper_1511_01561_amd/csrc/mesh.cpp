@@ -278,13 +278,18 @@ uint64_t layout_workspace(Mesh &m, int32_t prec_mask, char *base)
         o = align256(o + bytes);
         return base ? base + at : nullptr;
     };
+    // lean: what the batched stages of the recomputed box metric read, and
+    // the inverse map the geometry sums the recomputed mass over
+    const bool lean = (prec_mask & NUMA_WS_LEAN) && m.d.kind == NUMA_MESH_BOX;
     DeviceView v;
-    v.G = (int32_t *)take(4ull * m.nl);
+    if (!lean) v.G = (int32_t *)take(4ull * m.nl);
     v.off = (int32_t *)take(4ull * (m.nu + 1));
     v.idx = (int32_t *)take(4ull * m.nl);
     if (m.d.kind == NUMA_MESH_SHELL) v.hlat = (int32_t *)take(12ull * m.nh);
-    v.met = (double *)take(80ull * m.nl);
-    if (prec_mask & 2) v.met32 = (float *)take(40ull * m.nl);
+    if (!lean) {
+        v.met = (double *)take(80ull * m.nl);
+        if (prec_mask & 2) v.met32 = (float *)take(40ull * m.nl);
+    }
     v.ref = (double *)take(24ull * m.nu);
     v.M = (double *)take(8ull * m.nu);
     v.Minv = (double *)take(8ull * m.nu);
@@ -301,19 +306,25 @@ uint64_t layout_workspace(Mesh &m, int32_t prec_mask, char *base)
         v.hoff = (int32_t *)take(4ull * (m.nh + 1));
         v.hidx = (int32_t *)take(4ull * ncol);
     }
-    v.own = (int32_t *)take(4ull * m.nu);
-    v.toff = (int32_t *)take(4ull * (m.nu + 1));
-    v.tidx = (int32_t *)take(4ull * m.nl);
-    v.ev64 = (double *)take(40ull * m.nl);
-    if (prec_mask & 2) v.ev32 = (float *)take(20ull * m.nl);
-    v.qs = (double *)take(40ull * m.nu);
-    v.qs2 = (double *)take(40ull * m.nu);
-    if ((prec_mask & 4) && m.walls) v.imexLU = (double *)take(imex_factor_bytes(m));
+    if (!lean) {
+        v.own = (int32_t *)take(4ull * m.nu);
+        v.toff = (int32_t *)take(4ull * (m.nu + 1));
+        v.tidx = (int32_t *)take(4ull * m.nl);
+        v.ev64 = (double *)take(40ull * m.nl);
+        if (prec_mask & 2) v.ev32 = (float *)take(20ull * m.nl);
+        v.qs = (double *)take(40ull * m.nu);
+        v.qs2 = (double *)take(40ull * m.nu);
+        if ((prec_mask & 4) && m.walls) v.imexLU = (double *)take(imex_factor_bytes(m));
+    }
     v.D64 = (double *)take(8ull * kMaxP * kMaxP);
     v.D32 = (float *)take(4ull * kMaxP * kMaxP);
     v.xi64 = (double *)take(8ull * kMaxP);
     v.w64 = (double *)take(8ull * kMaxP);
-    if (base) m.dv = v;
+    v.flag = (int32_t *)take(4);
+    if (base) {
+        m.dv = v;
+        m.lean = lean;
+    }
     return o;
 }
 

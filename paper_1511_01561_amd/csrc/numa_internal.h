@@ -102,6 +102,7 @@ struct DeviceView {
     double *xi64 = nullptr;    // [N+1] GLL nodes
     double *w64 = nullptr;     // [N+1] GLL weights
     float *D32 = nullptr;      // same, FP32
+    int32_t *flag = nullptr;   // one int: the geometry's non-positive-Jacobian flag
 };
 
 struct Mesh {
@@ -124,6 +125,7 @@ struct Mesh {
     char *ws = nullptr;
     uint64_t ws_bytes = 0;
     int32_t prec_mask = 0;
+    bool lean = false;  // NUMA_WS_LEAN: only what batched recomputed-metric steps read
     DeviceView dv;
     bool uploaded = false, geom = false;
     int metric_mode = 0;  // NUMA_METRIC_STORED or NUMA_METRIC_RECOMPUTE (box)

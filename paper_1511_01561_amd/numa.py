@@ -21,6 +21,7 @@ METRIC_STORED, METRIC_RECOMPUTE = 0, 1
 RK_SSP33, RK_SSP53 = 0, 1
 STAGE_GATHER, STAGE_BLOCK, STAGE_COLOUR = 0, 1, 2
 WS_IMEX = 4
+WS_LEAN = 8
 FIELD_MASS, FIELD_REF, FIELD_COORDS, FIELD_METRIC, FIELD_GRAVITY, FIELD_LOCAL_COORDS = range(6)
 
 EXPORTED = ["numa_last_error", "numa_gll", "numa_mesh_create", "numa_mesh_destroy", "numa_mesh_info",

@@ -103,14 +103,21 @@ class GpuExecutor:
         self._turn = 0
         self._free = list(range(max_slots - 1, -1, -1))
 
-    def _prec_mask(self):
-        return 1 | (2 if self.prec else 0)
+    def _prec_mask(self, req: Request):
+        """the workspace a request's geometry needs: lean (no per-node metric,
+        gather map or mesh scratch) for boxes stepped with the recomputed
+        metric and no filter, which only the batched steps touch"""
+        m = 1 | (2 if self.prec else 0)
+        if (req.workload["mesh"]["kind"] == self.numa.MESH_BOX and self.metric == self.numa.METRIC_RECOMPUTE
+                and req.filter is None):
+            m |= self.numa.WS_LEAN
+        return m
 
     def sizes(self, req: Request):
         """(geometry workspace bytes, request bytes) of a request, on the host."""
         z = self._sizes.get(req.key)
         if z is None:
-            ws, nu, scr = self.numa.mesh_sizes(req.workload["mesh"], self._prec_mask(), self.prec)
+            ws, nu, scr = self.numa.mesh_sizes(req.workload["mesh"], self._prec_mask(req), self.prec)
             z = (ws + 256, 40 * nu + 256 + scr + 256)
             self._sizes[req.key] = z
         return z
@@ -122,7 +129,7 @@ class GpuExecutor:
         g = self._geoms.get(req.key)
         if g is None:
             with self.torch.cuda.stream(self.stream):
-                g = self.numa.Mesh(req.workload["mesh"], req.workload["phys"], prec_mask=self._prec_mask(),
+                g = self.numa.Mesh(req.workload["mesh"], req.workload["phys"], prec_mask=self._prec_mask(req),
                                    device=self.device, stream=self.stream)
                 if req.workload["mesh"]["kind"] == self.numa.MESH_BOX:
                     g.set_metric(self.metric)

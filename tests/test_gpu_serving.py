@@ -29,6 +29,22 @@ def box(n, N, seed=0, nz=None):
                                bubble_amp=rng.uniform(0.1, 2.0))
 
 
+def alone(torch, ex, r, prec=0):
+    """a served request run alone through numa_step on a mesh of its own with
+    the full workspace (the server's geometries are lean: batched steps only)"""
+    from paper_1511_01561_amd import numa
+    wl = r.workload
+    g = numa.Mesh(wl["mesh"], wl["phys"], prec_mask=3)
+    g.set_metric(ex.metric)
+    g.set_integrator(r.integrator)
+    if r.filter is not None:
+        g.set_filter(*r.filter)
+    q = g.init_state(wl["ic"], inputs.device_noise(g.n_unique, r.noise_seed))
+    g.step(q, 0.05, r.steps, prec=prec)
+    torch.cuda.synchronize()
+    return q
+
+
 def make(torch, wl, prec, seed):
     from paper_1511_01561_amd import numa
     g = numa.Mesh(wl["mesh"], wl["phys"], prec_mask=3)
@@ -147,11 +163,7 @@ def test_serving_results_same_alone_and_in_the_mix(torch_cuda, prec):
     assert st.max_active >= 2
     torch.cuda.synchronize()
     for r in reqs:
-        g = ex.geometry(r)
-        q = g.init_state(r.workload["ic"], inputs.device_noise(g.n_unique, r.noise_seed))
-        g.step(q, 0.05, r.steps, prec=prec)
-        torch.cuda.synchronize()
-        assert torch.equal(q, r.state), r.id
+        assert torch.equal(alone(torch, ex, r, prec), r.state), r.id
     ex.drop_graphs()
 
 
@@ -172,11 +184,7 @@ def test_serving_mixed_integrators_and_filters(torch_cuda):
     st = srv.run(reqs, realtime=False)
     assert len(st.latencies) == len(reqs)
     for r in reqs:
-        g = ex.geometry(r)
-        q = g.init_state(r.workload["ic"], inputs.device_noise(g.n_unique, r.noise_seed))
-        g.step(q, 0.05, r.steps)
-        torch.cuda.synchronize()
-        assert torch.equal(q, r.state), r.id
+        assert torch.equal(alone(torch, ex, r), r.state), r.id
     ex.drop_graphs()
 
 
@@ -204,11 +212,7 @@ def test_nonfinite_request_retires_alone(torch_cuda, prec):
     for r in reqs:
         if r.failed:
             continue
-        g = ex.geometry(r)
-        q = g.init_state(r.workload["ic"], inputs.device_noise(g.n_unique, r.noise_seed))
-        g.step(q, 0.05, r.steps, prec=prec)
-        torch.cuda.synchronize()
-        assert torch.equal(q, r.state), r.id
+        assert torch.equal(alone(torch, ex, r, prec), r.state), r.id
     ex.drop_graphs()
 
 
@@ -234,9 +238,5 @@ def test_admission_counts_geometry_and_evicts_idle_geometry(torch_cuda):
     assert len(st.latencies) == 4 and st.peak_bytes <= budget and st.max_active == 1
     assert len(srv.geoms) == 1
     for r in reqs:
-        g = ex.geometry(r)
-        q = g.init_state(r.workload["ic"], inputs.device_noise(g.n_unique, r.noise_seed))
-        g.step(q, 0.05, r.steps)
-        torch.cuda.synchronize()
-        assert torch.equal(q, r.state), r.id
+        assert torch.equal(alone(torch, ex, r), r.state), r.id
     ex.drop_graphs()

@@ -265,3 +265,40 @@ def test_imex_step_refused_before_setup(L):
         assert nb4.value > nb.value          # the line factors
     finally:
         L.numa_mesh_destroy(h)
+
+
+def test_lean_workspace_holds_only_what_batched_steps_read(L):
+    """NUMA_WS_LEAN: the inverse map, reference, M, M^-1, the recomputed
+    mass, wall normals, coordinates, column factors and the GLL tables, each
+    256-byte aligned; refused on meshes the batched steps do not take."""
+    def a256(x):
+        return (x + 255) // 256 * 256
+
+    wl = inputs.box_workload(8, 4, 3, 4, 5e4, 2.5e4, 6e3, terrain=300.0)
+    rc, h = _create(wl["mesh"])
+    assert rc == 0
+    try:
+        ne, nl, nu, nh, nk = (ct.c_int64() for _ in range(5))
+        assert L.numa_mesh_info(h, ct.byref(ne), ct.byref(nl), ct.byref(nu), ct.byref(nh), ct.byref(nk)) == 0
+        nl, nu, nh, P, kp = nl.value, nu.value, nh.value, 5, 9
+        want = (a256(4 * (nu + 1)) + a256(4 * nl) + a256(24 * nu) + 3 * a256(8 * nu) + a256(48 * nh)
+                + a256(24 * nu) + a256(32 * 8 * 4 * P * P) + a256(8 * kp * kp) + a256(4 * kp * kp)
+                + 2 * a256(8 * kp) + a256(4))
+        lean, full = ct.c_uint64(), ct.c_uint64()
+        assert L.numa_mesh_workspace_bytes(h, 3 | numa.WS_LEAN, ct.byref(lean)) == 0
+        assert L.numa_mesh_workspace_bytes(h, 3, ct.byref(full)) == 0
+        assert lean.value == want and full.value > 4 * lean.value
+        # binding a lean workspace is host-only; the device calls then still need the geometry
+        assert L.numa_mesh_attach_workspace(h, ct.c_void_p(256), lean.value, 3 | numa.WS_LEAN) == 0
+    finally:
+        L.numa_mesh_destroy(h)
+    for mesh in (inputs.shell_workload(ne=3, nz=2, N=4, seed=0)["mesh"],             # shell
+                 inputs.box_workload(6, 4, 3, 4, 5e4, 2.5e4, 6e3)["mesh"]):           # nx not a multiple of 4
+        rc, h = _create(mesh)
+        assert rc == 0
+        try:
+            nb = ct.c_uint64()
+            assert L.numa_mesh_workspace_bytes(h, 1 | numa.WS_LEAN, ct.byref(nb)) == 0
+            assert L.numa_mesh_attach_workspace(h, ct.c_void_p(256), nb.value, 1 | numa.WS_LEAN) == -4
+        finally:
+            L.numa_mesh_destroy(h)
