@@ -139,3 +139,31 @@ def test_stage_rhs_full_size_mixed_error_report(torch_cuda, oracle_mod):
     e = group_err(p.host(qm) - q0, qo - q0)
     print("full mixed 1-step increment", {k: "%.2e" % v for k, v in e.items()}, flush=True)
     assert max(e.values()) <= TOLMIX
+
+
+@pytest.mark.parametrize("nx,perz", [(16, False), (8, True), (32, False)])
+def test_stage_rhs_wide_finish_segments_n3(torch_cuda, oracle_mod, nx, perz):
+    """N = 3 takes the widest finish segment (16, 8 or 4 elements along x)
+    that divides nx: each against the oracle, and the same right-hand side
+    bit for bit when a batch with a narrower mesh forces 4-element segments."""
+    from paper_1511_01561_amd import numa
+    import torch
+    wl = inputs.box_workload(nx, 2, 2, 3, nx * 3e3, 6e3, 4e3, terrain=300.0, bubble_centre=(nx * 1.5e3, 3e3, 2e3),
+                             bubble_radius=2.5e3, periodic_z=perz)
+    p = Pair(wl, oracle_mod)
+    q = inputs.random_state(p.nu, seed=40 + nx)
+    for metric in (numa.METRIC_RECOMPUTE, numa.METRIC_STORED):
+        _check(p, q, metric, "N=3 nx=%d" % nx)
+    # one step alone (wide segment) against the same step batched with a 4-wide mesh
+    p.g.set_metric(numa.METRIC_RECOMPUTE)
+    other = numa.Mesh(_box(3)["mesh"], _box(3)["phys"], prec_mask=3)
+    other.set_metric(numa.METRIC_RECOMPUTE)
+    for prec in (numa.PREC_FP64, numa.PREC_MIXED):
+        qa = p.g.init_state(wl["ic"], None)
+        qb = qa.clone()
+        qo = other.init_state(_box(3)["ic"], None)
+        p.g.step(qa, 0.05, 2, prec=prec)
+        numa.step_batch([(p.g, qb, numa.alloc_scratch(p.g, prec), 0.05),
+                         (other, qo, numa.alloc_scratch(other, prec), 0.05)], 2, prec)
+        torch.cuda.synchronize()
+        assert torch.equal(qa, qb), prec
