@@ -132,9 +132,13 @@ __global__ __launch_bounds__(block_threads<N>()) void k_elem_batch(Batch B)
     __syncthreads();
     const bool act = l < NP;
     if (act) {
-        T Di[N + 1], Dj[N + 1], Dk[N + 1];
-        d_rows<N, T>(a.D, l, Di, Dj, Dk);
-        node_derive<N, T, false, GEO>(a, l, in, Di, Dj, Dk, s, o);
+        if constexpr (GEO == kMetricBox) {  // FP64 at N = 7, 8: R direction by direction
+            node_derive_box_dirs<N, T>(a, l, in, s, o);
+        } else {
+            T Di[N + 1], Dj[N + 1], Dk[N + 1];
+            d_rows<N, T>(a.D, l, Di, Dj, Dk);
+            node_derive<N, T, false, GEO>(a, l, in, Di, Dj, Dk, s, o);
+        }
     }
     __syncthreads();  // every lane has finished reading the tile
     T *st = &s[0][0];

@@ -347,6 +347,72 @@ __device__ __forceinline__ void node_derive(const RhsArgs<T> &a, int l, const No
     node_combine<T, SHELL, GEO>(a, dd, mx, in.u, in.v, in.w, in.rp, in.rb, gv, o);
 }
 
+// node_derive for the box's recomputed metric with R accumulated direction
+// by direction: every term of R is linear in the reference derivatives, so
+// the xi terms of all fields are added first (row i of D), then the eta
+// terms (row j), then the zeta terms (row k).  One row of D and five sums
+// are live instead of three rows and 24 derivatives (the one-node-per-lane
+// kernel at 64x64x16: N = 7 1197 -> 1040 us, N = 8 2491 -> 2467 us; no gain
+// on the shell's or the stored metric's kernels, which keep node_derive).
+// The same terms as node_combine (GEO == kMetricBox), summed in another
+// order.
+template <int N, typename T>
+__device__ __forceinline__ void node_derive_box_dirs(const RhsArgs<T> &a, int l, const NodeIn<T> &in,
+                                                     T (*s)[(N + 1) * (N + 1) * (N + 1)], NodeOut<T> &o)
+{
+    constexpr int P = N + 1, PP = P * P;
+    const int i = l % P, j = (l / P) % P, k = l / PP;
+    T mx[10];
+    box_node_metric<T>(a.bm, in.ez, in.zk, in.c0, in.c1, in.c2, in.c3, mx);
+    const T uu = (T)in.u, vv = (T)in.v, ww = (T)in.w;
+    const T Uc0 = uu * mx[0], Uc1 = vv * mx[4], Uc2 = uu * mx[6] + vv * mx[7] + ww * mx[8];
+    const double irho64 = 1.0 / (in.rb + in.rp);
+    const T irho = (T)irho64;
+    // A: the sums whose negatives are R (tile fields: 0 rho u, 1 rho v,
+    // 2 rho w, 3 u, 4 v, 5 w, 6 theta', 7 p')
+    T A[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int r = d == 0 ? i : (d == 1 ? j : k);
+        T Dr[P];
+#pragma unroll
+        for (int m = 0; m < P; ++m) Dr[m] = a.D[r * P + m];
+        auto dfd = [&](int f) -> T {
+            T acc = 0;
+#pragma unroll
+            for (int m = 0; m < P; ++m) {
+                const int at = d == 0 ? m + P * (j + P * k) : (d == 1 ? i + P * (m + P * k) : i + P * (j + P * m));
+                acc += Dr[m] * s[f][at];
+            }
+            return acc;
+        };
+        const T U = d == 0 ? Uc0 : (d == 1 ? Uc1 : Uc2);
+        // continuity: d(rho u)/dx = rho u_xi xi_x + rho u_zeta zeta_x, and so on
+        if (d == 0) A[0] += dfd(0) * mx[0];
+        if (d == 1) A[0] += dfd(1) * mx[4];
+        if (d == 2) A[0] += dfd(0) * mx[6] + dfd(1) * mx[7] + dfd(2) * mx[8];
+        // advection of u, v, w, theta'
+#pragma unroll
+        for (int f = 3; f < 7; ++f) A[f - 2] += U * dfd(f);
+        // pressure gradient over rho
+        const T dp = dfd(7);
+        if (d == 0) A[1] += irho * (dp * mx[0]);
+        if (d == 1) A[2] += irho * (dp * mx[4]);
+        if (d == 2) {
+            A[1] += irho * (dp * mx[6]);
+            A[2] += irho * (dp * mx[7]);
+            A[3] += irho * (dp * mx[8]);
+        }
+    }
+    const T buoy = (T)(in.rp * irho64);
+    o.R[0] = -A[0];
+    o.R[1] = -A[1];
+    o.R[2] = -A[2];
+    o.R[3] = -A[3] + buoy * (T)(-a.g0);
+    o.R[4] = -A[4];
+    o.Jw = mx[9];
+}
+
 // Gathers the element tile, differentiates it and evaluates R at node l of
 // element e.  Must be called by all lanes of the block (it synchronises);
 // returns false for the padding lanes (l >= (N+1)^3).
