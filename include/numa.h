@@ -56,6 +56,7 @@ extern "C" {
 #define NUMA_STAGE_GATHER 0  /* element kernel writes J w R per copy; a finish kernel gathers the copies */
 #define NUMA_STAGE_BLOCK 1   /* one kernel per block of element columns sums the copies in LDS */
 #define NUMA_STAGE_COLOUR 2  /* 8 colour passes add J w R into a unique-node accumulator */
+#define NUMA_STAGE_SPLIT 3   /* element kernel finishes its run's interior nodes; a face kernel the rest */
 
 #define NUMA_RK_SSP33 0      /* three-stage third-order SSP Runge-Kutta (Shu-Osher) */
 #define NUMA_RK_SSP53 1      /* five-stage third-order SSP Runge-Kutta (Spiteri-Ruuth) */
@@ -214,6 +215,15 @@ int32_t numa_mesh_set_metric(numa_mesh_t m, int32_t mode);
  *   and the update (the paper's scheme of re-ordering elements so that
  *   concurrent threads never update the same node, Sec. "OpenMP").  N <= 4,
  *   nx, ny, nz even.
+ * NUMA_STAGE_SPLIT: the element kernel's workgroup holds a run of
+ *   consecutive elements along x; it adds the copies of the x faces shared
+ *   inside the run in LDS and finishes every node whose copies it then holds
+ *   (local j and k interior to the element, away from the x face that starts
+ *   the run): M^-1, update, state.  The contributions of the other nodes
+ *   (the element faces in y and z, and the run-start faces) go to the
+ *   workspace scratch in rows along x, and a second kernel gathers them and
+ *   finishes those nodes.  N <= 4; the stage may write its input state (the
+ *   nodes the element kernel finishes are read by no other workgroup).
  * Meshes or stages a mode does not cover run NUMA_STAGE_GATHER.  NUMA_EINVAL
  * for an unknown mode.  Host only. */
 int32_t numa_mesh_set_stage(numa_mesh_t m, int32_t mode);

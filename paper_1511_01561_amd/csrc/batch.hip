@@ -30,8 +30,10 @@ struct BatchItem {
     int ni, nj, nkw;      // lattice extents; nkw: extent in z when periodic, else -1
     int nz, walls;
     int ne;               // elements
-    int mblk;             // finish blocks of the main layers: (nx/SEG) ny nz
-    FastDiv fx, fy, fseg;  // division by nx, ny and nx/SEG (colour passes: fseg by nx/2, fy by ny/2)
+    int mblk;             // finish blocks of the main layers: (nx/SEG) ny nz (split: of the face rows)
+    FastDiv fx, fy, fseg;  // division by nx, ny and nx/SEG (colour passes: fseg by nx/2, fy by ny/2;
+                           // split: fseg by ni)
+    FastDiv frl;           // split: division by the face rows per element layer, nj + (N - 1) ny
     double cdt;            // (beta / b) dt of the stage update
     double theta0;         // the box reference is isentropic: theta_bar = theta0 everywhere
     BoxMetric bm;          // constants of the recomputed metric
@@ -181,16 +183,69 @@ template <int N, typename T>
 constexpr int col_threads() { return ((col_eb<N, T>() * (N + 1) * (N + 1) + 63) / 64) * 64; }
 // workgroups per CU the column kernel is compiled for: in FP32 at N = 4 the
 // tile (40 KB) lets four share a CU if the registers fit 4 waves per SIMD
-template <int N, typename T>
-constexpr int col_blocks() { return (sizeof(T) == 4 && N == 4) ? 4 : 1; }
+template <int N, typename T, int MODE = 0>
+constexpr int col_blocks() { return (sizeof(T) == 4 && N == 4) ? (MODE == 2 ? 3 : 4) : 1; }
+
+// NUMA_STAGE_SPLIT: the DSS split between the element kernel and a finish
+// kernel over the element faces.  The EB elements of a column workgroup are
+// consecutive in the element order, so element q's west face (i = 0) and
+// element q - 1's east face (i = N) are the same nodes whenever both lie in
+// the workgroup and in one row (ex != 0): the workgroup adds those pairs in
+// LDS.  A node whose (j, k) is interior to the element (0 < j, k < N) then has
+// all its copies in the workgroup unless it sits on the x face that starts
+// the run (q = 0 or ex = 0), and the element kernel finishes it itself: M^-1,
+// the stage update and the state write (these nodes are never on a wall).
+// What remains are the face nodes (gj or gk a multiple of N: 4N of the
+// (N+1)^2 (j, k) pairs of an element, "face pairs") and the run-start nodes
+// of the interior pairs.  Their contributions are written in two arrays:
+//  * Fa [nz][ny][4N][ni][5] (of T): per element row (ey, ez), face pair fp and
+//    lattice position gi = ex N + i (i < N) the five values of the
+//    contribution of element ex at local i (at i = 0 the pair sum when the run
+//    holds element ex - 1), so the finish reads each face row of the lattice
+//    as one contiguous run per copy;
+//  * Fb [ne][4N + 2 (N-1)^2][5]: the copies that stay unpaired at run
+//    boundaries: slots 0..4N-1 the face pairs at i = N, 4N + ip the interior
+//    pair ip at i = 0, 4N + (N-1)^2 + ip the interior pair ip at i = N.
+// Face pairs fp(j, k): k = 0: j; k = N: N + 1 + j; 0 < k < N: 2 (N+1) +
+// 2 (k - 1) + (j == N).  Interior pairs: ip = (j - 1) + (N - 1)(k - 1).
+template <int N>
+__device__ __forceinline__ int split_fp(int j, int k)
+{
+    return k == 0 ? j : (k == N ? N + 1 + j : 2 * (N + 1) + 2 * (k - 1) + (j == N ? 1 : 0));
+}
+template <int N>
+__device__ __forceinline__ void split_fp_jk(int fp, int &j, int &k)
+{
+    if (fp <= N) {
+        j = fp;
+        k = 0;
+    } else if (fp < 2 * (N + 1)) {
+        j = fp - (N + 1);
+        k = N;
+    } else {
+        const int r = fp - 2 * (N + 1);
+        k = 1 + (r >> 1);
+        j = (r & 1) ? N : 0;
+    }
+}
+// slot in Fb of local node (N, j, k) (an unpaired east face)
+template <int N>
+__device__ __forceinline__ int split_slot_east(int j, int k)
+{
+    const bool face = j == 0 || j == N || k == 0 || k == N;
+    return face ? split_fp<N>(j, k) : 4 * N + (N - 1) * (N - 1) + (j - 1) + (N - 1) * (k - 1);
+}
+template <int N> constexpr int split_nb() { return 4 * N + 2 * (N - 1) * (N - 1); }
 
 // MODE 0: write J w R node-major for the finish kernel (NUMA_STAGE_GATHER);
 // MODE 1: one colour pass of NUMA_STAGE_COLOUR: the workgroup's elements are
 // the elements of colour `colour` (parity of ex, ey, ez), EB consecutive ones
 // along x, and every lane adds its nodes' J w R to the FP64 accumulator with
 // a plain read-modify-write (no other element of the colour has the node).
+// MODE 2: NUMA_STAGE_SPLIT (above): pair sums, the run-interior nodes
+// finished, the face contributions into Fa and Fb.
 template <int N, typename T, int MODE = 0>
-__global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T>())) void k_elem_col(Batch B, int colour)
+__global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) void k_elem_col(Batch B, int colour)
 {
     constexpr int P = N + 1, PP = P * P, NP = PP * P, EB = col_eb<N, T>(), BT = col_threads<N, T>();
     __shared__ T s[EB][8][NP];
@@ -206,8 +261,39 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T>())) void k
     constexpr bool F64 = sizeof(T) == 8;
     T irho[P], buoy[P], dz[8][P];
     double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
-    int ez = 0, base = 0;
+    int ez = 0, base = 0, exl = 0;
     const int layer = a.ni * a.nj;
+    // MODE 2: the run-interior nodes this lane finishes (interior pair ip,
+    // element qq, local ii; ii = 0 only where the run holds element qq - 1);
+    // their M^-1 and reference state are loaded now, used at the end
+    constexpr int NIN = (N - 1) * (N - 1) * EB * N, SPL = MODE == 2 && NIN > 0 ? (NIN + BT - 1) / BT : 1;
+    const int new_ = it.ne - e0 < EB ? it.ne - e0 : EB;
+    int32_t fI[SPL];
+    double fm[SPL], fq[SPL][5];
+#pragma unroll
+    for (int p = 0; p < SPL; ++p) {
+        fI[p] = -1;
+        fm[p] = 0.0;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) fq[p][v] = 0.0;
+    }
+    if constexpr (MODE == 2 && NIN > 0) {
+#pragma unroll
+        for (int p = 0; p < SPL; ++p) {
+            const int n = t + p * BT;
+            if (n >= NIN) continue;
+            const int ip = n / (EB * N), m = n - ip * (EB * N), qq = m / N, ii = m - qq * N;
+            if (qq >= new_) continue;
+            const BoxElem fe = box_elem((uint32_t)(e0 + qq), a.fx, a.fy);
+            if (ii == 0 && (qq == 0 || fe.ex == 0)) continue;  // run start: the face finish takes it
+            const int jj = 1 + ip % (N - 1), kk = 1 + ip / (N - 1);
+            fI[p] = fe.ex * N + ii + a.ni * (fe.ey * N + jj + a.nj * (fe.ez * N + kk));
+            fm[p] = it.Minv[fI[p]];
+            if (B.ca != 0.0)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) fq[p][v] = it.qn[fI[p] + v * a.nu];
+        }
+    }
     if (act) {
         BoxElem be;
         if constexpr (MODE == 1) {
@@ -219,6 +305,7 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T>())) void k
             be = box_elem((uint32_t)(e0 + q), a.fx, a.fy);
         }
         ez = be.ez;
+        exl = be.ex;
         const double *cp = a.hcol + (int64_t)(be.ex + a.nx * be.ey) * (4 * PP) + c;
         c0 = cp[0];
         c1 = cp[PP];
@@ -339,6 +426,33 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T>())) void k
         }
         return;  // every lane: no barrier follows
     }
+    if constexpr (MODE == 2) {
+        // the copies that stay unpaired go to Fb straight from the registers:
+        // the east face of an element whose east neighbour is not in the run,
+        // the interior pairs of the west face of a run start
+        constexpr int NFP = 4 * N, NIP = (N - 1) * (N - 1), NB = split_nb<N>();
+        const int64_t vs = (int64_t)a.nz * a.ny * NFP * a.ni;
+        T *Fb = (T *)it.ev + 5 * vs;
+        if (act) {
+            const int64_t eb = (int64_t)(e0 + q) * NB;
+            if (i == N && (q == EB - 1 || exl == a.nx - 1)) {
+#pragma unroll
+                for (int k = 0; k < P; ++k) {
+                    const int64_t o = (eb + split_slot_east<N>(j, k)) * 5;
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) Fb[o + v] = res[k][v];
+                }
+            }
+            if (NIP > 0 && i == 0 && (q == 0 || exl == 0) && j > 0 && j < N) {
+#pragma unroll
+                for (int k = 1; k < N; ++k) {
+                    const int64_t o = (eb + NFP + (j - 1) + (N - 1) * (k - 1)) * 5;
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) Fb[o + v] = res[k][v];
+                }
+            }
+        }
+    }
     __syncthreads();  // tiles read
     T *st = &s[0][0][0];
     if (act) {
@@ -348,10 +462,260 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T>())) void k
             for (int v = 0; v < 5; ++v) st[(q * NP + c + PP * k) * 5 + v] = res[k][v];
     }
     __syncthreads();
+    if constexpr (MODE == 2) {
+        constexpr int NFP = 4 * N, NIP = (N - 1) * (N - 1);
+        T *Fa = (T *)it.ev;
+        // Fa: the face pairs at i < N, the run's x pairs added (element qq's
+        // i = 0 copy plus element qq - 1's i = N copy).  Lane u < EB N 5 takes
+        // value v of node (qq, ii) of every face pair, so that each store
+        // instruction writes one contiguous run of the pair's row, and the
+        // lane's element, pair flag and offsets are formed once.
+        constexpr int RUN = EB * N * 5;  // values of one face pair of the workgroup
+        for (int u = t; u < RUN; u += BT) {
+            const int nd = u / 5, v = u - nd * 5, qq = nd / N, ii = nd - qq * N;
+            if (qq < new_) {
+                const BoxElem fe = box_elem((uint32_t)(e0 + qq), a.fx, a.fy);
+                const bool pair = ii == 0 && qq > 0 && fe.ex != 0;
+                const T *s0 = st + (qq * NP + ii) * 5 + v, *s1 = st + ((qq - 1) * NP + N) * 5 + v;
+                T *fo = Fa + (((int64_t)(fe.ez * a.ny + fe.ey) * NFP) * a.ni + fe.ex * N + ii) * 5 + v;
+#pragma unroll
+                for (int fp = 0; fp < NFP; ++fp) {
+                    int jj, kk;
+                    split_fp_jk<N>(fp, jj, kk);
+                    const int lo = P * (jj + P * kk) * 5;
+                    T val = s0[lo];
+                    if (pair) val += s1[lo];
+                    fo[(int64_t)fp * a.ni * 5] = val;
+                }
+            }
+        }
+        // the run-interior nodes: M^-1, the stage update, the state
+        if constexpr (NIN > 0) {
+            const StageCoef sc{B.ca, B.cb, it.cdt};
+#pragma unroll
+            for (int p = 0; p < SPL; ++p) {
+                if (fI[p] < 0) continue;
+                const int n = t + p * BT;
+                const int ip = n / (EB * N), m = n - ip * (EB * N), qq = m / N, ii = m - qq * N;
+                const int jj = 1 + ip % (N - 1), kk = 1 + ip / (N - 1);
+                const int l = ii + P * (jj + P * kk), lw = N + P * (jj + P * kk);
+                double r[5], o[5];
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    r[v] = (double)st[(qq * NP + l) * 5 + v];
+                    if (ii == 0) r[v] += (double)st[((qq - 1) * NP + lw) * 5 + v];
+                    r[v] *= fm[p];
+                }
+                if (F64 && B.fold) {
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) o[v] = rk_update_folded(sc, fq[p][v], r[v]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 5; ++v)
+                        o[v] = rk_update(sc, fq[p][v], sc.b == 0.0 ? 0.0 : it.qs[fI[p] + v * a.nu], r[v]);
+                }
+#pragma unroll
+                for (int v = 0; v < 5; ++v) it.qout[fI[p] + v * a.nu] = o[v];
+                flag_nonfinite(it.flag, o, 5);
+            }
+        }
+        return;
+    }
     // the workgroup's elements are consecutive: one contiguous run
     const int ne = it.ne - e0 < EB ? it.ne - e0 : EB;
     T *out = (T *)it.ev + (int64_t)e0 * (NP * 5);
     store_run<T>(out, st, ne * NP * 5, t, BT);
+}
+
+// NUMA_STAGE_SPLIT finish: the face nodes and the run-start interior nodes.
+// mblk blocks of an item take the face rows of the lattice, one node per
+// lane along x: per element layer ez the level gk = ez N (all nj rows), then
+// the levels ez N + 1 .. ez N + N - 1 (the ny rows gj = ey N), and with walls
+// the top level gk = nz N; frl divides by the rows per layer
+// nj + (N - 1) ny (fseg divides by ni).  The other blocks (interleaved) take
+// the interior pairs at the x face that starts a run: the elements e = c EB (one per element workgroup),
+// then the row starts e = r nx that are not multiples of EB.  Every node's
+// copies are read in a fixed order (z copies, y copies, then the x copies of
+// each), summed in FP64, multiplied by M^-1, projected at the walls and
+// advanced by the stage update.
+template <int N, typename T>
+__global__ __launch_bounds__(256) void k_fin_split(Batch B)
+{
+    constexpr int NFP = 4 * N, NIP = (N - 1) * (N - 1), NB = split_nb<N>(), EB = col_eb<N, T>();
+    const int g = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const BatchItem &it = B.it[batch_item(B, g, true)];
+    const int nx = (int)it.fx.d, ny = (int)it.fy.d, nz = it.nz, ni = it.ni, nj = it.nj;
+    // the item's blocks: mblk face-row blocks and nbb run-start blocks, the
+    // latter spread evenly (block k at k S + S - 1, S = total / nbb), so that
+    // every XCD's range of the launch holds its share of the scattered ones
+    int lb = g - it.boff;
+    const int nbb = NIP == 0 ? 0 : (((it.ne + EB - 1) / EB + ny * nz) * NIP + 255) / 256;
+    bool runstart = false;
+    if (nbb > 0) {
+        const int S = (it.mblk + nbb) / nbb;
+        if (lb < nbb * S) {
+            const int k = lb / S;
+            runstart = lb - k * S == S - 1;
+            lb = runstart ? k : lb - k;
+        } else {
+            lb -= nbb;
+        }
+    }
+    const int64_t vs = (int64_t)nz * ny * NFP * ni;
+    const T *Fa = (const T *)it.ev, *Fb = Fa + 5 * vs;
+    int gi, gj, gk;
+    double r[5] = {0, 0, 0, 0, 0};
+    // the stage update's operands are loaded as soon as the node is known,
+    // before its copies: one memory round trip per node instead of two
+    const StageCoef sc{B.ca, B.cb, it.cdt};
+    double mi, qnv[5], qsv[5];
+    int32_t I;
+    bool folded;
+    auto update_loads = [&]() {
+        I = gi + ni * (gj + nj * gk);
+        folded = B.fold && !(it.walls && (gk == 0 || gk == nz * N));
+        mi = it.Minv[I];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) {
+            qnv[v] = sc.a == 0.0 ? 0.0 : it.qn[I + v * it.nu];
+            qsv[v] = folded || sc.b == 0.0 ? 0.0 : it.qs[I + v * it.nu];
+        }
+    };
+    if (!runstart) {
+        const int rl = (int)it.frl.d;
+        const int nrows = nz * rl + (it.walls ? nj : 0);
+        const uint32_t id = (uint32_t)lb * 256u + threadIdx.x;
+        if (id >= (uint32_t)nrows * (uint32_t)ni) return;
+        const uint32_t R = fdiv(id, it.fseg);
+        gi = (int)(id - R * (uint32_t)ni);
+        const uint32_t ezr = fdiv(R, it.frl);
+        int rr = (int)(R - ezr * (uint32_t)rl);
+        if ((int)ezr == nz) {  // the top wall level
+            gk = nz * N;
+            gj = rr;
+        } else if (rr < nj) {
+            gk = (int)ezr * N;
+            gj = rr;
+        } else {
+            rr -= nj;
+            const uint32_t kk = fdiv((uint32_t)rr, it.fy);
+            gj = (rr - (int)kk * ny) * N;
+            gk = (int)ezr * N + 1 + (int)kk;
+        }
+        update_loads();
+        // copies: z (element layer, local k), y (element row, local j)
+        int zc[2], kc[2], nzc = 1, yc[2], jc[2], nyc = 1;
+        zc[0] = gk / N;
+        kc[0] = gk % N;
+        zc[1] = zc[0];
+        kc[1] = kc[0];
+        if (kc[0] == 0) {
+            if (it.walls && gk == nz * N) {
+                zc[0] = nz - 1;
+                kc[0] = N;
+            } else if (!(it.walls && gk == 0)) {
+                zc[1] = zc[0] == 0 ? nz - 1 : zc[0] - 1;
+                kc[1] = N;
+                nzc = 2;
+            }
+        }
+        yc[0] = gj / N;
+        jc[0] = gj % N;
+        yc[1] = yc[0];
+        jc[1] = jc[0];
+        if (jc[0] == 0) {
+            yc[1] = yc[0] == 0 ? ny - 1 : yc[0] - 1;
+            jc[1] = N;
+            nyc = 2;
+        }
+        const int ex = gi / N;
+        const bool xface = gi % N == 0;
+        // every copy's loads first (absent ones are not loaded), then the sum
+        T ca[2][2][5], cb[2][2][5];
+#pragma unroll
+        for (int z = 0; z < 2; ++z)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const bool has = z < nzc && y < nyc;
+                const int fp = split_fp<N>(jc[y], kc[z]);
+                const int64_t o = ((int64_t)(zc[z] * ny + yc[y]) * NFP + fp) * ni + gi;
+                const int ec = ex + nx * (yc[y] + ny * zc[z]);
+                const bool unpaired = has && xface && (ex == 0 || ec % EB == 0);
+                const int64_t ob = ((int64_t)(ex == 0 ? ec + nx - 1 : ec - 1) * NB + fp) * 5;
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    ca[z][y][v] = has ? Fa[o * 5 + v] : (T)0;
+                    cb[z][y][v] = unpaired ? Fb[ob + v] : (T)0;
+                }
+            }
+#pragma unroll
+        for (int z = 0; z < 2; ++z)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const bool has = z < nzc && y < nyc;
+                const bool unpaired = has && xface && (ex == 0 || (ex + nx * (yc[y] + ny * zc[z])) % EB == 0);
+#pragma unroll
+                for (int v = 0; v < 5; ++v) {
+                    if (has) r[v] += (double)ca[z][y][v];
+                    if (unpaired) r[v] += (double)cb[z][y][v];
+                }
+            }
+    } else {
+        if constexpr (NIP == 0) {
+            return;
+        } else {
+            const int nwg = (it.ne + EB - 1) / EB, nrs = ny * nz;
+            const int id = lb * 256 + (int)threadIdx.x;
+            const int cand = id / NIP, ip = id - cand * NIP;
+            if (cand >= nwg + nrs) return;
+            int e;
+            if (cand < nwg) {
+                e = cand * EB;
+            } else {
+                e = (cand - nwg) * nx;
+                if (e % EB == 0) return;  // a workgroup start: taken above
+            }
+            const BoxElem be = box_elem((uint32_t)e, it.fx, it.fy);
+            const int jj = 1 + ip % (N - 1), kk = 1 + ip / (N - 1);
+            gi = be.ex * N;
+            gj = be.ey * N + jj;
+            gk = be.ez * N + kk;
+            update_loads();
+            const int ew = be.ex == 0 ? e + nx - 1 : e - 1;  // the element west of the run start
+            const int64_t o0 = ((int64_t)e * NB + NFP + ip) * 5, o1 = ((int64_t)ew * NB + NFP + NIP + ip) * 5;
+            T c0[5], c1[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                c0[v] = Fb[o0 + v];
+                c1[v] = Fb[o1 + v];
+            }
+#pragma unroll
+            for (int v = 0; v < 5; ++v) r[v] = (double)c0[v] + (double)c1[v];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) r[v] *= mi;
+    double o[5];
+    if (folded) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) o[v] = rk_update_folded(sc, qnv[v], r[v]);
+    } else {
+        PointArgs p;
+        p.off = nullptr;
+        p.idx = nullptr;
+        p.Minv = it.Minv;
+        p.nrm = it.nrm;
+        p.nl = 0;
+        p.nu = it.nu;
+        p.nh = it.nh;
+        p.walls = it.walls;
+        noflux(p, I, r[1], r[2], r[3]);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) o[v] = rk_update(sc, qnv[v], qsv[v], r[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) it.qout[I + v * it.nu] = o[v];
+    flag_nonfinite(it.flag, o, 5);
 }
 
 // NUMA_STAGE_COLOUR: zero the accumulator [5][nu] of every item (a kernel,
@@ -574,8 +938,9 @@ __global__ void k_fin_batch(Batch B)
 }
 
 template <int N, typename T, int SEG>
-int32_t run_chunk_seg(const StepItem *items, int n, int phase, hipStream_t s, bool colour)
+int32_t run_chunk_seg(const StepItem *items, int n, int phase, hipStream_t s, int mode)
 {
+    const bool colour = mode == 1, split = mode == 2;
     Batch B;
     B.n = n;
     B.ca = items[0].c.a;
@@ -622,8 +987,11 @@ int32_t run_chunk_seg(const StepItem *items, int n, int phase, hipStream_t s, bo
         it.walls = m.walls ? 1 : 0;
         it.fx = fast_div((uint32_t)m.d.ne[0]);
         it.fy = fast_div((uint32_t)m.d.ne[1]);
-        it.fseg = fast_div((uint32_t)(m.d.ne[0] / SEG));
-        const int64_t mblk = (int64_t)(m.d.ne[0] / SEG) * m.d.ne[1] * m.d.ne[2];
+        // the gather finish's segments (a split item's x extent need not hold
+        // one: its fields are set below)
+        const int nseg = m.d.ne[0] / SEG > 0 ? m.d.ne[0] / SEG : 1;
+        it.fseg = fast_div((uint32_t)nseg);
+        const int64_t mblk = (int64_t)nseg * m.d.ne[1] * m.d.ne[2];
         it.mblk = (int)mblk;
         it.cdt = items[k].c.cdt;
         it.theta0 = m.ph.T0;
@@ -637,6 +1005,18 @@ int32_t run_chunk_seg(const StepItem *items, int n, int phase, hipStream_t s, bo
             it.fy = fast_div((uint32_t)(m.d.ne[1] / 2));
             eo += (it.ne + eb - 1) / eb * eb;
             bo += (m.nu + 255) / 256;
+        } else if (split) {  // face rows, 256 lattice points per block, then the run starts
+            const int nx = m.d.ne[0], ny = m.d.ne[1], nz = m.d.ne[2];
+            const int64_t rl = m.nj + (int64_t)(N - 1) * ny;
+            const int64_t rows = nz * rl + (m.walls ? m.nj : 0);
+            const int64_t nwg = (m.ne + eb - 1) / eb;
+            const int64_t nip = (int64_t)(N - 1) * (N - 1);
+            it.fseg = fast_div((uint32_t)m.ni);
+            it.frl = fast_div((uint32_t)rl);
+            it.mblk = (int)((rows * m.ni + 255) / 256);
+            eo += nwg * eb;
+            bo += it.mblk + ((nwg + (int64_t)ny * nz) * nip + 255) / 256;
+            (void)nx;
         } else {
             eo += (m.ne + eb - 1) / eb * eb;
             bo += mblk + (m.walls ? (int64_t)(m.d.ne[0] / SEG) * m.d.ne[1] : 0);
@@ -657,6 +1037,17 @@ int32_t run_chunk_seg(const StepItem *items, int n, int phase, hipStream_t s, bo
             } else {
                 hipLaunchKernelGGL(k_colour_finish, dim3((unsigned)bo), dim3(256), 0, s, B);
             }
+            NUMA_HIP(hipGetLastError());
+            return NUMA_OK;
+        }
+    }
+    if (split) {
+        if constexpr (kind == 0) {
+            if (phase == 0)
+                hipLaunchKernelGGL((k_elem_col<N, T, 2>), dim3((unsigned)(eo / eb)), dim3(col_threads<N, T>()), 0, s, B,
+                                   0);
+            else
+                hipLaunchKernelGGL((k_fin_split<N, T>), dim3((unsigned)bo), dim3(256), 0, s, B);
             NUMA_HIP(hipGetLastError());
             return NUMA_OK;
         }
@@ -699,15 +1090,15 @@ int pick_seg(const StepItem *items, int n)
 }
 
 template <int N, typename T>
-int32_t run_chunk(const StepItem *items, int n, int phase, hipStream_t s, bool colour)
+int32_t run_chunk(const StepItem *items, int n, int phase, hipStream_t s, int mode)
 {
     if constexpr (seg_wide<N>() != seg_for<N>()) {
         static_assert(seg_wide<N>() == 4 * seg_for<N>(), "segments 4x, 2x and 1x of the narrowest");
         const int seg = pick_seg<N>(items, n);
-        if (seg == seg_wide<N>()) return run_chunk_seg<N, T, seg_wide<N>()>(items, n, phase, s, colour);
-        if (seg == 2 * seg_for<N>()) return run_chunk_seg<N, T, 2 * seg_for<N>()>(items, n, phase, s, colour);
+        if (seg == seg_wide<N>()) return run_chunk_seg<N, T, seg_wide<N>()>(items, n, phase, s, mode);
+        if (seg == 2 * seg_for<N>()) return run_chunk_seg<N, T, 2 * seg_for<N>()>(items, n, phase, s, mode);
     }
-    return run_chunk_seg<N, T, seg_for<N>()>(items, n, phase, s, colour);
+    return run_chunk_seg<N, T, seg_for<N>()>(items, n, phase, s, mode);
 }
 
 // DSS of node-major FP64 contributions ev ([n_local][5]) into q with M^-1
@@ -758,20 +1149,20 @@ int32_t run_plain_finish(const Mesh &m, const double *ev, double *q, hipStream_t
 }
 
 template <typename T>
-int32_t run_stage_t(const StepItem *items, int n, int phase, hipStream_t s, bool colour)
+int32_t run_stage_t(const StepItem *items, int n, int phase, hipStream_t s, int mode)
 {
     for (int c0 = 0; c0 < n; c0 += kMaxBatch) {
         const int c = n - c0 < kMaxBatch ? n - c0 : kMaxBatch;
         int32_t rc;
         switch (items[0].mesh->N) {
-        case 1: rc = run_chunk<1, T>(items + c0, c, phase, s, colour); break;
-        case 2: rc = run_chunk<2, T>(items + c0, c, phase, s, colour); break;
-        case 3: rc = run_chunk<3, T>(items + c0, c, phase, s, colour); break;
-        case 4: rc = run_chunk<4, T>(items + c0, c, phase, s, colour); break;
-        case 5: rc = run_chunk<5, T>(items + c0, c, phase, s, colour); break;
-        case 6: rc = run_chunk<6, T>(items + c0, c, phase, s, colour); break;
-        case 7: rc = run_chunk<7, T>(items + c0, c, phase, s, colour); break;
-        default: rc = run_chunk<8, T>(items + c0, c, phase, s, colour); break;
+        case 1: rc = run_chunk<1, T>(items + c0, c, phase, s, mode); break;
+        case 2: rc = run_chunk<2, T>(items + c0, c, phase, s, mode); break;
+        case 3: rc = run_chunk<3, T>(items + c0, c, phase, s, mode); break;
+        case 4: rc = run_chunk<4, T>(items + c0, c, phase, s, mode); break;
+        case 5: rc = run_chunk<5, T>(items + c0, c, phase, s, mode); break;
+        case 6: rc = run_chunk<6, T>(items + c0, c, phase, s, mode); break;
+        case 7: rc = run_chunk<7, T>(items + c0, c, phase, s, mode); break;
+        default: rc = run_chunk<8, T>(items + c0, c, phase, s, mode); break;
         }
         if (rc) return rc;
     }
@@ -817,25 +1208,40 @@ bool colour_ok(const Mesh &m)
            m.N <= 4 && m.d.ne[0] % 2 == 0 && m.d.ne[1] % 2 == 0 && m.d.ne[2] % 2 == 0;
 }
 
+// NUMA_STAGE_SPLIT runs the column element kernel (recomputed metric, N <= 4);
+// its finish takes any x extent
+bool split_ok(const Mesh &m)
+{
+    return m.stage_mode == NUMA_STAGE_SPLIT && m.d.kind == NUMA_MESH_BOX && m.metric_mode == NUMA_METRIC_RECOMPUTE &&
+           m.N <= 4;
+}
+
 int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int phase, hipStream_t s)
 {
     // items the fused block kernels take (pencil.hip), the colour passes, the
-    // rest; partitioned in chunks on the stack, with no host allocation
+    // split DSS, the rest; partitioned in chunks on the stack, with no host
+    // allocation
     constexpr int kChunk = 4 * kMaxBatch;
-    StepItem part[3][kChunk];
+    StepItem part[4][kChunk];
     for (int c0 = 0; c0 < n; c0 += kChunk) {
         const int cn = n - c0 < kChunk ? n - c0 : kChunk;
-        int cnt[3] = {0, 0, 0};
+        int cnt[4] = {0, 0, 0, 0};
         for (int k = c0; k < c0 + cn; ++k) {
-            const int g = pencil_stage_ok(items[k], prec) ? 0 : colour_ok(*items[k].mesh) ? 1 : 2;
+            const Mesh &m = *items[k].mesh;
+            const int g = pencil_stage_ok(items[k], prec) ? 0 : colour_ok(m) ? 1 : split_ok(m) ? 2 : 3;
+            if (g == 3 && !box_batchable(m)) {
+                set_error("batched stage: a box mesh whose x element count does not fit the finish segment");
+                return NUMA_EUNSUPPORTED;
+            }
             part[g][cnt[g]++] = items[k];
         }
         int32_t rc;
         if (cnt[0] && (rc = launch_pencil_stage(part[0], cnt[0], prec, phase, s))) return rc;
-        for (int g = 1; g < 3; ++g) {
+        for (int g = 1; g < 4; ++g) {
             if (!cnt[g]) continue;
-            rc = prec == NUMA_PREC_MIXED ? run_stage_t<float>(part[g], cnt[g], phase, s, g == 1)
-                                         : run_stage_t<double>(part[g], cnt[g], phase, s, g == 1);
+            const int mode = g == 1 ? 1 : g == 2 ? 2 : 0;
+            rc = prec == NUMA_PREC_MIXED ? run_stage_t<float>(part[g], cnt[g], phase, s, mode)
+                                         : run_stage_t<double>(part[g], cnt[g], phase, s, mode);
             if (rc) return rc;
         }
     }

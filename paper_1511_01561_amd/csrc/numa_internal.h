@@ -203,6 +203,10 @@ struct StepItem {
 // Box meshes whose x extent fits the finish block's segment take the batched
 // kernels; phase 0 launches the element kernels, phase 1 the finish kernels.
 bool box_batchable(const Mesh &m);
+// the mesh's stages run through the batched kernels: box_batchable, or the
+// split DSS (NUMA_STAGE_SPLIT), which takes any box x extent
+bool split_ok(const Mesh &m);
+inline bool stage_batched(const Mesh &m) { return box_batchable(m) || split_ok(m); }
 int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int phase, hipStream_t s);
 
 // Batched steps (api.cpp), shared by numa_step_batch and the no-allocation

@@ -51,7 +51,7 @@ def _pair(N, ne, oracle_mod, mode=1):
     return p
 
 
-MODES = [1, 2]  # NUMA_STAGE_BLOCK, NUMA_STAGE_COLOUR
+MODES = [1, 2, 3]  # NUMA_STAGE_BLOCK, NUMA_STAGE_COLOUR, NUMA_STAGE_SPLIT
 
 
 @pytest.mark.parametrize("mode", MODES)
