@@ -230,7 +230,7 @@ int32_t numa_mesh_set_stage(numa_mesh_t m, int32_t mode)
         return NUMA_EINVAL;
     }
     if (mode != NUMA_STAGE_GATHER && mode != NUMA_STAGE_BLOCK && mode != NUMA_STAGE_COLOUR &&
-        mode != NUMA_STAGE_SPLIT) {
+        mode != NUMA_STAGE_SPLIT && mode != NUMA_STAGE_AUTO) {
         set_error("numa_mesh_set_stage: unknown mode %d", mode);
         return NUMA_EINVAL;
     }
@@ -514,7 +514,7 @@ static int32_t enqueue_step(numa_mesh_t m, int32_t prec, double dt, double *q, h
     double *buf[3] = {q, m->dv.qs, m->dv.qs2};
     int ns;
     const StagePlan *plan = stage_plan(m->integrator, &ns);
-    const bool batched = numa::stage_batched(*m);
+    const bool batched = numa::stage_batched(*m, prec);
     void *ev = m->dv.ev64;  // FP64-sized: element contributions of either precision, or an FP64 accumulator
     int32_t rc;
     for (int k = 0; k < ns; ++k) {
@@ -624,7 +624,7 @@ int32_t numa_stage_rhs(numa_mesh_t m, int32_t prec, const double *q, double *r, 
     // kernel folds q_s into the contributions): the summed, mass-weighted,
     // projected right-hand side itself
     const numa::StageCoef c{0.0, 0.0, 1.0};
-    if (numa::stage_batched(*m)) {
+    if (numa::stage_batched(*m, prec)) {
         void *ev = m->dv.ev64;  // FP64-sized: element contributions of either precision, or an FP64 accumulator
         numa::StepItem it = {m, q, q, r, ev, c};
         return run_batch_stage(&it, 1, prec, s);
@@ -669,7 +669,7 @@ int32_t numa_imex_step(numa_mesh_t m, int32_t prec, double dt, double ra, int32_
     const numa::StageCoef c{1.0, 0.0, 2.0 * dt};  // q* = q^{n-1} + 2 dt L(q^n)
     void *ev = m->dv.ev64;  // FP64-sized: element contributions of either precision, or an FP64 accumulator
     for (int n = 0; n < nsteps; ++n) {
-        if (numa::stage_batched(*m)) {
+        if (numa::stage_batched(*m, prec)) {
             numa::StepItem it = {m, qprev, qcur, m->dv.qs, ev, c};
             rc = run_batch_stage(&it, 1, prec, s);
         } else {
@@ -724,7 +724,7 @@ int32_t numa::check_batch(const numa_batch_item *items, int32_t n, int32_t prec,
         int32_t rc = need_ready(m, fn);
         if (rc) return rc;
         if ((rc = check_prec(m, prec, fn))) return rc;
-        if (!numa::stage_batched(*m)) {
+        if (!numa::stage_batched(*m, prec)) {
             set_error("%s: item %d: batched stages need a box mesh whose x element count fits the finish segment "
                       "(or NUMA_STAGE_SPLIT with the recomputed metric, N <= 4)", fn, k);
             return NUMA_EUNSUPPORTED;

@@ -194,18 +194,26 @@ constexpr int col_blocks() { return (sizeof(T) == 4 && N == 4) ? (MODE == 2 ? 3 
 // LDS.  A node whose (j, k) is interior to the element (0 < j, k < N) then has
 // all its copies in the workgroup unless it sits on the x face that starts
 // the run (q = 0 or ex = 0), and the element kernel finishes it itself: M^-1,
-// the stage update and the state write (these nodes are never on a wall).
-// What remains are the face nodes (gj or gk a multiple of N: 4N of the
-// (N+1)^2 (j, k) pairs of an element, "face pairs") and the run-start nodes
-// of the interior pairs.  Their contributions are written in two arrays:
+// the stage update and the state write (these nodes are never on a wall),
+// except in the run's first element (see Fb).  What remains are the face
+// nodes (gj or gk a multiple of N: 4N of the (N+1)^2 (j, k) pairs of an
+// element, "face pairs") and the interior rows of a run's first element.
+// Their contributions are written in two arrays:
 //  * Fa [nz][ny][4N][ni][5] (of T): per element row (ey, ez), face pair fp and
 //    lattice position gi = ex N + i (i < N) the five values of the
 //    contribution of element ex at local i (at i = 0 the pair sum when the run
 //    holds element ex - 1), so the finish reads each face row of the lattice
 //    as one contiguous run per copy;
-//  * Fb [ne][4N + 2 (N-1)^2][5]: the copies that stay unpaired at run
-//    boundaries: slots 0..4N-1 the face pairs at i = N, 4N + ip the interior
-//    pair ip at i = 0, 4N + (N-1)^2 + ip the interior pair ip at i = N.
+//  * Fb [ne][4N + (N-1)^2 (N+1)][5]: the copies the finish kernel takes at
+//    run boundaries: slots 0..4N-1 the face pairs at i = N and 4N + ip the
+//    interior pair ip at i = N of an element whose east neighbour is not in
+//    its run; 4N + (N-1)^2 + ip N + i the interior pair ip at i < N of a run's
+//    first element.  The finish kernel takes those N nodes of every interior
+//    row at a run start together (whole 32-byte sectors of the state rows,
+//    where single scattered nodes would cost a read-modify-write each), so
+//    the element kernel finishes none of its first element's nodes.
+// Fa, Fb and the face pairs fill (N+1)^3 values per element: the workspace's
+// contribution scratch.
 // Face pairs fp(j, k): k = 0: j; k = N: N + 1 + j; 0 < k < N: 2 (N+1) +
 // 2 (k - 1) + (j == N).  Interior pairs: ip = (j - 1) + (N - 1)(k - 1).
 template <int N>
@@ -233,9 +241,9 @@ template <int N>
 __device__ __forceinline__ int split_slot_east(int j, int k)
 {
     const bool face = j == 0 || j == N || k == 0 || k == N;
-    return face ? split_fp<N>(j, k) : 4 * N + (N - 1) * (N - 1) + (j - 1) + (N - 1) * (k - 1);
+    return face ? split_fp<N>(j, k) : 4 * N + (j - 1) + (N - 1) * (k - 1);
 }
-template <int N> constexpr int split_nb() { return 4 * N + 2 * (N - 1) * (N - 1); }
+template <int N> constexpr int split_nb() { return 4 * N + (N - 1) * (N - 1) * (N + 1); }
 
 // MODE 0: write J w R node-major for the finish kernel (NUMA_STAGE_GATHER);
 // MODE 1: one colour pass of NUMA_STAGE_COLOUR: the workgroup's elements are
@@ -264,8 +272,9 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
     int ez = 0, base = 0, exl = 0;
     const int layer = a.ni * a.nj;
     // MODE 2: the run-interior nodes this lane finishes (interior pair ip,
-    // element qq, local ii; ii = 0 only where the run holds element qq - 1);
-    // their M^-1 and reference state are loaded now, used at the end
+    // element qq, local ii; not in the run's first element, whose west
+    // neighbour is not in the workgroup); their M^-1 and reference state
+    // are loaded now, used at the end
     constexpr int NIN = (N - 1) * (N - 1) * EB * N, SPL = MODE == 2 && NIN > 0 ? (NIN + BT - 1) / BT : 1;
     const int new_ = it.ne - e0 < EB ? it.ne - e0 : EB;
     int32_t fI[SPL];
@@ -285,7 +294,7 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
             const int ip = n / (EB * N), m = n - ip * (EB * N), qq = m / N, ii = m - qq * N;
             if (qq >= new_) continue;
             const BoxElem fe = box_elem((uint32_t)(e0 + qq), a.fx, a.fy);
-            if (ii == 0 && (qq == 0 || fe.ex == 0)) continue;  // run start: the face finish takes it
+            if (qq == 0 || fe.ex == 0) continue;  // a run's first element: the finish kernel takes it
             const int jj = 1 + ip % (N - 1), kk = 1 + ip / (N - 1);
             fI[p] = fe.ex * N + ii + a.ni * (fe.ey * N + jj + a.nj * (fe.ez * N + kk));
             fm[p] = it.Minv[fI[p]];
@@ -427,9 +436,9 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
         return;  // every lane: no barrier follows
     }
     if constexpr (MODE == 2) {
-        // the copies that stay unpaired go to Fb straight from the registers:
-        // the east face of an element whose east neighbour is not in the run,
-        // the interior pairs of the west face of a run start
+        // the copies the finish kernel takes go to Fb straight from the
+        // registers: the east face of an element whose east neighbour is not
+        // in the run, the interior rows of a run's first element
         constexpr int NFP = 4 * N, NIP = (N - 1) * (N - 1), NB = split_nb<N>();
         const int64_t vs = (int64_t)a.nz * a.ny * NFP * a.ni;
         T *Fb = (T *)it.ev + 5 * vs;
@@ -443,10 +452,10 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
                     for (int v = 0; v < 5; ++v) Fb[o + v] = res[k][v];
                 }
             }
-            if (NIP > 0 && i == 0 && (q == 0 || exl == 0) && j > 0 && j < N) {
+            if (NIP > 0 && i < N && (q == 0 || exl == 0) && j > 0 && j < N) {
 #pragma unroll
                 for (int k = 1; k < N; ++k) {
-                    const int64_t o = (eb + NFP + (j - 1) + (N - 1) * (k - 1)) * 5;
+                    const int64_t o = (eb + NFP + NIP + ((j - 1) + (N - 1) * (k - 1)) * N + i) * 5;
 #pragma unroll
                     for (int v = 0; v < 5; ++v) Fb[o + v] = res[k][v];
                 }
@@ -533,8 +542,9 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
 // the levels ez N + 1 .. ez N + N - 1 (the ny rows gj = ey N), and with walls
 // the top level gk = nz N; frl divides by the rows per layer
 // nj + (N - 1) ny (fseg divides by ni).  The other blocks (interleaved) take
-// the interior pairs at the x face that starts a run: the elements e = c EB (one per element workgroup),
-// then the row starts e = r nx that are not multiples of EB.  Every node's
+// the interior rows of a run's first element, N nodes per row (i < N): the
+// elements e = c EB (one per element workgroup), then the row starts
+// e = r nx that are not multiples of EB.  Every node's
 // copies are read in a fixed order (z copies, y copies, then the x copies of
 // each), summed in FP64, multiplied by M^-1, projected at the walls and
 // advanced by the stage update.
@@ -549,7 +559,7 @@ __global__ __launch_bounds__(256) void k_fin_split(Batch B)
     // latter spread evenly (block k at k S + S - 1, S = total / nbb), so that
     // every XCD's range of the launch holds its share of the scattered ones
     int lb = g - it.boff;
-    const int nbb = NIP == 0 ? 0 : (((it.ne + EB - 1) / EB + ny * nz) * NIP + 255) / 256;
+    const int nbb = NIP == 0 ? 0 : (((it.ne + EB - 1) / EB + ny * nz) * NIP * N + 255) / 256;
     bool runstart = false;
     if (nbb > 0) {
         const int S = (it.mblk + nbb) / nbb;
@@ -666,7 +676,7 @@ __global__ __launch_bounds__(256) void k_fin_split(Batch B)
         } else {
             const int nwg = (it.ne + EB - 1) / EB, nrs = ny * nz;
             const int id = lb * 256 + (int)threadIdx.x;
-            const int cand = id / NIP, ip = id - cand * NIP;
+            const int cand = id / (NIP * N), rr = id - cand * (NIP * N), ip = rr / N, i = rr - ip * N;
             if (cand >= nwg + nrs) return;
             int e;
             if (cand < nwg) {
@@ -677,20 +687,20 @@ __global__ __launch_bounds__(256) void k_fin_split(Batch B)
             }
             const BoxElem be = box_elem((uint32_t)e, it.fx, it.fy);
             const int jj = 1 + ip % (N - 1), kk = 1 + ip / (N - 1);
-            gi = be.ex * N;
+            gi = be.ex * N + i;
             gj = be.ey * N + jj;
             gk = be.ez * N + kk;
             update_loads();
             const int ew = be.ex == 0 ? e + nx - 1 : e - 1;  // the element west of the run start
-            const int64_t o0 = ((int64_t)e * NB + NFP + ip) * 5, o1 = ((int64_t)ew * NB + NFP + NIP + ip) * 5;
+            const int64_t o0 = ((int64_t)e * NB + NFP + NIP + ip * N + i) * 5, o1 = ((int64_t)ew * NB + NFP + ip) * 5;
             T c0[5], c1[5];
 #pragma unroll
             for (int v = 0; v < 5; ++v) {
                 c0[v] = Fb[o0 + v];
-                c1[v] = Fb[o1 + v];
+                c1[v] = i == 0 ? Fb[o1 + v] : (T)0;
             }
 #pragma unroll
-            for (int v = 0; v < 5; ++v) r[v] = (double)c0[v] + (double)c1[v];
+            for (int v = 0; v < 5; ++v) r[v] = i == 0 ? (double)c0[v] + (double)c1[v] : (double)c0[v];
         }
     }
 #pragma unroll
@@ -1010,7 +1020,7 @@ int32_t run_chunk_seg(const StepItem *items, int n, int phase, hipStream_t s, in
             const int64_t rl = m.nj + (int64_t)(N - 1) * ny;
             const int64_t rows = nz * rl + (m.walls ? m.nj : 0);
             const int64_t nwg = (m.ne + eb - 1) / eb;
-            const int64_t nip = (int64_t)(N - 1) * (N - 1);
+            const int64_t nip = (int64_t)(N - 1) * (N - 1) * N;  // run-start lanes per candidate
             it.fseg = fast_div((uint32_t)m.ni);
             it.frl = fast_div((uint32_t)rl);
             it.mblk = (int)((rows * m.ni + 255) / 256);
@@ -1209,11 +1219,13 @@ bool colour_ok(const Mesh &m)
 }
 
 // NUMA_STAGE_SPLIT runs the column element kernel (recomputed metric, N <= 4);
-// its finish takes any x extent
-bool split_ok(const Mesh &m)
+// its finish takes any x extent.  NUMA_STAGE_AUTO takes it in FP64 (measured
+// faster than the gather there; in mixed precision the gather, whose FP32
+// contributions are half the bytes, is faster)
+bool split_ok(const Mesh &m, int32_t prec)
 {
-    return m.stage_mode == NUMA_STAGE_SPLIT && m.d.kind == NUMA_MESH_BOX && m.metric_mode == NUMA_METRIC_RECOMPUTE &&
-           m.N <= 4;
+    const bool mode = m.stage_mode == NUMA_STAGE_SPLIT || (m.stage_mode == NUMA_STAGE_AUTO && prec == NUMA_PREC_FP64);
+    return mode && m.d.kind == NUMA_MESH_BOX && m.metric_mode == NUMA_METRIC_RECOMPUTE && m.N <= 4;
 }
 
 int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int phase, hipStream_t s)
@@ -1228,7 +1240,7 @@ int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int phase
         int cnt[4] = {0, 0, 0, 0};
         for (int k = c0; k < c0 + cn; ++k) {
             const Mesh &m = *items[k].mesh;
-            const int g = pencil_stage_ok(items[k], prec) ? 0 : colour_ok(m) ? 1 : split_ok(m) ? 2 : 3;
+            const int g = pencil_stage_ok(items[k], prec) ? 0 : colour_ok(m) ? 1 : split_ok(m, prec) ? 2 : 3;
             if (g == 3 && !box_batchable(m)) {
                 set_error("batched stage: a box mesh whose x element count does not fit the finish segment");
                 return NUMA_EUNSUPPORTED;

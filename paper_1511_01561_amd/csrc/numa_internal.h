@@ -129,7 +129,7 @@ struct Mesh {
     DeviceView dv;
     bool uploaded = false, geom = false;
     int metric_mode = 0;  // NUMA_METRIC_STORED or NUMA_METRIC_RECOMPUTE (box)
-    int stage_mode = 0;   // NUMA_STAGE_GATHER, NUMA_STAGE_BLOCK or NUMA_STAGE_COLOUR (box)
+    int stage_mode = NUMA_STAGE_AUTO;  // NUMA_STAGE_* (box)
     int integrator = 0;         // NUMA_RK_SSP33 or NUMA_RK_SSP53
     double imex_dt = 0.0;       // dt of the IMEX factors in the workspace (valid when imex_ok)
     bool imex_ok = false;
@@ -203,10 +203,12 @@ struct StepItem {
 // Box meshes whose x extent fits the finish block's segment take the batched
 // kernels; phase 0 launches the element kernels, phase 1 the finish kernels.
 bool box_batchable(const Mesh &m);
-// the mesh's stages run through the batched kernels: box_batchable, or the
-// split DSS (NUMA_STAGE_SPLIT), which takes any box x extent
-bool split_ok(const Mesh &m);
-inline bool stage_batched(const Mesh &m) { return box_batchable(m) || split_ok(m); }
+// the mesh's stages of precision prec run the split DSS (NUMA_STAGE_SPLIT,
+// or NUMA_STAGE_AUTO in FP64)
+bool split_ok(const Mesh &m, int32_t prec);
+// ... through the batched kernels: box_batchable, or the split DSS, which
+// takes any box x extent
+inline bool stage_batched(const Mesh &m, int32_t prec) { return box_batchable(m) || split_ok(m, prec); }
 int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int phase, hipStream_t s);
 
 // Batched steps (api.cpp), shared by numa_step_batch and the no-allocation

@@ -19,7 +19,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 DSS_MASS, DSS_NOFLUX = 1, 2
 METRIC_STORED, METRIC_RECOMPUTE = 0, 1
 RK_SSP33, RK_SSP53 = 0, 1
-STAGE_GATHER, STAGE_BLOCK, STAGE_COLOUR, STAGE_SPLIT = 0, 1, 2, 3
+STAGE_GATHER, STAGE_BLOCK, STAGE_COLOUR, STAGE_SPLIT, STAGE_AUTO = 0, 1, 2, 3, 4
 WS_IMEX = 4
 WS_LEAN = 8
 FIELD_MASS, FIELD_REF, FIELD_COORDS, FIELD_METRIC, FIELD_GRAVITY, FIELD_LOCAL_COORDS = range(6)
@@ -297,7 +297,7 @@ class Mesh:
         check(lib().numa_mesh_set_step_graph(self._h, int(bool(enable))))
 
     def set_stage(self, mode: int):
-        """STAGE_GATHER (default), STAGE_BLOCK, STAGE_COLOUR or STAGE_SPLIT: how a fused stage sums the copies."""
+        """STAGE_AUTO (default), STAGE_GATHER, STAGE_BLOCK, STAGE_COLOUR or STAGE_SPLIT: how a fused stage sums the copies."""
         check(lib().numa_mesh_set_stage(self._h, mode))
 
     def profile(self, enable: bool):
