@@ -16,6 +16,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -67,6 +69,45 @@ def finish_bytes(nu, nl, n_wall, prec):
     contrib = 20 if prec == "mixed" else 40
     qs_nodes = nu if prec == "mixed" else n_wall
     return nu * (8 + 40 * 2.0 / 3.0 + 40) + qs_nodes * 40 + nl * contrib + n_wall * 24
+
+
+def split_layout(ne3, N):
+    """Node and contribution counts of the split DSS (NUMA_STAGE_SPLIT) on a
+    box of ne3 = (nx, ny, nz) elements: workgroups of EB consecutive elements
+    (EB = 256 // (N+1)^2); a run's first element (e % EB == 0 or ex == 0)
+    and an element whose east neighbour is in another run (e % EB == EB - 1 or
+    ex == nx - 1) write extra copies; the element kernel finishes the interior
+    rows of the other elements.  Returns (nodes finished by the element
+    kernel, face-row contribution values, run-boundary contribution values)."""
+    nx, ny, nz = ne3
+    ne = nx * ny * nz
+    EB = 256 // (N + 1) ** 2
+    e = np.arange(ne)
+    ex = e % nx
+    first = (e % EB == 0) | (ex == 0)
+    last = (e % EB == EB - 1) | (ex == nx - 1)
+    nip = (N - 1) ** 2
+    n_int = int((~first).sum()) * nip * N
+    fa = ne * 4 * N * N * 5
+    fb = (int(last.sum()) * (4 * N + nip) + int(first.sum()) * nip * N) * 5
+    return n_int, fa, fb
+
+
+def split_kernel_bytes(nu, n_wall, ne3, N, prec):
+    """Bytes of one launch of each split-DSS kernel (averaged over the 3
+    stages): the element kernel reads the state (5 x 8 B) and rho_bar, p_bar
+    (2 x 8 B) per unique node, writes the face-row and run-boundary
+    contributions, and finishes its nodes (M^-1, q^n in 2 of 3 stages, the new
+    state; the stage state too in mixed precision); the face kernel reads the
+    contributions back and finishes the rest (plus the stage state and normals
+    at the walls, the stage state everywhere in mixed precision)."""
+    n_int, fa, fb = split_layout(ne3, N)
+    w = 4 if prec == "mixed" else 8
+    upd = 8 + 40 * 2.0 / 3.0 + 40 + (40 if prec == "mixed" else 0)
+    el = nu * 56 + n_int * upd + (fa + fb) * w
+    n_face = nu - n_int
+    fin = n_face * upd + (0 if prec == "mixed" else n_wall * 40) + n_wall * 24 + (fa + fb) * w
+    return el, fin, 2 * (fa + fb) * w
 
 
 def stage_bytes(nu, ncol_nodes, prec):
@@ -441,8 +482,11 @@ def main():
             el_ms, el_n, fin_ms, fin_n = g.profile_read()
             g.profile(False)
             el_s, fin_s = el_ms / el_n * 1e-3, fin_ms / fin_n * 1e-3
-            ea = element_bytes(g.n_unique, g.n_local, name, metric)
-            fa = finish_bytes(g.n_unique, g.n_local, n_wall, name)
+            if metric == "recompute" and name == "fp64":  # NUMA_STAGE_AUTO: the split DSS in FP64
+                ea, fa, _ = split_kernel_bytes(g.n_unique, n_wall, mm["ne"], mm["N"], name)
+            else:
+                ea = element_bytes(g.n_unique, g.n_local, name, metric)
+                fa = finish_bytes(g.n_unique, g.n_local, n_wall, name)
             r["element_kernel"] = {"avg_launch_us": el_s * 1e6, "algorithmic_bytes": ea, "achieved_GBs": ea / el_s / 1e9}
             r["finish_kernel"] = {"avg_launch_us": fin_s * 1e6, "algorithmic_bytes": fa, "achieved_GBs": fa / fin_s / 1e9}
             _log("%s metric, %s: %.3f ms/step, %.3e updates/s; element %.1f us (%.0f GB/s), finish %.1f us (%.0f GB/s)"
@@ -484,12 +528,18 @@ def main():
         st_us = el["avg_launch_us"] + fin["avg_launch_us"]
         algo = stage_bytes(g.n_unique, ncol, prec)
         ach = algo / (st_us * 1e-6) / 1e9
-        return dict(kernel="fused SSP-RK3 stage: k_elem_col<4,%s> + k_fin_batch<4,4,%s> (recomputed metric, gather DSS)"
-                    % (("double",) * 2 if prec == "fp64" else ("float",) * 2),
-                    bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+        N = mm["N"]
+        if prec == "fp64":  # NUMA_STAGE_AUTO: the split DSS
+            kernel = ("fused SSP-RK3 stage: k_elem_col<%d,double,2> + k_fin_split<%d,double> (recomputed metric, "
+                      "split DSS)" % (N, N))
+            trip = split_kernel_bytes(g.n_unique, n_wall, mm["ne"], N, prec)[2]
+        else:
+            kernel = ("fused SSP-RK3 stage: k_elem_col<%d,float> + k_fin_batch<%d,%d,float> (recomputed metric, "
+                      "gather DSS)" % (N, N, 4))
+            trip = 2 * 20 * g.n_local
+        return dict(kernel=kernel, bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
                     algorithmic_bytes=algo, stage_us=st_us, copy_GBs=copy_GBs, copy_frac=ach / copy_GBs,
-                    contribution_round_trip_bytes=2 * (40 if prec == "fp64" else 20) * g.n_local,
-                    element_kernel=el, finish_kernel=fin)
+                    contribution_round_trip_bytes=trip, element_kernel=el, finish_kernel=fin)
 
     roofline = stage_roofline(head, "fp64")
     te, tf = load_traffic("element", workload), load_traffic("finish", workload)
@@ -500,10 +550,12 @@ def main():
     _log("stage: %.1f us, %.0f GB/s algorithmic = %.3f of 8 TB/s, %.3f of the copy rate"
          % (roofline["stage_us"], roofline["achieved"], roofline["frac"], roofline["copy_frac"]))
 
-    # the three DSS schedules of a stage on the same mesh (numa_mesh_set_stage)
+    # the DSS schedules of a stage on the same mesh (numa_mesh_set_stage; the
+    # default NUMA_STAGE_AUTO is the split one in FP64, the gather in mixed)
     g.set_metric(numa.METRIC_RECOMPUTE)
     modes = {}
-    for mode, mname in ((numa.STAGE_BLOCK, "block"), (numa.STAGE_COLOUR, "colour")):
+    for mode, mname in ((numa.STAGE_GATHER, "gather"), (numa.STAGE_SPLIT, "split"), (numa.STAGE_BLOCK, "block"),
+                        (numa.STAGE_COLOUR, "colour")):
         g.set_stage(mode)
         modes[mname] = {}
         for prec, name in ((numa.PREC_FP64, "fp64"), (numa.PREC_MIXED, "mixed")):
@@ -512,8 +564,7 @@ def main():
             gpu_s, wall_s = timed_steps(prec)
             modes[mname][name] = {"ms_per_step": 1e3 * wall_s / args.steps}
         _log("stage mode %s: %s" % (mname, {k: "%.3f ms" % v["ms_per_step"] for k, v in modes[mname].items()}))
-    g.set_stage(numa.STAGE_GATHER)
-    modes["gather"] = {k: {"ms_per_step": v["ms_per_step"]} for k, v in recomp.items() if k in ("fp64", "mixed")}
+    g.set_stage(numa.STAGE_AUTO)
 
     # accuracy: FP64 and mixed states after 1 and after the oracle's steps
     # (100 unless the CPU budget stopped it earlier)
