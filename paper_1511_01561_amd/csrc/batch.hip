@@ -245,6 +245,148 @@ __device__ __forceinline__ int split_slot_east(int j, int k)
 }
 template <int N> constexpr int split_nb() { return 4 * N + (N - 1) * (N - 1) * (N + 1); }
 
+// what the split-DSS output of a column workgroup needs of its box item
+struct SplitGeo {
+    int nx, ny, nz, ni, nj, nu;
+    FastDiv fx, fy;
+};
+
+// the run-interior nodes a lane of a column workgroup (EB elements, BT
+// lanes) finishes: interior pair ip, element qq, local ii, not in the run's
+// first element, whose west neighbour is not in the workgroup; I = -1 where
+// the lane has no node in that pass
+template <int N, int EB, int BT>
+struct SplitPre {
+    static constexpr int NIN = (N - 1) * (N - 1) * EB * N, SPL = NIN > 0 ? (NIN + BT - 1) / BT : 1;
+    int32_t I[SPL];
+    double m[SPL], qn[SPL][5];
+};
+
+// the lane's run-interior nodes and their M^-1 and q^n (loaded at the start
+// of the kernel, used at its end)
+template <int N, int EB, int BT>
+__device__ __forceinline__ void split_prefetch(const BatchItem &it, const SplitGeo &gm, bool load_qn, int t, int e0,
+                                               int new_, SplitPre<N, EB, BT> &pf)
+{
+    using S = SplitPre<N, EB, BT>;
+#pragma unroll
+    for (int p = 0; p < S::SPL; ++p) {
+        pf.I[p] = -1;
+        pf.m[p] = 0.0;
+#pragma unroll
+        for (int v = 0; v < 5; ++v) pf.qn[p][v] = 0.0;
+    }
+    if constexpr (S::NIN > 0) {
+#pragma unroll
+        for (int p = 0; p < S::SPL; ++p) {
+            const int n = t + p * BT;
+            if (n >= S::NIN) continue;
+            const int ip = n / (EB * N), m = n - ip * (EB * N), qq = m / N, ii = m - qq * N;
+            if (qq >= new_) continue;
+            const BoxElem fe = box_elem((uint32_t)(e0 + qq), gm.fx, gm.fy);
+            if (qq == 0 || fe.ex == 0) continue;  // a run's first element: the finish kernel takes it
+            const int jj = 1 + ip % (N - 1), kk = 1 + ip / (N - 1);
+            pf.I[p] = fe.ex * N + ii + gm.ni * (fe.ey * N + jj + gm.nj * (fe.ez * N + kk));
+            pf.m[p] = it.Minv[pf.I[p]];
+            if (load_qn)
+#pragma unroll
+                for (int v = 0; v < 5; ++v) pf.qn[p][v] = it.qn[pf.I[p] + v * gm.nu];
+        }
+    }
+}
+
+// the copies the finish kernel takes, straight from the lane's registers
+// (res[k][v] of its column (i, j) in element q): the east face of an element
+// whose east neighbour is not in the run, the interior rows of a run's first
+// element
+template <int N, typename T, int EB>
+__device__ __forceinline__ void split_store_fb(const BatchItem &it, const SplitGeo &gm, int e0, int q, int i, int j,
+                                               int exl, const T (*res)[5])
+{
+    constexpr int P = N + 1, NFP = 4 * N, NIP = (N - 1) * (N - 1), NB = split_nb<N>();
+    const int64_t vs = (int64_t)gm.nz * gm.ny * NFP * gm.ni;
+    T *Fb = (T *)it.ev + 5 * vs;
+    const int64_t eb = (int64_t)(e0 + q) * NB;
+    if (i == N && (q == EB - 1 || exl == gm.nx - 1)) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int64_t o = (eb + split_slot_east<N>(j, k)) * 5;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) Fb[o + v] = res[k][v];
+        }
+    }
+    if (NIP > 0 && i < N && (q == 0 || exl == 0) && j > 0 && j < N) {
+#pragma unroll
+        for (int k = 1; k < N; ++k) {
+            const int64_t o = (eb + NFP + NIP + ((j - 1) + (N - 1) * (k - 1)) * N + i) * 5;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) Fb[o + v] = res[k][v];
+        }
+    }
+}
+
+// after the contributions of the workgroup are in st ([q][l][5], synchronised):
+// the face rows (Fa, the run's x pairs added) and the run-interior nodes
+// (M^-1, the update sc, folded or not, the state)
+template <int N, typename T, int EB, int BT>
+__device__ __forceinline__ void split_store(const BatchItem &it, const SplitGeo &gm, const StageCoef &sc, bool fold,
+                                            const T *st, int t, int e0, int new_, const SplitPre<N, EB, BT> &pf)
+{
+    constexpr int P = N + 1, NP = P * P * P, NFP = 4 * N;
+    using S = SplitPre<N, EB, BT>;
+    T *Fa = (T *)it.ev;
+    // Fa: lane u < EB N 5 takes value v of node (qq, ii) of every face pair,
+    // so that each store instruction writes one contiguous run of the pair's
+    // row, and the lane's element, pair flag and offsets are formed once
+    constexpr int RUN = EB * N * 5;  // values of one face pair of the workgroup
+    for (int u = t; u < RUN; u += BT) {
+        const int nd = u / 5, v = u - nd * 5, qq = nd / N, ii = nd - qq * N;
+        if (qq < new_) {
+            const BoxElem fe = box_elem((uint32_t)(e0 + qq), gm.fx, gm.fy);
+            const bool pair = ii == 0 && qq > 0 && fe.ex != 0;
+            const T *s0 = st + (qq * NP + ii) * 5 + v, *s1 = st + ((qq - 1) * NP + N) * 5 + v;
+            T *fo = Fa + (((int64_t)(fe.ez * gm.ny + fe.ey) * NFP) * gm.ni + fe.ex * N + ii) * 5 + v;
+#pragma unroll
+            for (int fp = 0; fp < NFP; ++fp) {
+                int jj, kk;
+                split_fp_jk<N>(fp, jj, kk);
+                const int lo = P * (jj + P * kk) * 5;
+                T val = s0[lo];
+                if (pair) val += s1[lo];
+                fo[(int64_t)fp * gm.ni * 5] = val;
+            }
+        }
+    }
+    if constexpr (S::NIN > 0) {
+#pragma unroll
+        for (int p = 0; p < S::SPL; ++p) {
+            if (pf.I[p] < 0) continue;
+            const int n = t + p * BT;
+            const int ip = n / (EB * N), m = n - ip * (EB * N), qq = m / N, ii = m - qq * N;
+            const int jj = 1 + ip % (N - 1), kk = 1 + ip / (N - 1);
+            const int l = ii + P * (jj + P * kk), lw = N + P * (jj + P * kk);
+            double r[5], o[5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                r[v] = (double)st[(qq * NP + l) * 5 + v];
+                if (ii == 0) r[v] += (double)st[((qq - 1) * NP + lw) * 5 + v];
+                r[v] *= pf.m[p];
+            }
+            if (fold) {
+#pragma unroll
+                for (int v = 0; v < 5; ++v) o[v] = rk_update_folded(sc, pf.qn[p][v], r[v]);
+            } else {
+#pragma unroll
+                for (int v = 0; v < 5; ++v)
+                    o[v] = rk_update(sc, pf.qn[p][v], sc.b == 0.0 ? 0.0 : it.qs[pf.I[p] + v * gm.nu], r[v]);
+            }
+#pragma unroll
+            for (int v = 0; v < 5; ++v) it.qout[pf.I[p] + v * gm.nu] = o[v];
+            flag_nonfinite(it.flag, o, 5);
+        }
+    }
+}
+
 // MODE 0: write J w R node-major for the finish kernel (NUMA_STAGE_GATHER);
 // MODE 1: one colour pass of NUMA_STAGE_COLOUR: the workgroup's elements are
 // the elements of colour `colour` (parity of ex, ey, ez), EB consecutive ones
@@ -271,38 +413,11 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
     double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
     int ez = 0, base = 0, exl = 0;
     const int layer = a.ni * a.nj;
-    // MODE 2: the run-interior nodes this lane finishes (interior pair ip,
-    // element qq, local ii; not in the run's first element, whose west
-    // neighbour is not in the workgroup); their M^-1 and reference state
-    // are loaded now, used at the end
-    constexpr int NIN = (N - 1) * (N - 1) * EB * N, SPL = MODE == 2 && NIN > 0 ? (NIN + BT - 1) / BT : 1;
+    // MODE 2: the run-interior nodes this lane finishes, their M^-1 and q^n
     const int new_ = it.ne - e0 < EB ? it.ne - e0 : EB;
-    int32_t fI[SPL];
-    double fm[SPL], fq[SPL][5];
-#pragma unroll
-    for (int p = 0; p < SPL; ++p) {
-        fI[p] = -1;
-        fm[p] = 0.0;
-#pragma unroll
-        for (int v = 0; v < 5; ++v) fq[p][v] = 0.0;
-    }
-    if constexpr (MODE == 2 && NIN > 0) {
-#pragma unroll
-        for (int p = 0; p < SPL; ++p) {
-            const int n = t + p * BT;
-            if (n >= NIN) continue;
-            const int ip = n / (EB * N), m = n - ip * (EB * N), qq = m / N, ii = m - qq * N;
-            if (qq >= new_) continue;
-            const BoxElem fe = box_elem((uint32_t)(e0 + qq), a.fx, a.fy);
-            if (qq == 0 || fe.ex == 0) continue;  // a run's first element: the finish kernel takes it
-            const int jj = 1 + ip % (N - 1), kk = 1 + ip / (N - 1);
-            fI[p] = fe.ex * N + ii + a.ni * (fe.ey * N + jj + a.nj * (fe.ez * N + kk));
-            fm[p] = it.Minv[fI[p]];
-            if (B.ca != 0.0)
-#pragma unroll
-                for (int v = 0; v < 5; ++v) fq[p][v] = it.qn[fI[p] + v * a.nu];
-        }
-    }
+    const SplitGeo gm{a.nx, a.ny, a.nz, a.ni, a.nj, (int)a.nu, a.fx, a.fy};
+    SplitPre<N, EB, BT> pf;
+    if constexpr (MODE == 2) split_prefetch<N, EB, BT>(it, gm, B.ca != 0.0, t, e0, new_, pf);
     if (act) {
         BoxElem be;
         if constexpr (MODE == 1) {
@@ -436,31 +551,7 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
         return;  // every lane: no barrier follows
     }
     if constexpr (MODE == 2) {
-        // the copies the finish kernel takes go to Fb straight from the
-        // registers: the east face of an element whose east neighbour is not
-        // in the run, the interior rows of a run's first element
-        constexpr int NFP = 4 * N, NIP = (N - 1) * (N - 1), NB = split_nb<N>();
-        const int64_t vs = (int64_t)a.nz * a.ny * NFP * a.ni;
-        T *Fb = (T *)it.ev + 5 * vs;
-        if (act) {
-            const int64_t eb = (int64_t)(e0 + q) * NB;
-            if (i == N && (q == EB - 1 || exl == a.nx - 1)) {
-#pragma unroll
-                for (int k = 0; k < P; ++k) {
-                    const int64_t o = (eb + split_slot_east<N>(j, k)) * 5;
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) Fb[o + v] = res[k][v];
-                }
-            }
-            if (NIP > 0 && i < N && (q == 0 || exl == 0) && j > 0 && j < N) {
-#pragma unroll
-                for (int k = 1; k < N; ++k) {
-                    const int64_t o = (eb + NFP + NIP + ((j - 1) + (N - 1) * (k - 1)) * N + i) * 5;
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) Fb[o + v] = res[k][v];
-                }
-            }
-        }
+        if (act) split_store_fb<N, T, EB>(it, gm, e0, q, i, j, exl, res);
     }
     __syncthreads();  // tiles read
     T *st = &s[0][0][0];
@@ -472,62 +563,7 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
     }
     __syncthreads();
     if constexpr (MODE == 2) {
-        constexpr int NFP = 4 * N, NIP = (N - 1) * (N - 1);
-        T *Fa = (T *)it.ev;
-        // Fa: the face pairs at i < N, the run's x pairs added (element qq's
-        // i = 0 copy plus element qq - 1's i = N copy).  Lane u < EB N 5 takes
-        // value v of node (qq, ii) of every face pair, so that each store
-        // instruction writes one contiguous run of the pair's row, and the
-        // lane's element, pair flag and offsets are formed once.
-        constexpr int RUN = EB * N * 5;  // values of one face pair of the workgroup
-        for (int u = t; u < RUN; u += BT) {
-            const int nd = u / 5, v = u - nd * 5, qq = nd / N, ii = nd - qq * N;
-            if (qq < new_) {
-                const BoxElem fe = box_elem((uint32_t)(e0 + qq), a.fx, a.fy);
-                const bool pair = ii == 0 && qq > 0 && fe.ex != 0;
-                const T *s0 = st + (qq * NP + ii) * 5 + v, *s1 = st + ((qq - 1) * NP + N) * 5 + v;
-                T *fo = Fa + (((int64_t)(fe.ez * a.ny + fe.ey) * NFP) * a.ni + fe.ex * N + ii) * 5 + v;
-#pragma unroll
-                for (int fp = 0; fp < NFP; ++fp) {
-                    int jj, kk;
-                    split_fp_jk<N>(fp, jj, kk);
-                    const int lo = P * (jj + P * kk) * 5;
-                    T val = s0[lo];
-                    if (pair) val += s1[lo];
-                    fo[(int64_t)fp * a.ni * 5] = val;
-                }
-            }
-        }
-        // the run-interior nodes: M^-1, the stage update, the state
-        if constexpr (NIN > 0) {
-            const StageCoef sc{B.ca, B.cb, it.cdt};
-#pragma unroll
-            for (int p = 0; p < SPL; ++p) {
-                if (fI[p] < 0) continue;
-                const int n = t + p * BT;
-                const int ip = n / (EB * N), m = n - ip * (EB * N), qq = m / N, ii = m - qq * N;
-                const int jj = 1 + ip % (N - 1), kk = 1 + ip / (N - 1);
-                const int l = ii + P * (jj + P * kk), lw = N + P * (jj + P * kk);
-                double r[5], o[5];
-#pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    r[v] = (double)st[(qq * NP + l) * 5 + v];
-                    if (ii == 0) r[v] += (double)st[((qq - 1) * NP + lw) * 5 + v];
-                    r[v] *= fm[p];
-                }
-                if (F64 && B.fold) {
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) o[v] = rk_update_folded(sc, fq[p][v], r[v]);
-                } else {
-#pragma unroll
-                    for (int v = 0; v < 5; ++v)
-                        o[v] = rk_update(sc, fq[p][v], sc.b == 0.0 ? 0.0 : it.qs[fI[p] + v * a.nu], r[v]);
-                }
-#pragma unroll
-                for (int v = 0; v < 5; ++v) it.qout[fI[p] + v * a.nu] = o[v];
-                flag_nonfinite(it.flag, o, 5);
-            }
-        }
+        split_store<N, T, EB, BT>(it, gm, StageCoef{B.ca, B.cb, it.cdt}, F64 && B.fold, st, t, e0, new_, pf);
         return;
     }
     // the workgroup's elements are consecutive: one contiguous run
@@ -547,8 +583,9 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
 // e = r nx that are not multiples of EB.  Every node's
 // copies are read in a fixed order (z copies, y copies, then the x copies of
 // each), summed in FP64, multiplied by M^-1, projected at the walls and
-// advanced by the stage update.
-template <int N, typename T>
+// advanced by the stage update (PLAIN: the summed value itself, for the
+// filter: the stage operands are not read).
+template <int N, typename T, bool PLAIN = false>
 __global__ __launch_bounds__(256) void k_fin_split(Batch B)
 {
     constexpr int NFP = 4 * N, NIP = (N - 1) * (N - 1), NB = split_nb<N>(), EB = col_eb<N, T>();
@@ -561,8 +598,8 @@ __global__ __launch_bounds__(256) void k_fin_split(Batch B)
     int lb = g - it.boff;
     const int nbb = NIP == 0 ? 0 : (((it.ne + EB - 1) / EB + ny * nz) * NIP * N + 255) / 256;
     bool runstart = false;
-    if (nbb > 0) {
-        const int S = (it.mblk + nbb) / nbb;
+    if (NIP > 0 && nbb > 0) {
+        const int S = (it.mblk + nbb) / (NIP > 0 ? nbb : 1);
         if (lb < nbb * S) {
             const int k = lb / S;
             runstart = lb - k * S == S - 1;
@@ -583,12 +620,12 @@ __global__ __launch_bounds__(256) void k_fin_split(Batch B)
     bool folded;
     auto update_loads = [&]() {
         I = gi + ni * (gj + nj * gk);
-        folded = B.fold && !(it.walls && (gk == 0 || gk == nz * N));
+        folded = !PLAIN && B.fold && !(it.walls && (gk == 0 || gk == nz * N));
         mi = it.Minv[I];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
-            qnv[v] = sc.a == 0.0 ? 0.0 : it.qn[I + v * it.nu];
-            qsv[v] = folded || sc.b == 0.0 ? 0.0 : it.qs[I + v * it.nu];
+            qnv[v] = PLAIN || sc.a == 0.0 ? 0.0 : it.qn[I + v * it.nu];
+            qsv[v] = PLAIN || folded || sc.b == 0.0 ? 0.0 : it.qs[I + v * it.nu];
         }
     };
     if (!runstart) {
@@ -909,6 +946,109 @@ __global__ __launch_bounds__((col_threads<N, T>())) void k_elem_stream(Batch B)
     store_run<T>(out, st, ne * NP * 5, t, BT);
 }
 
+// The Boyd-Vandeven filter of a box with the recomputed metric through the
+// split DSS: the column workgroup of the stage (EB consecutive elements, a lane
+// per (i, j) column) gathers the state into an LDS tile, applies F along xi
+// and eta through the tile and along zeta in the lane's registers (the same
+// fma chains in the same direction order as k_filter), weights by J w and
+// hands J w (F q) to the split DSS: the run-interior nodes are finished here
+// (M^-1, no stage update), the others by k_fin_split.  The state is filtered
+// in place: the nodes finished here are read by no other workgroup, and the
+// face kernel reads only the contributions.
+struct FilterSplit {
+    BatchItem it;             // qs: the state read, qout: the state written (the same array)
+    double w[kMaxP];          // GLL weights
+    double F[kMaxP * kMaxP];  // 1D nodal filter matrix F[i * (N+1) + m]
+};
+
+template <int N>
+__global__ __launch_bounds__((col_threads<N, double>())) void k_filter_col(FilterSplit A)
+{
+    constexpr int P = N + 1, PP = P * P, NP = PP * P, EB = col_eb<N, double>(), BT = col_threads<N, double>();
+    __shared__ double s[EB][5][NP];
+    __shared__ double Fs[PP];
+    const BatchItem &it = A.it;
+    const int e0 = (int)xcd_remap(blockIdx.x, gridDim.x) * EB;
+    const int t = threadIdx.x, q = t / PP, c = t % PP, i = c % P, j = c / P;
+    const bool act = q < EB && e0 + q < it.ne;
+    if (t < PP) Fs[t] = A.F[t];
+    const int new_ = it.ne - e0 < EB ? it.ne - e0 : EB;
+    const SplitGeo gm{(int)it.fx.d, (int)it.fy.d, it.nz, it.ni, it.nj, it.nu, it.fx, it.fy};
+    SplitPre<N, EB, BT> pf;
+    split_prefetch<N, EB, BT>(it, gm, false, t, e0, new_, pf);
+    double jw[P];
+    int exl = 0;
+    if (act) {
+        const BoxElem be = box_elem((uint32_t)(e0 + q), it.fx, it.fy);
+        exl = be.ex;
+        const double c0 = it.hcol[(int64_t)(be.ex + gm.nx * be.ey) * (4 * PP) + c];
+        int gi = be.ex * N + i, gj = be.ey * N + j;
+        if (gi == gm.ni) gi = 0;
+        if (gj == gm.nj) gj = 0;
+        const int base = gi + gm.ni * gj, layer = gm.ni * gm.nj;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            int gk = be.ez * N + k;
+            if (gk == it.nkw) gk = 0;
+            const int32_t I = base + layer * gk;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) s[q][v][c + PP * k] = it.qs[I + v * gm.nu];
+            jw[k] = c0 * A.w[k];
+        }
+    }
+    __syncthreads();
+    double x[5][P];
+    if (act) {  // xi
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                double r = 0.0;
+#pragma unroll
+                for (int m = 0; m < P; ++m) r = fma(Fs[i * P + m], s[q][v][m + P * (j + P * k)], r);
+                x[v][k] = r;
+            }
+    }
+    __syncthreads();
+    if (act)
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) s[q][v][c + PP * k] = x[v][k];
+    __syncthreads();
+    double res[P][5];
+    if (act) {  // eta through the tile, zeta in registers, times J w
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                double r = 0.0;
+#pragma unroll
+                for (int m = 0; m < P; ++m) r = fma(Fs[j * P + m], s[q][v][i + P * (m + P * k)], r);
+                x[v][k] = r;
+            }
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) {
+                double r = 0.0;
+#pragma unroll
+                for (int m = 0; m < P; ++m) r = fma(Fs[k * P + m], x[v][m], r);
+                res[k][v] = jw[k] * r;
+            }
+        split_store_fb<N, double, EB>(it, gm, e0, q, i, j, exl, res);
+    }
+    __syncthreads();  // tile read
+    double *st = &s[0][0][0];
+    if (act)
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) st[(q * NP + c + PP * k) * 5 + v] = res[k][v];
+    __syncthreads();
+    split_store<N, double, EB, BT>(it, gm, StageCoef{0.0, 0.0, 1.0}, false, st, t, e0, new_, pf);
+}
+
 template <int N, int SEG, typename T, bool PLAIN = false>
 __global__ void k_fin_batch(Batch B)
 {
@@ -945,6 +1085,20 @@ __global__ void k_fin_batch(Batch B)
     box_finish_node<N, SEG, T, PLAIN>(p, b, (const T *)it.ev, sx, ey, kbase == 0 ? (int)ez : it.nz - 1, threadIdx.x,
                                       kbase, klayers, StageCoef{B.ca, B.cb, it.cdt}, it.qn, it.qs, it.qout,
                                       PLAIN ? nullptr : it.flag);
+}
+
+// the fields of a batch item that the split finish (k_fin_split) reads, for
+// the column workgroups of EB elements; returns the item's finish blocks
+int64_t split_item(const Mesh &m, int eb, BatchItem &it)
+{
+    const int N = m.N, ny = m.d.ne[1], nz = m.d.ne[2];
+    const int64_t rl = m.nj + (int64_t)(N - 1) * ny;
+    const int64_t rows = nz * rl + (m.walls ? m.nj : 0);
+    const int64_t nwg = (m.ne + eb - 1) / eb;
+    it.fseg = fast_div((uint32_t)m.ni);
+    it.frl = fast_div((uint32_t)rl);
+    it.mblk = (int)((rows * m.ni + 255) / 256);
+    return it.mblk + ((nwg + (int64_t)ny * nz) * ((int64_t)(N - 1) * (N - 1) * N) + 255) / 256;
 }
 
 template <int N, typename T, int SEG>
@@ -1016,17 +1170,8 @@ int32_t run_chunk_seg(const StepItem *items, int n, int phase, hipStream_t s, in
             eo += (it.ne + eb - 1) / eb * eb;
             bo += (m.nu + 255) / 256;
         } else if (split) {  // face rows, 256 lattice points per block, then the run starts
-            const int nx = m.d.ne[0], ny = m.d.ne[1], nz = m.d.ne[2];
-            const int64_t rl = m.nj + (int64_t)(N - 1) * ny;
-            const int64_t rows = nz * rl + (m.walls ? m.nj : 0);
-            const int64_t nwg = (m.ne + eb - 1) / eb;
-            const int64_t nip = (int64_t)(N - 1) * (N - 1) * N;  // run-start lanes per candidate
-            it.fseg = fast_div((uint32_t)m.ni);
-            it.frl = fast_div((uint32_t)rl);
-            it.mblk = (int)((rows * m.ni + 255) / 256);
-            eo += nwg * eb;
-            bo += it.mblk + ((nwg + (int64_t)ny * nz) * nip + 255) / 256;
-            (void)nx;
+            eo += (m.ne + eb - 1) / eb * eb;
+            bo += split_item(m, eb, it);
         } else {
             eo += (m.ne + eb - 1) / eb * eb;
             bo += mblk + (m.walls ? (int64_t)(m.d.ne[0] / SEG) * m.d.ne[1] : 0);
@@ -1209,6 +1354,72 @@ int32_t launch_box_plain_finish(const Mesh &m, const double *ev, double *q, hipS
     case 6: return run_plain_finish<6>(m, ev, q, s);
     case 7: return run_plain_finish<7>(m, ev, q, s);
     default: return run_plain_finish<8>(m, ev, q, s);
+    }
+}
+
+namespace {
+
+template <int N>
+int32_t run_filter_split(const Mesh &m, const double *F, double *q, hipStream_t s)
+{
+    constexpr int EB = col_eb<N, double>();
+    FilterSplit A{};
+    BatchItem &it = A.it;
+    it.qs = q;
+    it.qout = q;
+    it.qn = nullptr;
+    it.Minv = stage_minv(m);
+    it.nrm = m.dv.nrm;
+    it.ev = m.dv.ev64;
+    it.hcol = m.dv.hcol;
+    it.flag = nullptr;
+    it.nu = (int)m.nu;
+    it.nh = (int)m.nh;
+    it.ni = (int)m.ni;
+    it.nj = (int)m.nj;
+    it.nkw = m.d.periodic[2] ? (int)m.nk : -1;
+    it.nz = m.d.ne[2];
+    it.walls = m.walls ? 1 : 0;
+    it.ne = (int)m.ne;
+    it.fx = fast_div((uint32_t)m.d.ne[0]);
+    it.fy = fast_div((uint32_t)m.d.ne[1]);
+    it.cdt = 1.0;
+    it.eoff = 0;
+    it.boff = 0;
+    const int64_t bo = split_item(m, EB, it);
+    for (int k = 0; k <= N; ++k) A.w[k] = m.w[k];
+    for (int k = 0; k < (N + 1) * (N + 1); ++k) A.F[k] = F[k];
+    hipLaunchKernelGGL((k_filter_col<N>), dim3((unsigned)((m.ne + EB - 1) / EB)), dim3(col_threads<N, double>()), 0, s,
+                       A);
+    // the face nodes: the split finish with the identity update (a = b = 0, cdt = 1)
+    Batch B{};
+    B.n = 1;
+    B.fold = 0;
+    B.ca = 0.0;
+    B.cb = 0.0;
+    B.it[0] = it;
+    hipLaunchKernelGGL((k_fin_split<N, double, true>), dim3((unsigned)bo), dim3(256), 0, s, B);
+    NUMA_HIP(hipGetLastError());
+    return NUMA_OK;
+}
+
+}  // namespace
+
+bool filter_split_ok(const Mesh &m)
+{
+    return split_ok(m, NUMA_PREC_FP64);
+}
+
+int32_t launch_filter_split(const Mesh &m, const double *F, double *q, hipStream_t s)
+{
+    switch (m.N) {
+    case 1: return run_filter_split<1>(m, F, q, s);
+    case 2: return run_filter_split<2>(m, F, q, s);
+    case 3: return run_filter_split<3>(m, F, q, s);
+    case 4: return run_filter_split<4>(m, F, q, s);
+    default:
+        set_error("filter: the split DSS takes N <= 4");
+        return NUMA_EUNSUPPORTED;
     }
 }
 

@@ -236,6 +236,7 @@ int32_t launch_filter(Mesh &m, double order, int32_t cutoff, double *q, hipStrea
     }
     for (int k = 0; k < m.P; ++k) a.w[k] = m.w[k];
     filter_matrix(m.N, m.xi, m.w, order, cutoff, a.F);
+    if (!shell && filter_split_ok(m)) return launch_filter_split(m, a.F, q, s);
     const int geo = shell ? kGeoStored : (m.metric_mode == NUMA_METRIC_RECOMPUTE ? kGeoBoxCol : kGeoBox);
     // the box (x extent a multiple of the finish segment) and the shell sum
     // node-major contributions with their stage finish kernels; other boxes

@@ -172,6 +172,10 @@ int32_t launch_dss(Mesh &m, int32_t nvar, const double *cin, double *out, int32_
 void filter_sigma(int N, double order, int32_t cutoff, double *sigma);
 void filter_matrix(int N, const double *xi, const double *w, double order, int32_t cutoff, double *F);
 int32_t launch_filter(Mesh &m, double order, int32_t cutoff, double *q, hipStream_t s);
+// the filter of a box whose FP64 stages take the split DSS, through the same
+// DSS (column element kernel, face finish); F: the 1D nodal filter matrix
+bool filter_split_ok(const Mesh &m);
+int32_t launch_filter_split(const Mesh &m, const double *F, double *q, hipStream_t s);
 int32_t launch_box_plain_finish(const Mesh &m, const double *ev, double *q, hipStream_t s);
 int32_t launch_shell_plain_finish(Mesh &m, const double *ev, double *q, hipStream_t s);
 uint64_t imex_lds_bytes(const Mesh &m);
