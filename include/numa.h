@@ -276,8 +276,11 @@ int32_t numa_dss(numa_mesh_t m, int32_t nvar, const double *c_elem, double *out,
  * (1/2 at t = 1/2, 0 for the top mode N); cutoff >= N leaves every element
  * unchanged.  filter_order must be finite and > 0, cutoff >= 0 (NUMA_EINVAL
  * otherwise).  The state is the perturbation state (rho', u, v, w, theta'), so
- * the hydrostatic reference is not filtered.  Uses the mesh's contribution
- * scratch, like numa_step: calls on one mesh on different streams race. */
+ * the hydrostatic reference is not filtered.  On a box whose FP64 stages take
+ * the split DSS (numa_mesh_set_stage) the filter takes it too (the same
+ * contributions, their copies summed in that schedule's order).  Uses the
+ * mesh's contribution scratch, like numa_step: calls on one mesh on different
+ * streams race. */
 int32_t numa_filter(numa_mesh_t m, double filter_order, int32_t cutoff, double *q, void *stream);
 
 /* The 1D filter matrix of numa_filter for GLL order `order` (1..8):
@@ -303,7 +306,10 @@ int32_t numa_rk_stage(numa_mesh_t m, int32_t stage, double dt, const double *qn,
  * element kernel writes every element-local node's contribution J w R
  * (node-major: a copy's five values together); the finish kernel sums the
  * copies of each unique node, applies M^-1, the wall projection and the
- * update.  In FP64 (box and shell; not the generic box path, nor the box at
+ * update (the mesh's DSS schedule, numa_mesh_set_stage: by default in FP64
+ * on the box the element kernel already sums the copies inside its run of
+ * elements and finishes those nodes, and writes only the others' copies for
+ * the finish kernel).  In FP64 (box and shell; not the generic box path, nor the box at
  * N = 5, 6 with the recomputed metric) the contribution
  * away from the walls is J w (q_s + c dt R), so that the finish need not read
  * q_s there; with the recomputed metric M is then the sum of the recomputed
