@@ -184,7 +184,7 @@ constexpr int col_threads() { return ((col_eb<N, T>() * (N + 1) * (N + 1) + 63) 
 // workgroups per CU the column kernel is compiled for: in FP32 at N = 4 the
 // tile (40 KB) lets four share a CU if the registers fit 4 waves per SIMD
 template <int N, typename T, int MODE = 0>
-constexpr int col_blocks() { return (sizeof(T) == 4 && N == 4) ? (MODE == 2 ? 3 : 4) : 1; }
+constexpr int col_blocks() { return (sizeof(T) == 4 && N == 4) ? (MODE == 2 ? 2 : 4) : 1; }
 
 // NUMA_STAGE_SPLIT: the DSS split between the element kernel and a finish
 // kernel over the element faces.  The EB elements of a column workgroup are
@@ -295,46 +295,46 @@ __device__ __forceinline__ void split_prefetch(const BatchItem &it, const SplitG
     }
 }
 
-// the copies the finish kernel takes, straight from the lane's registers
-// (res[k][v] of its column (i, j) in element q): the east face of an element
-// whose east neighbour is not in the run, the interior rows of a run's first
-// element
-template <int N, typename T, int EB>
-__device__ __forceinline__ void split_store_fb(const BatchItem &it, const SplitGeo &gm, int e0, int q, int i, int j,
-                                               int exl, const T (*res)[5])
-{
-    constexpr int P = N + 1, NFP = 4 * N, NIP = (N - 1) * (N - 1), NB = split_nb<N>();
-    const int64_t vs = (int64_t)gm.nz * gm.ny * NFP * gm.ni;
-    T *Fb = (T *)it.ev + 5 * vs;
-    const int64_t eb = (int64_t)(e0 + q) * NB;
-    if (i == N && (q == EB - 1 || exl == gm.nx - 1)) {
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            const int64_t o = (eb + split_slot_east<N>(j, k)) * 5;
-#pragma unroll
-            for (int v = 0; v < 5; ++v) Fb[o + v] = res[k][v];
-        }
-    }
-    if (NIP > 0 && i < N && (q == 0 || exl == 0) && j > 0 && j < N) {
-#pragma unroll
-        for (int k = 1; k < N; ++k) {
-            const int64_t o = (eb + NFP + NIP + ((j - 1) + (N - 1) * (k - 1)) * N + i) * 5;
-#pragma unroll
-            for (int v = 0; v < 5; ++v) Fb[o + v] = res[k][v];
-        }
-    }
-}
-
 // after the contributions of the workgroup are in st ([q][l][5], synchronised):
-// the face rows (Fa, the run's x pairs added) and the run-interior nodes
-// (M^-1, the update sc, folded or not, the state)
+// the copies the finish kernel takes at run boundaries (Fb), the face rows
+// (Fa, the run's x pairs added) and the run-interior nodes (M^-1, the update
+// sc, folded or not, the state)
 template <int N, typename T, int EB, int BT>
 __device__ __forceinline__ void split_store(const BatchItem &it, const SplitGeo &gm, const StageCoef &sc, bool fold,
                                             const T *st, int t, int e0, int new_, const SplitPre<N, EB, BT> &pf)
 {
-    constexpr int P = N + 1, NP = P * P * P, NFP = 4 * N;
+    constexpr int P = N + 1, NP = P * P * P, NFP = 4 * N, NIP = (N - 1) * (N - 1), NB = split_nb<N>();
     using S = SplitPre<N, EB, BT>;
     T *Fa = (T *)it.ev;
+    // Fb: the east face (slot order: face pairs, then interior pairs) of an
+    // element whose east neighbour is not in the run, the interior rows of a
+    // run's first element (ip, then i)
+    T *Fb = Fa + 5 * (int64_t)gm.nz * gm.ny * NFP * gm.ni;
+    int ex = box_elem((uint32_t)e0, gm.fx, gm.fy).ex;  // x index of element qq, stepped along the run
+    for (int qq = 0; qq < new_; ++qq, ex = ex + 1 == gm.nx ? 0 : ex + 1) {
+        if (!(qq == EB - 1 || ex == gm.nx - 1 || qq == 0 || ex == 0)) continue;
+        T *fb = Fb + (int64_t)(e0 + qq) * NB * 5;
+        if (qq == EB - 1 || ex == gm.nx - 1) {
+            for (int u = t; u < (NFP + NIP) * 5; u += BT) {
+                const int slot = u / 5, v = u - slot * 5;
+                int jj, kk;
+                if (slot < NFP) {
+                    split_fp_jk<N>(slot, jj, kk);
+                } else {
+                    jj = 1 + (slot - NFP) % (N - 1);
+                    kk = 1 + (slot - NFP) / (N - 1);
+                }
+                fb[u] = st[(qq * NP + N + P * (jj + P * kk)) * 5 + v];
+            }
+        }
+        if (NIP > 0 && (qq == 0 || ex == 0)) {
+            for (int u = t; u < NIP * N * 5; u += BT) {
+                const int nd = u / 5, v = u - nd * 5, ip = nd / N, ii = nd - ip * N;
+                const int jj = 1 + ip % (N - 1), kk = 1 + ip / (N - 1);
+                fb[(NFP + NIP) * 5 + u] = st[(qq * NP + ii + P * (jj + P * kk)) * 5 + v];
+            }
+        }
+    }
     // Fa: lane u < EB N 5 takes value v of node (qq, ii) of every face pair,
     // so that each store instruction writes one contiguous run of the pair's
     // row, and the lane's element, pair flag and offsets are formed once
@@ -411,7 +411,7 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
     constexpr bool F64 = sizeof(T) == 8;
     T irho[P], buoy[P], dz[8][P];
     double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
-    int ez = 0, base = 0, exl = 0;
+    int ez = 0, base = 0;
     const int layer = a.ni * a.nj;
     // MODE 2: the run-interior nodes this lane finishes, their M^-1 and q^n
     const int new_ = it.ne - e0 < EB ? it.ne - e0 : EB;
@@ -429,7 +429,6 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
             be = box_elem((uint32_t)(e0 + q), a.fx, a.fy);
         }
         ez = be.ez;
-        exl = be.ex;
         const double *cp = a.hcol + (int64_t)(be.ex + a.nx * be.ey) * (4 * PP) + c;
         c0 = cp[0];
         c1 = cp[PP];
@@ -549,9 +548,6 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
             }
         }
         return;  // every lane: no barrier follows
-    }
-    if constexpr (MODE == 2) {
-        if (act) split_store_fb<N, T, EB>(it, gm, e0, q, i, j, exl, res);
     }
     __syncthreads();  // tiles read
     T *st = &s[0][0][0];
@@ -977,10 +973,8 @@ __global__ __launch_bounds__((col_threads<N, double>())) void k_filter_col(Filte
     SplitPre<N, EB, BT> pf;
     split_prefetch<N, EB, BT>(it, gm, false, t, e0, new_, pf);
     double jw[P];
-    int exl = 0;
     if (act) {
         const BoxElem be = box_elem((uint32_t)(e0 + q), it.fx, it.fy);
-        exl = be.ex;
         const double c0 = it.hcol[(int64_t)(be.ex + gm.nx * be.ey) * (4 * PP) + c];
         int gi = be.ex * N + i, gj = be.ey * N + j;
         if (gi == gm.ni) gi = 0;
@@ -1036,7 +1030,6 @@ __global__ __launch_bounds__((col_threads<N, double>())) void k_filter_col(Filte
                 for (int m = 0; m < P; ++m) r = fma(Fs[k * P + m], x[v][m], r);
                 res[k][v] = jw[k] * r;
             }
-        split_store_fb<N, double, EB>(it, gm, e0, q, i, j, exl, res);
     }
     __syncthreads();  // tile read
     double *st = &s[0][0][0];
