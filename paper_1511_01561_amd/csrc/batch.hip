@@ -308,27 +308,33 @@ __device__ __forceinline__ void split_store(const BatchItem &it, const SplitGeo 
     T *Fa = (T *)it.ev;
     // Fb: the east face (slot order: face pairs, then interior pairs) of an
     // element whose east neighbour is not in the run, the interior rows of a
-    // run's first element (ip, then i)
+    // run's first element (ip, then i); by the last wavefront where the face
+    // rows below leave most of its lanes idle (N = 4: 8 of 64), else by all
+    constexpr int RUN = EB * N * 5;  // values of one face pair of the workgroup
+    constexpr bool LASTW = RUN <= BT - 48;
+    constexpr int FBS = LASTW ? 64 : BT;
     T *Fb = Fa + 5 * (int64_t)gm.nz * gm.ny * NFP * gm.ni;
+    const int tb = LASTW ? t - (BT - 64) : t;
     int ex = box_elem((uint32_t)e0, gm.fx, gm.fy).ex;  // x index of element qq, stepped along the run
-    for (int qq = 0; qq < new_; ++qq, ex = ex + 1 == gm.nx ? 0 : ex + 1) {
+    for (int qq = 0; tb >= 0 && qq < new_; ++qq, ex = ex + 1 == gm.nx ? 0 : ex + 1) {
         if (!(qq == EB - 1 || ex == gm.nx - 1 || qq == 0 || ex == 0)) continue;
         T *fb = Fb + (int64_t)(e0 + qq) * NB * 5;
         if (qq == EB - 1 || ex == gm.nx - 1) {
-            for (int u = t; u < (NFP + NIP) * 5; u += BT) {
+            for (int u = tb; u < (NFP + NIP) * 5; u += FBS) {
                 const int slot = u / 5, v = u - slot * 5;
                 int jj, kk;
                 if (slot < NFP) {
                     split_fp_jk<N>(slot, jj, kk);
-                } else {
-                    jj = 1 + (slot - NFP) % (N - 1);
-                    kk = 1 + (slot - NFP) / (N - 1);
+                } else {  // interior pairs (N > 1)
+                    constexpr int M = N > 1 ? N - 1 : 1;
+                    jj = 1 + (slot - NFP) % M;
+                    kk = 1 + (slot - NFP) / M;
                 }
                 fb[u] = st[(qq * NP + N + P * (jj + P * kk)) * 5 + v];
             }
         }
         if (NIP > 0 && (qq == 0 || ex == 0)) {
-            for (int u = t; u < NIP * N * 5; u += BT) {
+            for (int u = tb; u < NIP * N * 5; u += FBS) {
                 const int nd = u / 5, v = u - nd * 5, ip = nd / N, ii = nd - ip * N;
                 const int jj = 1 + ip % (N - 1), kk = 1 + ip / (N - 1);
                 fb[(NFP + NIP) * 5 + u] = st[(qq * NP + ii + P * (jj + P * kk)) * 5 + v];
@@ -338,7 +344,6 @@ __device__ __forceinline__ void split_store(const BatchItem &it, const SplitGeo 
     // Fa: lane u < EB N 5 takes value v of node (qq, ii) of every face pair,
     // so that each store instruction writes one contiguous run of the pair's
     // row, and the lane's element, pair flag and offsets are formed once
-    constexpr int RUN = EB * N * 5;  // values of one face pair of the workgroup
     for (int u = t; u < RUN; u += BT) {
         const int nd = u / 5, v = u - nd * 5, qq = nd / N, ii = nd - qq * N;
         if (qq < new_) {
