@@ -236,13 +236,6 @@ __device__ __forceinline__ void split_fp_jk(int fp, int &j, int &k)
         j = (r & 1) ? N : 0;
     }
 }
-// slot in Fb of local node (N, j, k) (an unpaired east face)
-template <int N>
-__device__ __forceinline__ int split_slot_east(int j, int k)
-{
-    const bool face = j == 0 || j == N || k == 0 || k == N;
-    return face ? split_fp<N>(j, k) : 4 * N + (j - 1) + (N - 1) * (k - 1);
-}
 template <int N> constexpr int split_nb() { return 4 * N + (N - 1) * (N - 1) * (N + 1); }
 
 // what the split-DSS output of a column workgroup needs of its box item
