@@ -390,8 +390,9 @@ __device__ __forceinline__ void split_store(const BatchItem &it, const SplitGeo 
 // the elements of colour `colour` (parity of ex, ey, ez), EB consecutive ones
 // along x, and every lane adds its nodes' J w R to the FP64 accumulator with
 // a plain read-modify-write (no other element of the colour has the node).
-// MODE 2: NUMA_STAGE_SPLIT (above): pair sums, the run-interior nodes
-// finished, the face contributions into Fa and Fb.
+// MODE 2: NUMA_STAGE_SPLIT (above) in mixed precision (FP64 takes the
+// two-pass k_elem_col2 below): pair sums, the run-interior nodes finished, the
+// face contributions into Fa and Fb.
 template <int N, typename T, int MODE = 0>
 __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) void k_elem_col(Batch B, int colour)
 {
@@ -564,6 +565,175 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
     const int ne = it.ne - e0 < EB ? it.ne - e0 : EB;
     T *out = (T *)it.ev + (int64_t)e0 * (NP * 5);
     store_run<T>(out, st, ne * NP * 5, t, BT);
+}
+
+// The FP64 split stage with a two-pass tile (the element kernel of the split
+// DSS in FP64).  k_elem_col keeps eight tile fields (8 (N+1)^3 doubles per
+// element) and every field's zeta derivative in registers, which leaves room
+// for two workgroups per CU.  Here the tile holds five fields at a time, the
+// size of the output staging: first p', u, v, w, theta', from which the
+// momentum and theta' rows of R follow (advection, pressure gradient,
+// buoyancy), then rho u, rho v, rho w for the mass row.  The lane takes its
+// column's values from the tile, the xi and eta rows per node.  Each term is
+// the product and sum of k_elem_col; the tail is the split DSS.  Three
+// workgroups per CU at N = 4 (50 KB of LDS), four below (N = 3: 40 KB, a
+// 16-byte stack frame, measured faster than three without it).
+template <int N> constexpr int col2_waves() { return N <= 3 ? 4 : 3; }
+template <int N>
+__global__ __launch_bounds__((col_threads<N, double>()), (col2_waves<N>())) void k_elem_col2(Batch B)
+{
+    using T = double;
+    constexpr int P = N + 1, PP = P * P, NP = PP * P, EB = col_eb<N, T>(), BT = col_threads<N, T>();
+    __shared__ T s[EB][5][NP];
+    const int g0 = (int)xcd_remap(blockIdx.x, gridDim.x) * EB;
+    const BatchItem &it = B.it[batch_item(B, g0, false)];
+    const RhsArgs<T> a = elem_args<T>(B, it);
+    const int e0 = g0 - it.eoff;
+    const int t = threadIdx.x, q = t / PP, c = t % PP, i = c % P, j = c / P;
+    const bool act = q < EB && e0 + q < it.ne;
+    const int new_ = it.ne - e0 < EB ? it.ne - e0 : EB;
+    const SplitGeo gm{a.nx, a.ny, a.nz, a.ni, a.nj, (int)a.nu, a.fx, a.fy};
+    const bool fold = B.fold != 0;
+    const double cdt = it.cdt, gz = -a.g0;
+    const int walls = it.walls;
+    // per node of the column: rho, rho' and 1/rho (formed as in k_elem_col)
+    double rho[P], rp[P], ir[P];
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+    int ez = 0;
+    if (act) {
+        const BoxElem be = box_elem((uint32_t)(e0 + q), a.fx, a.fy);
+        ez = be.ez;
+        const double *cp = a.hcol + (int64_t)(be.ex + a.nx * be.ey) * (4 * PP) + c;
+        c0 = cp[0];
+        c1 = cp[PP];
+        c2 = cp[2 * PP];
+        c3 = cp[3 * PP];
+        int gi = be.ex * N + i, gj = be.ey * N + j;
+        if (gi == a.ni) gi = 0;
+        if (gj == a.nj) gj = 0;
+        const int base = gi + a.ni * gj, layer = a.ni * a.nj;
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            int gk = be.ez * N + k;
+            if (gk == a.nk) gk = 0;
+            const int32_t I = base + layer * gk;
+            const double *qp = a.q + I, *rf = a.ref + I;
+            const double r_ = qp[0], u = qp[a.nu], v = qp[2 * a.nu], w = qp[3 * a.nu], tp = qp[4 * a.nu];
+            const double rb = rf[0], tb = it.theta0, pb = rf[2 * a.nu];
+            rho[k] = rb + r_;
+            rp[k] = r_;
+            const double dl = r_ * tb + rb * tp + r_ * tp;
+            const int l = c + PP * k;
+            s[q][0][l] = pb * eos_rel(dl / (rb * tb), a.gamma, a.eos);
+            s[q][1][l] = u;
+            s[q][2][l] = v;
+            s[q][3][l] = w;
+            s[q][4][l] = tp;
+            ir[k] = 1.0 / rho[k];
+        }
+    }
+    __syncthreads();  // first tile complete
+    double res[P][5];
+    T Di[P], Dj[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+        Di[m] = a.D[i * P + m];
+        Dj[m] = a.D[j * P + m];
+    }
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            T mx[10];
+            box_node_metric<T>(a.bm, ez, B.xi[k], c0 * B.w[k], c1, c2, c3, mx);
+            const int l = c + PP * k;
+            const T uu = s[q][1][l], vv = s[q][2][l], ww = s[q][3][l], tt = s[q][4][l];
+            T dd[5][3];
+#pragma unroll
+            for (int f = 0; f < 5; ++f) {
+                T da = 0, db = 0, dz = 0;
+#pragma unroll
+                for (int m = 0; m < P; ++m) {
+                    da += Di[m] * s[q][f][m + P * (j + P * k)];
+                    db += Dj[m] * s[q][f][i + P * (m + P * k)];
+                    dz += a.D[k * P + m] * s[q][f][c + PP * m];
+                }
+                dd[f][0] = da;
+                dd[f][1] = db;
+                dd[f][2] = dz;
+            }
+            T Uc[3];
+            Uc[0] = uu * mx[0];
+            Uc[1] = vv * mx[4];
+            Uc[2] = uu * mx[6] + vv * mx[7] + ww * mx[8];
+            auto adv = [&](int f) -> T { return Uc[0] * dd[f][0] + Uc[1] * dd[f][1] + Uc[2] * dd[f][2]; };
+            const T bk = rp[k] * ir[k];
+            T R[4];
+            R[0] = -adv(1) - (dd[0][0] * mx[0] + dd[0][2] * mx[6]) * ir[k];
+            R[1] = -adv(2) - (dd[0][1] * mx[4] + dd[0][2] * mx[7]) * ir[k];
+            R[2] = -adv(3) - dd[0][2] * mx[8] * ir[k] + bk * gz;
+            R[3] = -adv(4);
+            const bool wall = walls && ((ez == 0 && k == 0) || (ez == a.nz - 1 && k == N));
+            if (fold && !wall) {
+                const T qv[4] = {uu, vv, ww, tt};
+#pragma unroll
+                for (int v = 0; v < 4; ++v) res[k][v + 1] = mx[9] * fma((T)cdt, R[v], qv[v]);
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) res[k][v + 1] = mx[9] * R[v];
+            }
+        }
+    }
+    // the mass fluxes of the column, formed from the first tile
+    T fl[P][3];
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int l = c + PP * k;
+            fl[k][0] = rho[k] * s[q][1][l];
+            fl[k][1] = rho[k] * s[q][2][l];
+            fl[k][2] = rho[k] * s[q][3][l];
+        }
+    }
+    __syncthreads();  // first tile read
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+#pragma unroll
+            for (int f = 0; f < 3; ++f) s[q][f][c + PP * k] = fl[k][f];
+    }
+    __syncthreads();  // second tile complete
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            T mx[10];
+            box_node_metric<T>(a.bm, ez, B.xi[k], c0 * B.w[k], c1, c2, c3, mx);
+            T da = 0, db = 0, dz[3] = {0, 0, 0};
+#pragma unroll
+            for (int m = 0; m < P; ++m) {
+                da += Di[m] * s[q][0][m + P * (j + P * k)];
+                db += Dj[m] * s[q][1][i + P * (m + P * k)];
+#pragma unroll
+                for (int f = 0; f < 3; ++f) dz[f] += a.D[k * P + m] * s[q][f][c + PP * m];
+            }
+            const T R0 = -((da * mx[0] + dz[0] * mx[6]) + (db * mx[4] + dz[1] * mx[7]) + dz[2] * mx[8]);
+            const bool wall = walls && ((ez == 0 && k == 0) || (ez == a.nz - 1 && k == N));
+            res[k][0] = (fold && !wall) ? mx[9] * fma((T)cdt, R0, rp[k]) : mx[9] * R0;
+        }
+    }
+    // the run-interior nodes' M^-1 and q^n (issued here, where the tiles'
+    // registers are free)
+    SplitPre<N, EB, BT> pf;
+    split_prefetch<N, EB, BT>(it, gm, B.ca != 0.0, t, e0, new_, pf);
+    __syncthreads();  // second tile read
+    T *st = &s[0][0][0];
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+#pragma unroll
+            for (int v = 0; v < 5; ++v) st[(q * NP + c + PP * k) * 5 + v] = res[k][v];
+    }
+    __syncthreads();
+    split_store<N, T, EB, BT>(it, gm, StageCoef{B.ca, B.cb, cdt}, fold, st, t, e0, new_, pf);
 }
 
 // NUMA_STAGE_SPLIT finish: the face nodes and the run-start interior nodes.
@@ -1189,11 +1359,15 @@ int32_t run_chunk_seg(const StepItem *items, int n, int phase, hipStream_t s, in
     }
     if (split) {
         if constexpr (kind == 0) {
-            if (phase == 0)
-                hipLaunchKernelGGL((k_elem_col<N, T, 2>), dim3((unsigned)(eo / eb)), dim3(col_threads<N, T>()), 0, s, B,
-                                   0);
-            else
+            if (phase == 0) {
+                if constexpr (std::is_same<T, double>::value)
+                    hipLaunchKernelGGL((k_elem_col2<N>), dim3((unsigned)(eo / eb)), dim3(col_threads<N, T>()), 0, s, B);
+                else
+                    hipLaunchKernelGGL((k_elem_col<N, T, 2>), dim3((unsigned)(eo / eb)), dim3(col_threads<N, T>()), 0, s,
+                                       B, 0);
+            } else {
                 hipLaunchKernelGGL((k_fin_split<N, T>), dim3((unsigned)bo), dim3(256), 0, s, B);
+            }
             NUMA_HIP(hipGetLastError());
             return NUMA_OK;
         }

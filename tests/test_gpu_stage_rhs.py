@@ -1,10 +1,11 @@
 """The right-hand side as the benchmark's stage kernels compute it, against
 the oracle.
 
-numa_stage_rhs runs numa_step's own element and finish kernels (the column
-kernels k_elem_col / k_elem_stream with the recomputed metric, k_elem_batch
-with the stored metric or FP64 at N = 7, 8; the box finish k_fin_batch; the
-generic and shell finishes elsewhere) as a stage whose update is the identity
+numa_stage_rhs runs numa_step's own element and finish kernels (with the
+recomputed metric the split DSS in FP64 up to N = 4: k_elem_col2 and the face
+finish k_fin_split; otherwise the column kernels k_elem_col / k_elem_stream,
+k_elem_batch with the stored metric or FP64 at N = 7, 8, and the box finish
+k_fin_batch; the generic and shell finishes elsewhere) as a stage whose update is the identity
 on R.  Its output is M^-1 DSS(J w R) with the wall projection, which the
 oracle computes as dss(rhs(q), MASS | NOFLUX) (Eq. (discstrongform), Eq.
 (derivatives), Code example 1).  Tolerances: FP64 1e-12 and mixed precision
