@@ -579,12 +579,18 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
 // workgroups per CU at N = 4 (50 KB of LDS), four below (N = 3: 40 KB, a
 // 16-byte stack frame, measured faster than three without it).
 template <int N> constexpr int col2_waves() { return N <= 3 ? 4 : 3; }
+// doubles after each element's tile: at N = 4, 8 spread the xi and eta rows of
+// the two or three elements a wavefront spans over the LDS banks (50,640
+// bytes, still three workgroups per CU); at N = 3 the 40 KB tile has no room
+template <int N> constexpr int col2_pad() { return N == 4 ? 8 : 0; }
 template <int N>
 __global__ __launch_bounds__((col_threads<N, double>()), (col2_waves<N>())) void k_elem_col2(Batch B)
 {
     using T = double;
     constexpr int P = N + 1, PP = P * P, NP = PP * P, EB = col_eb<N, T>(), BT = col_threads<N, T>();
-    __shared__ T s[EB][5][NP];
+    constexpr int PAD = col2_pad<N>();
+    __shared__ T s[EB][5 * NP + PAD];
+    auto S = [&](int qq, int f, int l) -> T & { return s[qq][f * NP + l]; };
     const int g0 = (int)xcd_remap(blockIdx.x, gridDim.x) * EB;
     const BatchItem &it = B.it[batch_item(B, g0, false)];
     const RhsArgs<T> a = elem_args<T>(B, it);
@@ -624,11 +630,11 @@ __global__ __launch_bounds__((col_threads<N, double>()), (col2_waves<N>())) void
             rp[k] = r_;
             const double dl = r_ * tb + rb * tp + r_ * tp;
             const int l = c + PP * k;
-            s[q][0][l] = pb * eos_rel(dl / (rb * tb), a.gamma, a.eos);
-            s[q][1][l] = u;
-            s[q][2][l] = v;
-            s[q][3][l] = w;
-            s[q][4][l] = tp;
+            S(q, 0, l) = pb * eos_rel(dl / (rb * tb), a.gamma, a.eos);
+            S(q, 1, l) = u;
+            S(q, 2, l) = v;
+            S(q, 3, l) = w;
+            S(q, 4, l) = tp;
             ir[k] = 1.0 / rho[k];
         }
     }
@@ -646,16 +652,16 @@ __global__ __launch_bounds__((col_threads<N, double>()), (col2_waves<N>())) void
             T mx[10];
             box_node_metric<T>(a.bm, ez, B.xi[k], c0 * B.w[k], c1, c2, c3, mx);
             const int l = c + PP * k;
-            const T uu = s[q][1][l], vv = s[q][2][l], ww = s[q][3][l], tt = s[q][4][l];
+            const T uu = S(q, 1, l), vv = S(q, 2, l), ww = S(q, 3, l), tt = S(q, 4, l);
             T dd[5][3];
 #pragma unroll
             for (int f = 0; f < 5; ++f) {
                 T da = 0, db = 0, dz = 0;
 #pragma unroll
                 for (int m = 0; m < P; ++m) {
-                    da += Di[m] * s[q][f][m + P * (j + P * k)];
-                    db += Dj[m] * s[q][f][i + P * (m + P * k)];
-                    dz += a.D[k * P + m] * s[q][f][c + PP * m];
+                    da += Di[m] * S(q, f, m + P * (j + P * k));
+                    db += Dj[m] * S(q, f, i + P * (m + P * k));
+                    dz += a.D[k * P + m] * S(q, f, c + PP * m);
                 }
                 dd[f][0] = da;
                 dd[f][1] = db;
@@ -689,9 +695,9 @@ __global__ __launch_bounds__((col_threads<N, double>()), (col2_waves<N>())) void
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             const int l = c + PP * k;
-            fl[k][0] = rho[k] * s[q][1][l];
-            fl[k][1] = rho[k] * s[q][2][l];
-            fl[k][2] = rho[k] * s[q][3][l];
+            fl[k][0] = rho[k] * S(q, 1, l);
+            fl[k][1] = rho[k] * S(q, 2, l);
+            fl[k][2] = rho[k] * S(q, 3, l);
         }
     }
     __syncthreads();  // first tile read
@@ -699,7 +705,7 @@ __global__ __launch_bounds__((col_threads<N, double>()), (col2_waves<N>())) void
 #pragma unroll
         for (int k = 0; k < P; ++k)
 #pragma unroll
-            for (int f = 0; f < 3; ++f) s[q][f][c + PP * k] = fl[k][f];
+            for (int f = 0; f < 3; ++f) S(q, f, c + PP * k) = fl[k][f];
     }
     __syncthreads();  // second tile complete
     if (act) {
@@ -710,10 +716,10 @@ __global__ __launch_bounds__((col_threads<N, double>()), (col2_waves<N>())) void
             T da = 0, db = 0, dz[3] = {0, 0, 0};
 #pragma unroll
             for (int m = 0; m < P; ++m) {
-                da += Di[m] * s[q][0][m + P * (j + P * k)];
-                db += Dj[m] * s[q][1][i + P * (m + P * k)];
+                da += Di[m] * S(q, 0, m + P * (j + P * k));
+                db += Dj[m] * S(q, 1, i + P * (m + P * k));
 #pragma unroll
-                for (int f = 0; f < 3; ++f) dz[f] += a.D[k * P + m] * s[q][f][c + PP * m];
+                for (int f = 0; f < 3; ++f) dz[f] += a.D[k * P + m] * S(q, f, c + PP * m);
             }
             const T R0 = -((da * mx[0] + dz[0] * mx[6]) + (db * mx[4] + dz[1] * mx[7]) + dz[2] * mx[8]);
             const bool wall = walls && ((ez == 0 && k == 0) || (ez == a.nz - 1 && k == N));
@@ -725,7 +731,7 @@ __global__ __launch_bounds__((col_threads<N, double>()), (col2_waves<N>())) void
     SplitPre<N, EB, BT> pf;
     split_prefetch<N, EB, BT>(it, gm, B.ca != 0.0, t, e0, new_, pf);
     __syncthreads();  // second tile read
-    T *st = &s[0][0][0];
+    T *st = &s[0][0];
     if (act) {
 #pragma unroll
         for (int k = 0; k < P; ++k)
