@@ -1135,7 +1135,9 @@ template <int N>
 __global__ __launch_bounds__((col_threads<N, double>())) void k_filter_col(FilterSplit A)
 {
     constexpr int P = N + 1, PP = P * P, NP = PP * P, EB = col_eb<N, double>(), BT = col_threads<N, double>();
-    __shared__ double s[EB][5][NP];
+    constexpr int PAD = col2_pad<N>();  // the two-pass stage kernel's bank spread
+    __shared__ double s[EB][5 * NP + PAD];
+    auto S = [&](int qq, int f, int l) -> double & { return s[qq][f * NP + l]; };
     __shared__ double Fs[PP];
     const BatchItem &it = A.it;
     const int e0 = (int)xcd_remap(blockIdx.x, gridDim.x) * EB;
@@ -1160,7 +1162,7 @@ __global__ __launch_bounds__((col_threads<N, double>())) void k_filter_col(Filte
             if (gk == it.nkw) gk = 0;
             const int32_t I = base + layer * gk;
 #pragma unroll
-            for (int v = 0; v < 5; ++v) s[q][v][c + PP * k] = it.qs[I + v * gm.nu];
+            for (int v = 0; v < 5; ++v) S(q, v, c + PP * k) = it.qs[I + v * gm.nu];
             jw[k] = c0 * A.w[k];
         }
     }
@@ -1173,7 +1175,7 @@ __global__ __launch_bounds__((col_threads<N, double>())) void k_filter_col(Filte
             for (int v = 0; v < 5; ++v) {
                 double r = 0.0;
 #pragma unroll
-                for (int m = 0; m < P; ++m) r = fma(Fs[i * P + m], s[q][v][m + P * (j + P * k)], r);
+                for (int m = 0; m < P; ++m) r = fma(Fs[i * P + m], S(q, v, m + P * (j + P * k)), r);
                 x[v][k] = r;
             }
     }
@@ -1182,7 +1184,7 @@ __global__ __launch_bounds__((col_threads<N, double>())) void k_filter_col(Filte
 #pragma unroll
         for (int k = 0; k < P; ++k)
 #pragma unroll
-            for (int v = 0; v < 5; ++v) s[q][v][c + PP * k] = x[v][k];
+            for (int v = 0; v < 5; ++v) S(q, v, c + PP * k) = x[v][k];
     __syncthreads();
     double res[P][5];
     if (act) {  // eta through the tile, zeta in registers, times J w
@@ -1192,7 +1194,7 @@ __global__ __launch_bounds__((col_threads<N, double>())) void k_filter_col(Filte
             for (int v = 0; v < 5; ++v) {
                 double r = 0.0;
 #pragma unroll
-                for (int m = 0; m < P; ++m) r = fma(Fs[j * P + m], s[q][v][i + P * (m + P * k)], r);
+                for (int m = 0; m < P; ++m) r = fma(Fs[j * P + m], S(q, v, i + P * (m + P * k)), r);
                 x[v][k] = r;
             }
 #pragma unroll
@@ -1206,7 +1208,7 @@ __global__ __launch_bounds__((col_threads<N, double>())) void k_filter_col(Filte
             }
     }
     __syncthreads();  // tile read
-    double *st = &s[0][0][0];
+    double *st = &s[0][0];
     if (act)
 #pragma unroll
         for (int k = 0; k < P; ++k)
