@@ -577,12 +577,15 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
 // column's values from the tile, the xi and eta rows per node.  Each term is
 // the product and sum of k_elem_col; the tail is the split DSS.  Three
 // workgroups per CU at N = 4 (50 KB of LDS), four below (N = 3: 40 KB, a
-// 16-byte stack frame, measured faster than three without it).
-template <int N> constexpr int col2_waves() { return N <= 3 ? 4 : 3; }
+// 16-byte stack frame, measured faster than three without it); N = 5, 6 as
+// noted below.
+template <int N> constexpr int col2_waves() { return N <= 3 ? 4 : (N == 4 ? 3 : 2); }
 // doubles after each element's tile: at N = 4, 8 spread the xi and eta rows of
 // the two or three elements a wavefront spans over the LDS banks (50,640
 // bytes, still three workgroups per CU); at N = 3 the 40 KB tile has no room
 template <int N> constexpr int col2_pad() { return N == 4 ? 8 : 0; }
+// N = 5, 6 (three and two elements per 128-lane workgroup, 26-27 KB of LDS):
+// two waves per SIMD, where three would spill
 template <int N>
 __global__ __launch_bounds__((col_threads<N, double>()), (col2_waves<N>())) void k_elem_col2(Batch B)
 {
@@ -1296,7 +1299,7 @@ int32_t run_chunk_seg(const StepItem *items, int n, int phase, hipStream_t s, in
     // FP64 update that uses q_s (b != 0): the column and one-node-per-lane
     // element kernels fold q_s into the contributions (the streaming one,
     // which runs at its register limit, does not)
-    B.fold = (std::is_same<T, double>::value && B.cb != 0.0 && !(recompute && kind == 1)) ? 1 : 0;
+    B.fold = (std::is_same<T, double>::value && B.cb != 0.0 && (split || !(recompute && kind == 1))) ? 1 : 0;
     int64_t eo = 0, bo = 0;
     for (int k = 0; k < n; ++k) {
         const Mesh &m = *items[k].mesh;
@@ -1378,7 +1381,16 @@ int32_t run_chunk_seg(const StepItem *items, int n, int phase, hipStream_t s, in
             }
             NUMA_HIP(hipGetLastError());
             return NUMA_OK;
+        } else if constexpr (kind == 1 && std::is_same<T, double>::value && N <= 6) {
+            if (phase == 0)
+                hipLaunchKernelGGL((k_elem_col2<N>), dim3((unsigned)(eo / eb)), dim3(col_threads<N, T>()), 0, s, B);
+            else
+                hipLaunchKernelGGL((k_fin_split<N, T>), dim3((unsigned)bo), dim3(256), 0, s, B);
+            NUMA_HIP(hipGetLastError());
+            return NUMA_OK;
         }
+        set_error("split DSS: no element kernel for this order and precision");
+        return NUMA_EUNSUPPORTED;
     }
     if (phase == 0) {
         if (!recompute) {
@@ -1580,7 +1592,7 @@ int32_t run_filter_split(const Mesh &m, const double *F, double *q, hipStream_t 
 
 bool filter_split_ok(const Mesh &m)
 {
-    return split_ok(m, NUMA_PREC_FP64);
+    return m.N <= 4 && split_ok(m, NUMA_PREC_FP64);
 }
 
 int32_t launch_filter_split(const Mesh &m, const double *F, double *q, hipStream_t s)
@@ -1602,14 +1614,16 @@ bool colour_ok(const Mesh &m)
            m.N <= 4 && m.d.ne[0] % 2 == 0 && m.d.ne[1] % 2 == 0 && m.d.ne[2] % 2 == 0;
 }
 
-// NUMA_STAGE_SPLIT runs the column element kernel (recomputed metric, N <= 4);
-// its finish takes any x extent.  NUMA_STAGE_AUTO takes it in FP64 (measured
-// faster than the gather there; in mixed precision the gather, whose FP32
-// contributions are half the bytes, is faster)
+// NUMA_STAGE_SPLIT runs a column element kernel (recomputed metric; N <= 4,
+// and in FP64 N = 5, 6 with the two-pass kernel); its finish takes any x
+// extent.  NUMA_STAGE_AUTO takes it in FP64 (measured faster than the gather
+// there; in mixed precision the gather, whose FP32 contributions are half the
+// bytes, is faster)
 bool split_ok(const Mesh &m, int32_t prec)
 {
     const bool mode = m.stage_mode == NUMA_STAGE_SPLIT || (m.stage_mode == NUMA_STAGE_AUTO && prec == NUMA_PREC_FP64);
-    return mode && m.d.kind == NUMA_MESH_BOX && m.metric_mode == NUMA_METRIC_RECOMPUTE && m.N <= 4;
+    const int nmax = prec == NUMA_PREC_FP64 ? 6 : 4;
+    return mode && m.d.kind == NUMA_MESH_BOX && m.metric_mode == NUMA_METRIC_RECOMPUTE && m.N <= nmax;
 }
 
 int32_t launch_batch_stage(const StepItem *items, int n, int32_t prec, int phase, hipStream_t s)
