@@ -183,6 +183,11 @@ template <int N, typename T>
 constexpr int col_threads() { return ((col_eb<N, T>() * (N + 1) * (N + 1) + 63) / 64) * 64; }
 // workgroups per CU the column kernel is compiled for: in FP32 at N = 4 the
 // tile (40 KB) lets four share a CU if the registers fit 4 waves per SIMD
+// elements per workgroup of the split DSS (the run length along x): the column
+// kernels' up to N = 4, above that a 256-lane workgroup of the two-pass kernel
+template <int N> constexpr int split_eb() { return N <= 4 ? col_eb<N, double>() : 256 / ((N + 1) * (N + 1)); }
+template <int N> constexpr int split_threads() { return ((split_eb<N>() * (N + 1) * (N + 1) + 63) / 64) * 64; }
+
 template <int N, typename T, int MODE = 0>
 constexpr int col_blocks() { return (sizeof(T) == 4 && N == 4) ? (MODE == 2 ? 2 : 4) : 1; }
 
@@ -584,13 +589,13 @@ template <int N> constexpr int col2_waves() { return N <= 3 ? 4 : (N == 4 ? 3 : 
 // the two or three elements a wavefront spans over the LDS banks (50,640
 // bytes, still three workgroups per CU); at N = 3 the 40 KB tile has no room
 template <int N> constexpr int col2_pad() { return N == 4 ? 8 : 0; }
-// N = 5, 6 (three and two elements per 128-lane workgroup, 26-27 KB of LDS):
-// two waves per SIMD, where three would spill
+// N = 5, 6 (seven and five elements per 256-lane workgroup, 60 and 69 KB of
+// LDS): two waves per SIMD
 template <int N>
-__global__ __launch_bounds__((col_threads<N, double>()), (col2_waves<N>())) void k_elem_col2(Batch B)
+__global__ __launch_bounds__((split_threads<N>()), (col2_waves<N>())) void k_elem_col2(Batch B)
 {
     using T = double;
-    constexpr int P = N + 1, PP = P * P, NP = PP * P, EB = col_eb<N, T>(), BT = col_threads<N, T>();
+    constexpr int P = N + 1, PP = P * P, NP = PP * P, EB = split_eb<N>(), BT = split_threads<N>();
     constexpr int PAD = col2_pad<N>();
     __shared__ T s[EB][5 * NP + PAD];
     auto S = [&](int qq, int f, int l) -> T & { return s[qq][f * NP + l]; };
@@ -761,7 +766,7 @@ __global__ __launch_bounds__((col_threads<N, double>()), (col2_waves<N>())) void
 template <int N, typename T, bool PLAIN = false>
 __global__ __launch_bounds__(256) void k_fin_split(Batch B)
 {
-    constexpr int NFP = 4 * N, NIP = (N - 1) * (N - 1), NB = split_nb<N>(), EB = col_eb<N, T>();
+    constexpr int NFP = 4 * N, NIP = (N - 1) * (N - 1), NB = split_nb<N>(), EB = split_eb<N>();
     const int g = (int)xcd_remap(blockIdx.x, gridDim.x);
     const BatchItem &it = B.it[batch_item(B, g, true)];
     const int nx = (int)it.fx.d, ny = (int)it.fy.d, nz = it.nz, ni = it.ni, nj = it.nj;
@@ -1295,7 +1300,7 @@ int32_t run_chunk_seg(const StepItem *items, int n, int phase, hipStream_t s, in
     constexpr bool col_ok = kind != 2;
     const bool recompute = items[0].mesh->metric_mode == NUMA_METRIC_RECOMPUTE;
     const bool col = recompute && col_ok;
-    const int eb = col ? col_eb<N, T>() : 1;
+    const int eb = split ? split_eb<N>() : col ? col_eb<N, T>() : 1;
     // FP64 update that uses q_s (b != 0): the column and one-node-per-lane
     // element kernels fold q_s into the contributions (the streaming one,
     // which runs at its register limit, does not)
@@ -1372,7 +1377,7 @@ int32_t run_chunk_seg(const StepItem *items, int n, int phase, hipStream_t s, in
         if constexpr (kind == 0) {
             if (phase == 0) {
                 if constexpr (std::is_same<T, double>::value)
-                    hipLaunchKernelGGL((k_elem_col2<N>), dim3((unsigned)(eo / eb)), dim3(col_threads<N, T>()), 0, s, B);
+                    hipLaunchKernelGGL((k_elem_col2<N>), dim3((unsigned)(eo / eb)), dim3(split_threads<N>()), 0, s, B);
                 else
                     hipLaunchKernelGGL((k_elem_col<N, T, 2>), dim3((unsigned)(eo / eb)), dim3(col_threads<N, T>()), 0, s,
                                        B, 0);
@@ -1383,7 +1388,7 @@ int32_t run_chunk_seg(const StepItem *items, int n, int phase, hipStream_t s, in
             return NUMA_OK;
         } else if constexpr (kind == 1 && std::is_same<T, double>::value && N <= 6) {
             if (phase == 0)
-                hipLaunchKernelGGL((k_elem_col2<N>), dim3((unsigned)(eo / eb)), dim3(col_threads<N, T>()), 0, s, B);
+                hipLaunchKernelGGL((k_elem_col2<N>), dim3((unsigned)(eo / eb)), dim3(split_threads<N>()), 0, s, B);
             else
                 hipLaunchKernelGGL((k_fin_split<N, T>), dim3((unsigned)bo), dim3(256), 0, s, B);
             NUMA_HIP(hipGetLastError());
