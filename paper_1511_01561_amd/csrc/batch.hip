@@ -184,8 +184,13 @@ constexpr int col_threads() { return ((col_eb<N, T>() * (N + 1) * (N + 1) + 63) 
 // workgroups per CU the column kernel is compiled for: in FP32 at N = 4 the
 // tile (40 KB) lets four share a CU if the registers fit 4 waves per SIMD
 // elements per workgroup of the split DSS (the run length along x): the column
-// kernels' up to N = 4, above that a 256-lane workgroup of the two-pass kernel
-template <int N> constexpr int split_eb() { return N <= 4 ? col_eb<N, double>() : 256 / ((N + 1) * (N + 1)); }
+// kernels' up to N = 4, above that as many as 256 lanes and an 80 KB tile
+// (two workgroups per CU) hold: 7, 5, 4, 2 at N = 5..8
+template <int N> constexpr int split_eb()
+{
+    constexpr int PP = (N + 1) * (N + 1), lanes = 256 / PP, lds = 2048 / (PP * (N + 1));
+    return N <= 4 ? col_eb<N, double>() : (lanes < lds ? lanes : lds);
+}
 template <int N> constexpr int split_threads() { return ((split_eb<N>() * (N + 1) * (N + 1) + 63) / 64) * 64; }
 
 template <int N, typename T, int MODE = 0>
@@ -1386,7 +1391,7 @@ int32_t run_chunk_seg(const StepItem *items, int n, int phase, hipStream_t s, in
             }
             NUMA_HIP(hipGetLastError());
             return NUMA_OK;
-        } else if constexpr (kind == 1 && std::is_same<T, double>::value && N <= 6) {
+        } else if constexpr (std::is_same<T, double>::value) {
             if (phase == 0)
                 hipLaunchKernelGGL((k_elem_col2<N>), dim3((unsigned)(eo / eb)), dim3(split_threads<N>()), 0, s, B);
             else
@@ -1627,7 +1632,7 @@ bool colour_ok(const Mesh &m)
 bool split_ok(const Mesh &m, int32_t prec)
 {
     const bool mode = m.stage_mode == NUMA_STAGE_SPLIT || (m.stage_mode == NUMA_STAGE_AUTO && prec == NUMA_PREC_FP64);
-    const int nmax = prec == NUMA_PREC_FP64 ? 6 : 4;
+    const int nmax = prec == NUMA_PREC_FP64 ? 8 : 4;
     return mode && m.d.kind == NUMA_MESH_BOX && m.metric_mode == NUMA_METRIC_RECOMPUTE && m.N <= nmax;
 }
 

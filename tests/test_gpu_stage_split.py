@@ -6,10 +6,10 @@ nodes whose copies it then holds; the element faces in y and z and the x
 faces that start a run are finished by a second kernel from contributions
 written in rows along x.  The meshes cover runs that stay in one row of
 elements, runs that wrap onto the next row or layer (nx not a multiple of,
-or smaller than, the run length: 2 elements at N = 6, 3 at N = 5, 10 at
-N = 4, 16 at N = 3, 28 at N = 2, 64 at N = 1), walls and periodic z.  FP64
-takes the split DSS up to N = 6, mixed precision up to N = 4 (above, the
-gather, which these tests then check as well).  FP64 within 1e-12 and mixed
+or smaller than, the run length: 2 elements at N = 8, 4 at N = 7, 5 at
+N = 6, 7 at N = 5, 10 at N = 4, 16 at N = 3, 28 at N = 2, 64 at N = 1),
+walls and periodic z.  FP64 takes the split DSS up to N = 8, mixed precision
+up to N = 4 (above, the gather, which these tests then check as well).  FP64 within 1e-12 and mixed
 precision within 1e-5, relative max-norm per variable group, for the
 right-hand side (numa_stage_rhs), for steps of both integrators (the
 five-stage one writes a stage over its own input), for the filtered step and
@@ -48,6 +48,10 @@ CASES = [
     (5, (3, 2, 3), True),
     (6, (5, 3, 2), False),
     (6, (4, 2, 2), True),
+    (7, (5, 2, 2), False),
+    (7, (3, 2, 2), True),
+    (8, (4, 2, 2), False),
+    (8, (2, 2, 2), True),
 ]
 
 
@@ -181,7 +185,7 @@ def test_split_resume_and_batch_bitwise(torch_cuda, oracle_mod, prec):
         assert torch.equal(it[1], a), k
 
 
-@pytest.mark.parametrize("N", [3, 4, 5, 6])
+@pytest.mark.parametrize("N", [3, 4, 5, 6, 7, 8])
 def test_split_full_size(torch_cuda, oracle_mod, N):
     """The 64 x 64 x 16 box: the right-hand side at 1e-12 (FP64) and 1e-5
     (mixed), and one FP64 step against the oracle's."""
