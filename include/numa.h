@@ -223,11 +223,13 @@ int32_t numa_mesh_set_metric(numa_mesh_t m, int32_t mode);
  *   the run): M^-1, update, state.  The contributions of the other nodes
  *   (the element faces in y and z, and the run-start faces) go to the
  *   workspace scratch in rows along x, and a second kernel gathers them and
- *   finishes those nodes.  N <= 4; the stage may write its input state (the
- *   nodes the element kernel finishes are read by no other workgroup).
+ *   finishes those nodes.  Recomputed metric; FP64 N = 1..8 (runs of
+ *   64, 28, 16, 10, 7, 5, 4, 2 elements), mixed precision N <= 4; the stage
+ *   may write its input state (the nodes the element kernel finishes are
+ *   read by no other workgroup).
  * NUMA_STAGE_AUTO (default): NUMA_STAGE_SPLIT for FP64 stages where it
  *   applies, NUMA_STAGE_GATHER otherwise (the faster of the two in each
- *   precision on the 64 x 64 x 16 box, N = 3 and 4).
+ *   precision on the 64 x 64 x 16 box, N = 3..8).
  * Meshes or stages a mode does not cover run NUMA_STAGE_GATHER.  NUMA_EINVAL
  * for an unknown mode.  Host only. */
 int32_t numa_mesh_set_stage(numa_mesh_t m, int32_t mode);
@@ -276,9 +278,9 @@ int32_t numa_dss(numa_mesh_t m, int32_t nvar, const double *c_elem, double *out,
  * (1/2 at t = 1/2, 0 for the top mode N); cutoff >= N leaves every element
  * unchanged.  filter_order must be finite and > 0, cutoff >= 0 (NUMA_EINVAL
  * otherwise).  The state is the perturbation state (rho', u, v, w, theta'), so
- * the hydrostatic reference is not filtered.  On a box whose FP64 stages take
- * the split DSS (numa_mesh_set_stage) the filter takes it too (the same
- * contributions, their copies summed in that schedule's order).  Uses the
+ * the hydrostatic reference is not filtered.  On a box (N <= 4) whose FP64
+ * stages take the split DSS (numa_mesh_set_stage) the filter takes it too
+ * (the same contributions, their copies summed in that schedule's order).  Uses the
  * mesh's contribution scratch, like numa_step: calls on one mesh on different
  * streams race. */
 int32_t numa_filter(numa_mesh_t m, double filter_order, int32_t cutoff, double *q, void *stream);
