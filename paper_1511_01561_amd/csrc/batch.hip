@@ -860,36 +860,39 @@ __global__ __launch_bounds__(256) void k_fin_split(Batch B)
         }
         const int ex = gi / N;
         const bool xface = gi % N == 0;
-        // every copy's loads first (absent ones are not loaded), then the sum
-        T ca[2][2][5], cb[2][2][5];
+        // the face rows' copies (absent ones are not loaded) are loaded
+        // together, then summed; the run-start x copies (Fb, at most one
+        // node in EB N of a row) after them
+        T ca[2][2][5];
 #pragma unroll
         for (int z = 0; z < 2; ++z)
 #pragma unroll
             for (int y = 0; y < 2; ++y) {
                 const bool has = z < nzc && y < nyc;
-                const int fp = split_fp<N>(jc[y], kc[z]);
-                const int64_t o = ((int64_t)(zc[z] * ny + yc[y]) * NFP + fp) * ni + gi;
-                const int ec = ex + nx * (yc[y] + ny * zc[z]);
-                const bool unpaired = has && xface && (ex == 0 || ec % EB == 0);
-                const int64_t ob = ((int64_t)(ex == 0 ? ec + nx - 1 : ec - 1) * NB + fp) * 5;
+                const int64_t o = ((int64_t)(zc[z] * ny + yc[y]) * NFP + split_fp<N>(jc[y], kc[z])) * ni + gi;
 #pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    ca[z][y][v] = has ? Fa[o * 5 + v] : (T)0;
-                    cb[z][y][v] = unpaired ? Fb[ob + v] : (T)0;
-                }
+                for (int v = 0; v < 5; ++v) ca[z][y][v] = has ? Fa[o * 5 + v] : (T)0;
             }
 #pragma unroll
         for (int z = 0; z < 2; ++z)
 #pragma unroll
-            for (int y = 0; y < 2; ++y) {
-                const bool has = z < nzc && y < nyc;
-                const bool unpaired = has && xface && (ex == 0 || (ex + nx * (yc[y] + ny * zc[z])) % EB == 0);
+            for (int y = 0; y < 2; ++y)
+                if (z < nzc && y < nyc)
 #pragma unroll
-                for (int v = 0; v < 5; ++v) {
-                    if (has) r[v] += (double)ca[z][y][v];
-                    if (unpaired) r[v] += (double)cb[z][y][v];
+                    for (int v = 0; v < 5; ++v) r[v] += (double)ca[z][y][v];
+        if (xface) {
+#pragma unroll
+            for (int z = 0; z < 2; ++z)
+#pragma unroll
+                for (int y = 0; y < 2; ++y) {
+                    const int ec = ex + nx * (yc[y] + ny * zc[z]);
+                    if (z < nzc && y < nyc && (ex == 0 || ec % EB == 0)) {
+                        const int64_t ob = ((int64_t)(ex == 0 ? ec + nx - 1 : ec - 1) * NB + split_fp<N>(jc[y], kc[z])) * 5;
+#pragma unroll
+                        for (int v = 0; v < 5; ++v) r[v] += (double)Fb[ob + v];
+                    }
                 }
-            }
+        }
     } else {
         if constexpr (NIP == 0) {
             return;
