@@ -530,7 +530,7 @@ def main():
         ach = algo / (st_us * 1e-6) / 1e9
         N = mm["N"]
         if prec == "fp64":  # NUMA_STAGE_AUTO: the split DSS
-            kernel = ("fused SSP-RK3 stage: k_elem_col2<%d> + k_fin_split<%d,double,false> (recomputed metric, "
+            kernel = ("fused SSP-RK3 stage: k_elem_col2<%d,double> + k_fin_split<%d,double,false> (recomputed metric, "
                       "split DSS)" % (N, N))
             trip = split_kernel_bytes(g.n_unique, n_wall, mm["ne"], N, prec)[2]
         else:

@@ -194,7 +194,7 @@ template <int N> constexpr int split_eb()
 template <int N> constexpr int split_threads() { return ((split_eb<N>() * (N + 1) * (N + 1) + 63) / 64) * 64; }
 
 template <int N, typename T, int MODE = 0>
-constexpr int col_blocks() { return (sizeof(T) == 4 && N == 4) ? (MODE == 2 ? 2 : 4) : 1; }
+constexpr int col_blocks() { return (sizeof(T) == 4 && N == 4) ? 4 : 1; }
 
 // NUMA_STAGE_SPLIT: the DSS split between the element kernel and a finish
 // kernel over the element faces.  The EB elements of a column workgroup are
@@ -400,9 +400,7 @@ __device__ __forceinline__ void split_store(const BatchItem &it, const SplitGeo 
 // the elements of colour `colour` (parity of ex, ey, ez), EB consecutive ones
 // along x, and every lane adds its nodes' J w R to the FP64 accumulator with
 // a plain read-modify-write (no other element of the colour has the node).
-// MODE 2: NUMA_STAGE_SPLIT (above) in mixed precision (FP64 takes the
-// two-pass k_elem_col2 below): pair sums, the run-interior nodes finished, the
-// face contributions into Fa and Fb.
+// (NUMA_STAGE_SPLIT takes the two-pass k_elem_col2 below.)
 template <int N, typename T, int MODE = 0>
 __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) void k_elem_col(Batch B, int colour)
 {
@@ -422,11 +420,6 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
     double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
     int ez = 0, base = 0;
     const int layer = a.ni * a.nj;
-    // MODE 2: the run-interior nodes this lane finishes, their M^-1 and q^n
-    const int new_ = it.ne - e0 < EB ? it.ne - e0 : EB;
-    const SplitGeo gm{a.nx, a.ny, a.nz, a.ni, a.nj, (int)a.nu, a.fx, a.fy};
-    SplitPre<N, EB, BT> pf;
-    if constexpr (MODE == 2) split_prefetch<N, EB, BT>(it, gm, B.ca != 0.0, t, e0, new_, pf);
     if (act) {
         BoxElem be;
         if constexpr (MODE == 1) {
@@ -567,41 +560,42 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
             for (int v = 0; v < 5; ++v) st[(q * NP + c + PP * k) * 5 + v] = res[k][v];
     }
     __syncthreads();
-    if constexpr (MODE == 2) {
-        split_store<N, T, EB, BT>(it, gm, StageCoef{B.ca, B.cb, it.cdt}, F64 && B.fold, st, t, e0, new_, pf);
-        return;
-    }
     // the workgroup's elements are consecutive: one contiguous run
     const int ne = it.ne - e0 < EB ? it.ne - e0 : EB;
     T *out = (T *)it.ev + (int64_t)e0 * (NP * 5);
     store_run<T>(out, st, ne * NP * 5, t, BT);
 }
 
-// The FP64 split stage with a two-pass tile (the element kernel of the split
-// DSS in FP64).  k_elem_col keeps eight tile fields (8 (N+1)^3 doubles per
-// element) and every field's zeta derivative in registers, which leaves room
-// for two workgroups per CU.  Here the tile holds five fields at a time, the
+// The element kernel of the split DSS (NUMA_STAGE_SPLIT, above), with a
+// two-pass tile.  k_elem_col keeps eight tile fields (8 (N+1)^3 doubles per
+// element in FP64) and every field's zeta derivative in registers, which leaves
+// room for two workgroups per CU.  Here the tile holds five fields at a time, the
 // size of the output staging: first p', u, v, w, theta', from which the
 // momentum and theta' rows of R follow (advection, pressure gradient,
 // buoyancy), then rho u, rho v, rho w for the mass row.  The lane takes its
 // column's values from the tile, the xi and eta rows per node.  Each term is
-// the product and sum of k_elem_col; the tail is the split DSS.  Three
-// workgroups per CU at N = 4 (50 KB of LDS), four below (N = 3: 40 KB, a
-// 16-byte stack frame, measured faster than three without it); N = 5, 6 as
-// noted below.
-template <int N> constexpr int col2_waves() { return N <= 3 ? 4 : (N == 4 ? 3 : 2); }
+// the product and sum of k_elem_col (in mixed precision the tile and the
+// contractions FP32, rho, 1/rho, rho'/rho and p' formed in FP64 as there);
+// the tail is the split DSS.  FP64: three workgroups per CU at N = 4 (50 KB
+// of LDS), four below (N = 3: 40 KB, a 16-byte stack frame, measured faster
+// than three without it); N = 5..8 as noted below.  Mixed (N <= 4): four
+// waves per SIMD.
+template <int N, typename T> constexpr int col2_waves()
+{
+    return sizeof(T) == 4 ? 4 : (N <= 3 ? 4 : (N == 4 ? 3 : 2));
+}
 // doubles after each element's tile: at N = 4, 8 spread the xi and eta rows of
 // the two or three elements a wavefront spans over the LDS banks (50,640
 // bytes, still three workgroups per CU); at N = 3 the 40 KB tile has no room
-template <int N> constexpr int col2_pad() { return N == 4 ? 8 : 0; }
+template <int N, typename T = double> constexpr int col2_pad() { return sizeof(T) == 8 && N == 4 ? 8 : 0; }
 // N = 5, 6 (seven and five elements per 256-lane workgroup, 60 and 69 KB of
 // LDS): two waves per SIMD
-template <int N>
-__global__ __launch_bounds__((split_threads<N>()), (col2_waves<N>())) void k_elem_col2(Batch B)
+template <int N, typename T = double>
+__global__ __launch_bounds__((split_threads<N>()), (col2_waves<N, T>())) void k_elem_col2(Batch B)
 {
-    using T = double;
+    constexpr bool F64 = sizeof(T) == 8;
     constexpr int P = N + 1, PP = P * P, NP = PP * P, EB = split_eb<N>(), BT = split_threads<N>();
-    constexpr int PAD = col2_pad<N>();
+    constexpr int PAD = col2_pad<N, T>();
     __shared__ T s[EB][5 * NP + PAD];
     auto S = [&](int qq, int f, int l) -> T & { return s[qq][f * NP + l]; };
     const int g0 = (int)xcd_remap(blockIdx.x, gridDim.x) * EB;
@@ -615,8 +609,10 @@ __global__ __launch_bounds__((split_threads<N>()), (col2_waves<N>())) void k_ele
     const bool fold = B.fold != 0;
     const double cdt = it.cdt, gz = -a.g0;
     const int walls = it.walls;
-    // per node of the column: rho, rho' and 1/rho (formed as in k_elem_col)
-    double rho[P], rp[P], ir[P];
+    // per node of the column, formed in FP64 as in k_elem_col: rho, 1/rho and
+    // rho' (FP64; in mixed precision rho'/rho, the buoyancy factor)
+    double rho[P];
+    T ir[P], bq[P];
     double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
     int ez = 0;
     if (act) {
@@ -640,19 +636,20 @@ __global__ __launch_bounds__((split_threads<N>()), (col2_waves<N>())) void k_ele
             const double r_ = qp[0], u = qp[a.nu], v = qp[2 * a.nu], w = qp[3 * a.nu], tp = qp[4 * a.nu];
             const double rb = rf[0], tb = it.theta0, pb = rf[2 * a.nu];
             rho[k] = rb + r_;
-            rp[k] = r_;
             const double dl = r_ * tb + rb * tp + r_ * tp;
             const int l = c + PP * k;
-            S(q, 0, l) = pb * eos_rel(dl / (rb * tb), a.gamma, a.eos);
-            S(q, 1, l) = u;
-            S(q, 2, l) = v;
-            S(q, 3, l) = w;
-            S(q, 4, l) = tp;
-            ir[k] = 1.0 / rho[k];
+            S(q, 0, l) = (T)(pb * eos_rel(dl / (rb * tb), a.gamma, a.eos));
+            S(q, 1, l) = (T)u;
+            S(q, 2, l) = (T)v;
+            S(q, 3, l) = (T)w;
+            S(q, 4, l) = (T)tp;
+            const double ird = 1.0 / rho[k];
+            ir[k] = (T)ird;
+            bq[k] = F64 ? (T)r_ : (T)(r_ * ird);
         }
     }
     __syncthreads();  // first tile complete
-    double res[P][5];
+    T res[P][5];
     T Di[P], Dj[P];
 #pragma unroll
     for (int m = 0; m < P; ++m) {
@@ -685,7 +682,7 @@ __global__ __launch_bounds__((split_threads<N>()), (col2_waves<N>())) void k_ele
             Uc[1] = vv * mx[4];
             Uc[2] = uu * mx[6] + vv * mx[7] + ww * mx[8];
             auto adv = [&](int f) -> T { return Uc[0] * dd[f][0] + Uc[1] * dd[f][1] + Uc[2] * dd[f][2]; };
-            const T bk = rp[k] * ir[k];
+            const T bk = F64 ? bq[k] * ir[k] : bq[k];
             T R[4];
             R[0] = -adv(1) - (dd[0][0] * mx[0] + dd[0][2] * mx[6]) * ir[k];
             R[1] = -adv(2) - (dd[0][1] * mx[4] + dd[0][2] * mx[7]) * ir[k];
@@ -708,9 +705,9 @@ __global__ __launch_bounds__((split_threads<N>()), (col2_waves<N>())) void k_ele
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             const int l = c + PP * k;
-            fl[k][0] = rho[k] * S(q, 1, l);
-            fl[k][1] = rho[k] * S(q, 2, l);
-            fl[k][2] = rho[k] * S(q, 3, l);
+            fl[k][0] = (T)(rho[k] * (double)S(q, 1, l));
+            fl[k][1] = (T)(rho[k] * (double)S(q, 2, l));
+            fl[k][2] = (T)(rho[k] * (double)S(q, 3, l));
         }
     }
     __syncthreads();  // first tile read
@@ -736,7 +733,7 @@ __global__ __launch_bounds__((split_threads<N>()), (col2_waves<N>())) void k_ele
             }
             const T R0 = -((da * mx[0] + dz[0] * mx[6]) + (db * mx[4] + dz[1] * mx[7]) + dz[2] * mx[8]);
             const bool wall = walls && ((ez == 0 && k == 0) || (ez == a.nz - 1 && k == N));
-            res[k][0] = (fold && !wall) ? mx[9] * fma((T)cdt, R0, rp[k]) : mx[9] * R0;
+            res[k][0] = (fold && !wall) ? mx[9] * fma((T)cdt, R0, bq[k]) : mx[9] * R0;
         }
     }
     // the run-interior nodes' M^-1 and q^n (issued here, where the tiles'
@@ -1151,7 +1148,7 @@ template <int N>
 __global__ __launch_bounds__((col_threads<N, double>())) void k_filter_col(FilterSplit A)
 {
     constexpr int P = N + 1, PP = P * P, NP = PP * P, EB = col_eb<N, double>(), BT = col_threads<N, double>();
-    constexpr int PAD = col2_pad<N>();  // the two-pass stage kernel's bank spread
+    constexpr int PAD = col2_pad<N, double>();  // the two-pass stage kernel's bank spread
     __shared__ double s[EB][5 * NP + PAD];
     auto S = [&](int qq, int f, int l) -> double & { return s[qq][f * NP + l]; };
     __shared__ double Fs[PP];
@@ -1384,11 +1381,7 @@ int32_t run_chunk_seg(const StepItem *items, int n, int phase, hipStream_t s, in
     if (split) {
         if constexpr (kind == 0) {
             if (phase == 0) {
-                if constexpr (std::is_same<T, double>::value)
-                    hipLaunchKernelGGL((k_elem_col2<N>), dim3((unsigned)(eo / eb)), dim3(split_threads<N>()), 0, s, B);
-                else
-                    hipLaunchKernelGGL((k_elem_col<N, T, 2>), dim3((unsigned)(eo / eb)), dim3(col_threads<N, T>()), 0, s,
-                                       B, 0);
+                hipLaunchKernelGGL((k_elem_col2<N, T>), dim3((unsigned)(eo / eb)), dim3(split_threads<N>()), 0, s, B);
             } else {
                 hipLaunchKernelGGL((k_fin_split<N, T>), dim3((unsigned)bo), dim3(256), 0, s, B);
             }
