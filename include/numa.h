@@ -278,8 +278,8 @@ int32_t numa_dss(numa_mesh_t m, int32_t nvar, const double *c_elem, double *out,
  * (1/2 at t = 1/2, 0 for the top mode N); cutoff >= N leaves every element
  * unchanged.  filter_order must be finite and > 0, cutoff >= 0 (NUMA_EINVAL
  * otherwise).  The state is the perturbation state (rho', u, v, w, theta'), so
- * the hydrostatic reference is not filtered.  On a box (N <= 4) whose FP64
- * stages take the split DSS (numa_mesh_set_stage) the filter takes it too
+ * the hydrostatic reference is not filtered.  On a box whose FP64 stages
+ * take the split DSS (numa_mesh_set_stage) the filter takes it too
  * (the same contributions, their copies summed in that schedule's order).  Uses the
  * mesh's contribution scratch, like numa_step: calls on one mesh on different
  * streams race. */

@@ -1145,18 +1145,28 @@ struct FilterSplit {
 };
 
 template <int N>
-__global__ __launch_bounds__((col_threads<N, double>())) void k_filter_col(FilterSplit A)
+__global__ __launch_bounds__((split_threads<N>())) void k_filter_col(FilterSplit A)
 {
-    constexpr int P = N + 1, PP = P * P, NP = PP * P, EB = col_eb<N, double>(), BT = col_threads<N, double>();
+    constexpr int P = N + 1, PP = P * P, NP = PP * P, EB = split_eb<N>(), BT = split_threads<N>();
     constexpr int PAD = col2_pad<N, double>();  // the two-pass stage kernel's bank spread
     __shared__ double s[EB][5 * NP + PAD];
     auto S = [&](int qq, int f, int l) -> double & { return s[qq][f * NP + l]; };
-    __shared__ double Fs[PP];
+    // the 1D filter matrix: in LDS up to N = 4; above, the lane's xi and eta
+    // rows in registers and the zeta row from the kernel arguments, so that
+    // the N = 7 tile (80 KB) leaves room for two workgroups per CU
+    constexpr bool FREG = N >= 5;
+    __shared__ double Fs[FREG ? 1 : PP];
+    double Fi[P], Fj[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+        Fi[m] = FREG ? A.F[((int)threadIdx.x % PP % P) * P + m] : 0.0;
+        Fj[m] = FREG ? A.F[((int)threadIdx.x % PP / P) * P + m] : 0.0;
+    }
     const BatchItem &it = A.it;
     const int e0 = (int)xcd_remap(blockIdx.x, gridDim.x) * EB;
     const int t = threadIdx.x, q = t / PP, c = t % PP, i = c % P, j = c / P;
     const bool act = q < EB && e0 + q < it.ne;
-    if (t < PP) Fs[t] = A.F[t];
+    if (!FREG && t < PP) Fs[t] = A.F[t];
     const int new_ = it.ne - e0 < EB ? it.ne - e0 : EB;
     const SplitGeo gm{(int)it.fx.d, (int)it.fy.d, it.nz, it.ni, it.nj, it.nu, it.fx, it.fy};
     SplitPre<N, EB, BT> pf;
@@ -1188,7 +1198,7 @@ __global__ __launch_bounds__((col_threads<N, double>())) void k_filter_col(Filte
             for (int v = 0; v < 5; ++v) {
                 double r = 0.0;
 #pragma unroll
-                for (int m = 0; m < P; ++m) r = fma(Fs[i * P + m], S(q, v, m + P * (j + P * k)), r);
+                for (int m = 0; m < P; ++m) r = fma(FREG ? Fi[m] : Fs[i * P + m], S(q, v, m + P * (j + P * k)), r);
                 x[v][k] = r;
             }
     }
@@ -1207,7 +1217,7 @@ __global__ __launch_bounds__((col_threads<N, double>())) void k_filter_col(Filte
             for (int v = 0; v < 5; ++v) {
                 double r = 0.0;
 #pragma unroll
-                for (int m = 0; m < P; ++m) r = fma(Fs[j * P + m], S(q, v, i + P * (m + P * k)), r);
+                for (int m = 0; m < P; ++m) r = fma(FREG ? Fj[m] : Fs[j * P + m], S(q, v, i + P * (m + P * k)), r);
                 x[v][k] = r;
             }
 #pragma unroll
@@ -1216,7 +1226,7 @@ __global__ __launch_bounds__((col_threads<N, double>())) void k_filter_col(Filte
             for (int v = 0; v < 5; ++v) {
                 double r = 0.0;
 #pragma unroll
-                for (int m = 0; m < P; ++m) r = fma(Fs[k * P + m], x[v][m], r);
+                for (int m = 0; m < P; ++m) r = fma(FREG ? A.F[k * P + m] : Fs[k * P + m], x[v][m], r);
                 res[k][v] = jw[k] * r;
             }
     }
@@ -1553,7 +1563,7 @@ namespace {
 template <int N>
 int32_t run_filter_split(const Mesh &m, const double *F, double *q, hipStream_t s)
 {
-    constexpr int EB = col_eb<N, double>();
+    constexpr int EB = split_eb<N>();
     FilterSplit A{};
     BatchItem &it = A.it;
     it.qs = q;
@@ -1580,8 +1590,7 @@ int32_t run_filter_split(const Mesh &m, const double *F, double *q, hipStream_t 
     const int64_t bo = split_item(m, EB, it);
     for (int k = 0; k <= N; ++k) A.w[k] = m.w[k];
     for (int k = 0; k < (N + 1) * (N + 1); ++k) A.F[k] = F[k];
-    hipLaunchKernelGGL((k_filter_col<N>), dim3((unsigned)((m.ne + EB - 1) / EB)), dim3(col_threads<N, double>()), 0, s,
-                       A);
+    hipLaunchKernelGGL((k_filter_col<N>), dim3((unsigned)((m.ne + EB - 1) / EB)), dim3(split_threads<N>()), 0, s, A);
     // the face nodes: the split finish with the identity update (a = b = 0, cdt = 1)
     Batch B{};
     B.n = 1;
@@ -1598,7 +1607,7 @@ int32_t run_filter_split(const Mesh &m, const double *F, double *q, hipStream_t 
 
 bool filter_split_ok(const Mesh &m)
 {
-    return m.N <= 4 && split_ok(m, NUMA_PREC_FP64);
+    return split_ok(m, NUMA_PREC_FP64);
 }
 
 int32_t launch_filter_split(const Mesh &m, const double *F, double *q, hipStream_t s)
@@ -1608,8 +1617,12 @@ int32_t launch_filter_split(const Mesh &m, const double *F, double *q, hipStream
     case 2: return run_filter_split<2>(m, F, q, s);
     case 3: return run_filter_split<3>(m, F, q, s);
     case 4: return run_filter_split<4>(m, F, q, s);
+    case 5: return run_filter_split<5>(m, F, q, s);
+    case 6: return run_filter_split<6>(m, F, q, s);
+    case 7: return run_filter_split<7>(m, F, q, s);
+    case 8: return run_filter_split<8>(m, F, q, s);
     default:
-        set_error("filter: the split DSS takes N <= 4");
+        set_error("filter: the split DSS takes N <= 8");
         return NUMA_EUNSUPPORTED;
     }
 }
