@@ -572,8 +572,9 @@ __global__ __launch_bounds__((col_threads<N, T>()), (col_blocks<N, T, MODE>())) 
 // room for two workgroups per CU.  Here the tile holds five fields at a time, the
 // size of the output staging: first p', u, v, w, theta', from which the
 // momentum and theta' rows of R follow (advection, pressure gradient,
-// buoyancy), then rho u, rho v, rho w for the mass row.  The lane takes its
-// column's values from the tile, the xi and eta rows per node.  Each term is
+// buoyancy), then rho u and rho v for the mass row (rho w enters it only
+// through zeta, from the lane's own column).  The lane takes its column's
+// values from the tile once per pass, the xi and eta rows per node.  Each term is
 // the product and sum of k_elem_col (in mixed precision the tile and the
 // contractions FP32, rho, 1/rho, rho'/rho and p' formed in FP64 as there);
 // the tail is the split DSS.  FP64: three workgroups per CU at N = 4 (50 KB
@@ -699,7 +700,9 @@ __global__ __launch_bounds__((split_threads<N>()), (col2_waves<N, T>())) void k_
             }
         }
     }
-    // the mass fluxes of the column, formed from the first tile
+    // the mass fluxes of the column, formed from the first tile: rho u and
+    // rho v go through the second tile (their xi and eta rows), the column's
+    // own values stay in registers for the zeta derivatives
     T fl[P][3];
     if (act) {
 #pragma unroll
@@ -715,7 +718,7 @@ __global__ __launch_bounds__((split_threads<N>()), (col2_waves<N, T>())) void k_
 #pragma unroll
         for (int k = 0; k < P; ++k)
 #pragma unroll
-            for (int f = 0; f < 3; ++f) S(q, f, c + PP * k) = fl[k][f];
+            for (int f = 0; f < 2; ++f) S(q, f, c + PP * k) = fl[k][f];
     }
     __syncthreads();  // second tile complete
     if (act) {
@@ -729,7 +732,7 @@ __global__ __launch_bounds__((split_threads<N>()), (col2_waves<N, T>())) void k_
                 da += Di[m] * S(q, 0, m + P * (j + P * k));
                 db += Dj[m] * S(q, 1, i + P * (m + P * k));
 #pragma unroll
-                for (int f = 0; f < 3; ++f) dz[f] += a.D[k * P + m] * S(q, f, c + PP * m);
+                for (int f = 0; f < 3; ++f) dz[f] += a.D[k * P + m] * fl[m][f];
             }
             const T R0 = -((da * mx[0] + dz[0] * mx[6]) + (db * mx[4] + dz[1] * mx[7]) + dz[2] * mx[8]);
             const bool wall = walls && ((ez == 0 && k == 0) || (ez == a.nz - 1 && k == N));
